@@ -1,0 +1,75 @@
+"""Pins of the oracle's Krylov solvers and the full two-level solve."""
+import numpy as np
+import pytest
+
+from oracle import kernel, krylov, solver, disk
+import ls_inputs as li
+
+
+def test_gmres_converges_in_number_of_distinct_eigenvalues():
+    rng = np.random.default_rng(0)
+    N = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    eig = np.array([2.0, 3.0 + 1j, -1.5j])[rng.integers(0, 3, N)]
+    A = Q @ np.diag(eig) @ np.linalg.inv(Q)
+    b = rng.standard_normal(N) + 0j
+    x, info = krylov.gmres_right(lambda v: A @ v, lambda v: v, b, 1e-12, 20)
+    assert info["iters"] == 3
+    assert np.linalg.norm(A @ x - b) < 1e-10 * np.linalg.norm(b)
+
+
+def test_fgmres_with_changing_preconditioner():
+    rng = np.random.default_rng(1)
+    N = 30
+    A = np.eye(N) * 4 + rng.standard_normal((N, N)) * 0.3
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    Dinv = 1 / np.diag(A)
+    calls = []
+
+    def prec(v):
+        calls.append(1)
+        return v * Dinv * (1.0 + 0.3 * np.sin(len(calls)))   # differs each call
+
+    x, info = krylov.fgmres(lambda v: A @ v, prec, b, 1e-12, 60)
+    assert np.linalg.norm(A @ x - b) < 1e-11 * np.linalg.norm(b)
+    # fixed iteration mode runs exactly that many
+    _, info2 = krylov.fgmres(lambda v: A @ v, prec, b, 1e-12, 60, fixed_iters=3)
+    assert info2["iters"] == 3
+
+
+@pytest.mark.slow
+def test_two_level_solve_matches_dense_solution():
+    cfg = li.config_inputs("c1_64_gauss_disk")
+    P = solver.Problem(cfg["n"], cfg["h"], cfg["omega"], cfg["m"], slabs_L=4, ext=10)
+    f = P.rhs(cfg["uI"])
+    u, info = P.solve(f, tol=1e-8)
+    us = solver.dense_solve(P.W, P.m, P.omega, f)
+    assert info["relres_true"] < 1e-8
+    assert np.linalg.norm(u - us) / np.linalg.norm(us) < 1e-6
+    assert info["iters"] <= 6 and max(info["inner_iters"]) <= 3
+
+
+def test_zero_medium_gives_zero_field():
+    n = 32
+    omega = 2 * np.pi * 3.2
+    P = solver.Problem(n, 1 / n, omega, np.zeros((n, n)), slabs_L=2, ext=5)
+    f = P.rhs(li.plane_wave(n, omega, 0.4))
+    assert np.all(f == 0)
+    u, info = P.solve(f)
+    assert np.all(u == 0) and info["iters"] == 0
+
+
+def test_disk_bessel_series():
+    """Discrete LS solution approaches the closed-form disk field as h -> 0."""
+    errs = []
+    for n in (64, 128):
+        omega = 2 * np.pi * 6
+        m = li.disk_medium(n, 0.2, 0.3)
+        W = kernel.kernel_samples(n, 1 / n, omega)
+        Gh = kernel.circulant_spectrum(W)
+        f = kernel.rhs_from_incident(W, m, li.plane_wave(n, omega, 0.0), omega, Gh)
+        u, _ = krylov.fgmres(lambda v: kernel.apply_H(W, m, v, omega, Gh), lambda r: r, f, 1e-12, 300)
+        X, Z = li.grid_coords(n)
+        ue = disk.disk_scattered_field(X, Z, omega, 0.2, 0.3)
+        errs.append(np.linalg.norm(u - ue) / np.linalg.norm(ue))
+    assert errs[0] < 0.025 and errs[1] < 0.006 and errs[0] / errs[1] > 3.0
