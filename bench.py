@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-level Lippmann-Schwinger solver on one MI355X.
+
+Workload (default): 1024 x 1024 grid on the unit square, h = 1/1024,
+omega = 2*pi*100 (10.24 points per wavelength), medium = 8 Gaussian bumps
+(seed 0), one plane wave at the seeded angle, 16 layers per direction with
+10-line extensions, FP64, bi-directional inner preconditioner, outer flexible
+GMRES to relative residual 1e-8.
+
+One step = one ls_solve of one right-hand side (the on-line stage, plan
+reused).  Prints one JSON line.  Also reports:
+  * roofline of the dominant kernel (the batched block-cyclic-reduction slab
+    solve), timed live with HIP events on the plan's stream;
+  * the FFT matvec (ls_apply) achieved HBM GB/s on a batch of 8;
+  * cpu_baseline: the FP64 CPU oracle, estimated from a bounded sample of the
+    same workload (see cpu_baseline()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def slab_solve_bytes(n, q):
+    """Algorithmic bytes of one banded slab solve (c128): the band factors of
+    a block-tridiagonal LU with bandwidth q+1 read once, n*q*(3q+4) entries,
+    plus reading and writing the right-hand side."""
+    return 16 * (n * q * (3 * q + 4) + 2 * n * q)
+
+
+def apply_bytes(n, batch):
+    """Algorithmic bytes of ls_apply: per right-hand side read v, write/read
+    the n x 2n intermediate twice each way, re-read v, write y (11 n^2 c128);
+    per batch the medium (n^2 doubles) and the stored quarter spectrum
+    ((n+1)^2 c128)."""
+    P = 2 * n
+    return batch * 11 * n * n * 16 + n * n * 8 + (P // 2 + 1) ** 2 * 16
+
+
+def cpu_baseline(cfg, counts, L, ext):
+    """Time the FP64 oracle on a bounded sample of the workload and scale it
+    to one solve with the operation counts of the GPU run.
+
+    Sample: 3 applications of H at 1024^2 (FFT, all cores), 3 sparse C
+    products, 3 A products, and one extended slab of the workload's shape
+    (1024 x 84 unknowns) factored with SuperLU and solved 3 times.  The slab
+    uses stencils computed by the oracle on a 128^2 grid with the same omega*h
+    (the SVD of the full 1024^2 set-up is off-line work and not part of a
+    solve).  Estimated oracle solve time =
+      n_H t_H + n_alg2 (4 L t_slab + 2 t_C) + n_outer t_A,
+    the oracle doing 4 L local solves per Alg. 2 application.
+    """
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    from oracle import kernel, sparsify, slabs
+    t_start = time.perf_counter()
+    n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    Gh = kernel.circulant_spectrum(W)
+    v = np.exp(1j * np.linspace(0, 7, n * n)).reshape(n, n)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        kernel.apply_H(W, m, v, omega, Gh)
+    t_H = (time.perf_counter() - t0) / reps
+    n_small = 128
+    Ws = kernel.kernel_samples(n_small, 1.0 / n, omega)   # same h, omega
+    al, be, _ = sparsify.stencils(Ws, n_small)
+    C = sparsify.assemble_C(al, be, m, omega)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C @ v.reshape(-1)
+    t_C = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sparsify.apply_A(al, v)
+    t_A = (time.perf_counter() - t0) / reps
+    part = slabs.layer_partition(n, L, ext)[1]
+    Cl = slabs.assemble_slab(al, be, m, omega, part, ext)
+    t0 = time.perf_counter()
+    lu = spla.splu(Cl.tocsc())
+    t_fac = time.perf_counter() - t0
+    b = np.ones(Cl.shape[0], dtype=complex)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lu.solve(b)
+    t_slab = (time.perf_counter() - t0) / reps
+    n_outer = counts["outer"]
+    n_alg2 = counts["inner"]
+    n_H = n_outer + 2
+    t_est = n_H * t_H + n_alg2 * (4 * L * t_slab + 2 * t_C) + n_outer * t_A
+    sample_s = time.perf_counter() - t_start
+    return {
+        "value": 1.0 / t_est,
+        "unit": "solves/s",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": (f"{reps} H applies ({t_H*1e3:.0f} ms each), {reps} C and A products, one "
+                   f"1024x{part[3]-part[2]+1} slab SuperLU factor ({t_fac:.1f} s, off-line) and "
+                   f"{reps} solves ({t_slab*1e3:.0f} ms each); scaled by n_H={n_H}, "
+                   f"n_alg2={n_alg2}, 4L={4*L} local solves per Alg. 2; sample took {sample_s:.1f} s"),
+        "est_solve_s": t_est,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--slab-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on a "
+              f"single MI355X and has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import ls_inputs as li
+    from paper_1602_07652_amd import Plan
+
+    dev = torch.device("cuda:0")
+    cfg = li.config_inputs("c2_1024_bumps")
+    n, omega, L, ext = cfg["n"], cfg["omega"], cfg["slabs"], 10
+    log(f"workload n={n} omega={omega:.3f} L={L} theta={cfg['theta']:.4f}")
+    m_d = torch.from_numpy(cfg["m"]).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, max_batch=8)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"plan created in {setup_s:.2f} s")
+    uI = torch.from_numpy(cfg["uI"]).to(dev)
+    f = plan.rhs_from_incident(uI)
+    u = torch.empty_like(f)
+    infos = []
+    for _ in range(args.warmup):
+        _, info = plan.solve(f, tol=args.tol, out=u)
+        log(f"warmup solve {info[0]}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        _, info = plan.solve(f, tol=args.tol, out=u)
+        infos.append(info[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} solves in {elapsed:.3f} s; last {infos[-1]}")
+    value = args.steps / elapsed
+
+    # dominant kernel: slab solve of an interior layer (q = 84), HIP events on the plan stream
+    lims = plan.slab_info(0, 1)
+    q = lims[3] - lims[2] + 1
+    b = torch.randn(n * q, dtype=torch.complex128, device=dev)
+    x = torch.empty_like(b)
+    stream = plan.stream
+    for _ in range(3):
+        plan.slab_solve(0, 1, b, out=x)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.slab_reps):
+        plan.slab_solve(0, 1, b, out=x)
+    ev1.record(stream)
+    ev1.synchronize()
+    slab_ms = ev0.elapsed_time(ev1) / args.slab_reps
+    slab_alg = slab_solve_bytes(n, q)
+    slab_gbs = slab_alg / (slab_ms * 1e-3) / 1e9
+    log(f"slab solve q={q}: {slab_ms*1e3:.1f} us, {slab_gbs:.0f} GB/s algorithmic")
+
+    # FFT matvec: ls_apply on a batch of 8
+    B = 8
+    vb = torch.randn((B, n, n), dtype=torch.complex128, device=dev)
+    yb = torch.empty_like(vb)
+    for _ in range(2):
+        plan.apply(vb, out=yb)
+    ev0.record(stream)
+    reps = 10
+    for _ in range(reps):
+        plan.apply(vb, out=yb)
+    ev1.record(stream)
+    ev1.synchronize()
+    apply_ms = ev0.elapsed_time(ev1) / reps
+    apply_gbs = apply_bytes(n, B) / (apply_ms * 1e-3) / 1e9
+    log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic")
+
+    outer = float(np.mean([i["outer_its"] for i in infos]))
+    inner = float(np.mean([i["inner_its_total"] for i in infos]))
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle sample ...")
+        cpu = cpu_baseline(cfg, {"outer": outer, "inner": inner}, L, ext)
+        log(f"cpu baseline {cpu}")
+    rec = {
+        "metric": "LS solves/sec at rel. residual 1e-8 (plain vs FNO+FP32+batched); FFT-matvec HBM GB/s",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain two-level solve, 1024^2 grid, omega=2*pi*100, 8 Gaussian bumps (seed 0), "
+                        "one plane wave, 16 layers x 2 directions, ext 10, FP64, BD inner preconditioner",
+            "variant": "plain (FP64, one right-hand side at a time)",
+            "outer_its": outer,
+            "inner_its_total": inner,
+            "relres_true": max(i["relres_true"] for i in infos),
+            "setup_s": setup_s,
+            "fft_matvec_GBs": apply_gbs,
+            "fft_matvec_ms_batch8": apply_ms,
+        },
+        "roofline": {
+            "kernel": "slab solve (block cyclic reduction, q=%d)" % q,
+            "bound": "hbm",
+            "achieved": slab_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": slab_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "ms_per_launch": slab_ms,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

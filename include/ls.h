@@ -1,0 +1,182 @@
+/*
+ * ls.h -- C ABI of the MI355X two-level Lippmann-Schwinger solver.
+ *
+ * Method: Zepeda-Nunez & Zhao, "Fast alternating bi-directional
+ * preconditioner for the 2D high-frequency Lippmann-Schwinger equation"
+ * (arXiv 1602.07652).  The discrete problem is H u = f with
+ * H = I + omega^2 G D and f = -omega^2 G D u_I (Section 2, eq.
+ * discrete_Lipmann-Schwinger); the preconditioner is Alg. 3 (Section 4):
+ * an inner GMRES on the sparsified system C v = A r (Section 2, eq.
+ * preconditioner) preconditioned by the bi-directional sweep, Alg. 2
+ * (Section 3.5), built from Alg. 1 (Section 3.4) on horizontal and vertical
+ * slabs.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Grid: n x n points x_{i,j} = (h (i+1), h (j+1)), 0 <= i, j < n
+ *   (Section 2, 0-based).  A grid vector is stored row by row, x fastest:
+ *   element (i, j) at index j*n + i (the global ordering of Section 3.2).
+ * - Complex vectors are interleaved (re, im) doubles: a grid vector is
+ *   2*n*n doubles; a batch of `batch` vectors is contiguous, stride 2*n*n.
+ * - Unless stated otherwise pointers are DEVICE pointers (HIP device memory
+ *   on the plan's device).  The caller owns them; the library never keeps
+ *   them after the call returns.
+ * - All device work is enqueued on the plan's stream (a hipStream_t passed
+ *   as void*, NULL for the default stream).  ls_apply, ls_stencil_*,
+ *   ls_slab_solve, ls_sweep and ls_bidirectional return without
+ *   synchronising; ls_precond_apply and ls_solve synchronise (GMRES needs
+ *   the inner products on the host).
+ * - A plan is not re-entrant: one host thread and one stream per plan.
+ * - Return value: LS_OK or an error code; on error ls_last_error() gives a
+ *   message (per thread).  No C++ exception crosses this ABI.  Outputs are
+ *   unspecified after an error other than LS_ENOCONV.
+ */
+#ifndef LS_MI355X_H
+#define LS_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ls_plan ls_plan;
+
+typedef enum {
+  LS_OK = 0,
+  LS_EINVAL = 1,      /* bad argument (size, pointer, option) */
+  LS_ENOMEM = 2,      /* device allocation failed */
+  LS_EDEVICE = 3,     /* a HIP call failed */
+  LS_ENOCONV = 4,     /* GMRES hit its iteration limit; outputs hold the last iterate */
+  LS_ESINGULAR = 5,   /* a zero or non-finite pivot in a slab factorisation */
+  LS_EUNSUPPORTED = 6 /* valid request outside what this build implements */
+} ls_status;
+
+/* Arithmetic of the on-line stage. */
+enum { LS_FP64 = 0 };
+
+/* Inner preconditioner used inside Alg. 3. */
+enum {
+  LS_PREC_BD = 0,   /* Alg. 2, bi-directional sweep (the paper's choice) */
+  LS_PREC_PT1 = 1,  /* Alg. 1 on horizontal slabs only (one direction) */
+  LS_PREC_NONE = 2  /* inner GMRES without preconditioner */
+};
+
+typedef struct {
+  int slabs;             /* L, number of layers per direction; 0 = n/64 (at least 1) */
+  int ext;               /* extension of each layer in grid rows (Section 5: 10) */
+  double inner_tol;      /* inner GMRES relative tolerance (Alg. 3: 1e-3) */
+  int max_outer;         /* outer flexible-GMRES iteration limit (no restart) */
+  int max_inner;         /* inner GMRES iteration limit */
+  double shift_c;        /* complex shift in the cut-off region, omega^2 sigma = shift_c*omega (Section 3.3) */
+  int precision;         /* LS_FP64 */
+  int precond;           /* LS_PREC_* */
+  int inner_fixed_iters; /* > 0: inner GMRES runs exactly this many iterations */
+  int max_batch;         /* largest `batch` passed to ls_apply / ls_rhs_from_incident */
+} ls_options;
+
+typedef struct {
+  int outer_its;          /* outer flexible-GMRES iterations */
+  int inner_its_total;    /* inner GMRES iterations summed over all outer iterations */
+  double relres_est;      /* least-squares residual estimate at exit */
+  double relres_true;     /* ||f - H u|| / ||f|| recomputed in FP64 at exit */
+  int converged;          /* 1 if relres_est <= tol */
+  double t_ms;            /* wall time of this right-hand side */
+} ls_solve_info;
+
+/* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,
+ * max_inner 50, shift_c 0, LS_FP64, LS_PREC_BD, inner_fixed_iters 0,
+ * max_batch 1.  Never fails. */
+void ls_options_default(ls_options* opt);
+
+/* Off-line stage (Section 4.1): builds everything that depends on the
+ * medium.  n >= 8 with 2n-1 <= 4096 (the padded FFT side P is the power of
+ * two >= 2n-1); h > 0; omega > 0; m: DEVICE pointer to n*n doubles
+ * (m(x_{i,j}) at index j*n + i), copied -- the caller keeps ownership.
+ * Each extended layer must satisfy q = thickness + extensions <= 128 and
+ * each layer must be at least ext rows thick.  opt may be NULL (defaults).
+ * stream: hipStream_t as void*.  On success *out owns all device memory of
+ * the plan.  Steps: kernel samples w and the circulant spectrum (Section 2),
+ * stencils alpha/beta (Section 2), slab matrices (Section 3.3) and their
+ * block-cyclic-reduction factors (Section 4.1). */
+ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const double* m,
+                         const ls_options* opt, void* stream);
+
+/* Frees the plan (synchronises its stream first).  NULL is accepted. */
+ls_status ls_plan_destroy(ls_plan* plan);
+
+/* Hv = v + omega^2 G (m . v) for `batch` vectors (Section 2; Section 4.2:
+ * zero-padded 2-D FFT convolution with the precomputed spectrum).
+ * 1 <= batch <= opt.max_batch.  v == Hv (in place) is allowed. */
+ls_status ls_apply(ls_plan* plan, const double* v, double* Hv, int batch);
+
+/* f = -omega^2 G (m . u_I) (Section 2). */
+ls_status ls_rhs_from_incident(ls_plan* plan, const double* uI, double* f, int batch);
+
+/* z ~= C^{-1} A r by Alg. 3: inner GMRES on C v = A r, x0 = 0, right-
+ * preconditioned by opt.precond, stopping at relative residual inner_tol
+ * (or after inner_fixed_iters iterations).  Synchronises.  Returns
+ * LS_ENOCONV if the inner limit was hit (z then holds the last iterate). */
+ls_status ls_precond_apply(ls_plan* plan, const double* r, double* z, int batch);
+
+/* u ~= H^{-1} f by flexible GMRES (x0 = 0, no restart) preconditioned by
+ * ls_precond_apply, until the relative residual estimate is <= tol.
+ * info: HOST array of `batch` records or NULL.  Synchronises.
+ * LS_ENOCONV if some right-hand side hit max_outer. */
+ls_status ls_solve(ls_plan* plan, const double* f, double* u, int batch, double tol,
+                   ls_solve_info* info);
+
+const char* ls_status_str(ls_status s);
+const char* ls_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Step-level entry points.  Each exposes one step of the path above on the
+ * plan's device data, so it can be checked on its own.
+ * ---------------------------------------------------------------------- */
+
+/* Geometry: P (padded FFT side), L (slabs per direction), the padded side
+ * and the number of complex entries of the stored spectrum. */
+ls_status ls_plan_dims(const ls_plan* plan, int* P, int* L, int* spec_side);
+
+/* Quadrature weights w_q, q in [-(n-1), n-1]^2 (Section 2: h^2 G(h|q|) off
+ * the diagonal, the modified trapezoidal weight at q = 0), written to the
+ * DEVICE array w of (2n-1)^2 complex, w[(qz+n-1)*(2n-1) + qx+n-1]. */
+ls_status ls_get_kernel_samples(ls_plan* plan, double* w);
+
+/* Stored spectrum: S[ky][kx] for 0 <= kx, ky <= P/2 (spec_side = P/2+1),
+ * S = (omega^2 / P^2) * FFT2(circulant embedding of w) (Section 2).  The
+ * full spectrum is even in kx and ky and symmetric in (kx, ky), so this
+ * quarter holds all of it.  DEVICE array of spec_side^2 complex. */
+ls_status ls_get_spectrum(ls_plan* plan, double* S);
+
+/* Stencil tables alpha and beta (Section 2), HOST arrays of 81 complex each,
+ * index ((tz*3 + tx)*3 + dz+1)*3 + dx+1 with the type per axis
+ * 0 = low edge (index 0), 1 = interior, 2 = high edge (index n-1). */
+ls_status ls_get_stencils(ls_plan* plan, double* alpha, double* beta);
+
+/* y = A r and y = C v (Section 2: C = A + omega^2 B D on A's pattern). */
+ls_status ls_stencil_A(ls_plan* plan, const double* r, double* y, int batch);
+ls_status ls_stencil_C(ls_plan* plan, const double* v, double* y, int batch);
+
+/* Layer geometry (Section 3.1): orient 0 = horizontal layers (rows of
+ * constant z), 1 = vertical layers (columns).  Writes lims[4] = {a, b, z0,
+ * z1}: layer lines [a, b], extended lines [z0, z1] along the slab's short
+ * axis.  HOST array. */
+ls_status ls_slab_info(const ls_plan* plan, int orient, int slab, int* lims);
+
+/* x = (C^l)^{-1} b for one extended slab (Section 3.3 matrix, factored off
+ * line).  b, x: DEVICE arrays of n*q complex in the slab frame
+ * [long][short]: element (i, r) at index i*q + r is the grid point at long
+ * coordinate i and short coordinate z0 + r (horizontal: x = i, z = z0 + r;
+ * vertical: z = i, x = z0 + r).  b == x allowed. */
+ls_status ls_slab_solve(ls_plan* plan, int orient, int slab, const double* b, double* x);
+
+/* v = Preconditioner(g) (Alg. 1) on horizontal (orient 0) or vertical
+ * (orient 1) layers; g, v grid vectors, g != v. */
+ls_status ls_sweep(ls_plan* plan, int orient, const double* g, double* v);
+
+/* v = BiDirectionalPreconditioner(g) (Alg. 2); g != v. */
+ls_status ls_bidirectional(ls_plan* plan, const double* g, double* v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS_MI355X_H */

@@ -1,0 +1,264 @@
+// Sparsifying stencils and the sparse operators A and C.
+//
+// Section 2: A has the pattern of the 9-point neighbourhood mu(k); its
+// stencil alpha minimises ||alpha G(mu(0), mu(0)^c)|| over unit vectors,
+// i.e. alpha is the conjugate of the left singular vector of the smallest
+// singular value of M = G(mu, mu^c).  Section 4.1: this is the SVD of a
+// 9 x N matrix.  Here M M^* (|mu| x |mu|, Hermitian) is formed by a
+// deterministic FP64 reduction over the grid, and its smallest eigenvector
+// is found with cyclic Jacobi on the equivalent real symmetric matrix
+// [[Re, -Im], [Im, Re]].  Boundary points use the same minimisation with
+// mu clipped to the grid (types: low edge / interior / high edge per
+// axis), with representative points at the grid centre, edge midpoints and
+// corners.  The phase is fixed so that the centre coefficient is real and
+// positive.  C = A H on A's pattern: C(k, k+d) = alpha_d + omega^2 beta_d
+// m_{k+d}, beta_d = sum_{d'} alpha_{d'} w_{d'-d} (Section 2).
+//
+// Stencil tables: index ((tz*3 + tx)*3 + dz+1)*3 + dx+1.
+#include "ls_internal.h"
+
+#include <cmath>
+
+namespace {
+
+__device__ __forceinline__ void type_range(int t, int& lo, int& hi) {
+  lo = (t == 0) ? 0 : -1;
+  hi = (t == 2) ? 0 : 1;
+}
+
+__device__ __forceinline__ int type_rep(int t, int n) { return t == 0 ? 0 : (t == 1 ? n / 2 : n - 1); }
+
+__device__ __forceinline__ cplx wq(const cplx* __restrict__ circ, int P, int qx, int qz) {
+  const int x = qx < 0 ? qx + P : qx;
+  const int z = qz < 0 ? qz + P : qz;
+  return circ[(size_t)z * P + x];
+}
+
+// One workgroup per (type, d, d'), d <= d' in the type's offset list:
+// gram[type][d][d'] = sum_{p not in mu(k0)} w_{k0+d-p} conj(w_{k0+d'-p}).
+__global__ __launch_bounds__(256) void k_gram(const cplx* __restrict__ circ, int n, int P,
+                                              cplx* __restrict__ gram) {
+  const int type = blockIdx.y;
+  const int tz = type / 3, tx = type % 3;
+  int zlo, zhi, xlo, xhi;
+  type_range(tz, zlo, zhi);
+  type_range(tx, xlo, xhi);
+  const int nx = xhi - xlo + 1, nz = zhi - zlo + 1, mt = nx * nz;
+  const int pair = blockIdx.x;  // d1 * 9 + d2
+  const int d1 = pair / 9, d2 = pair % 9;
+  if (d1 >= mt || d2 >= mt || d2 < d1) return;
+  const int dz1 = zlo + d1 / nx, dx1 = xlo + d1 % nx;
+  const int dz2 = zlo + d2 / nx, dx2 = xlo + d2 % nx;
+  const int j0 = type_rep(tz, n), i0 = type_rep(tx, n);
+  cplx acc = cmk(0.0, 0.0);
+  const int N = n * n;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const int pj = k / n, pi = k % n;
+    const int ddz = pj - j0, ddx = pi - i0;
+    if (ddz >= zlo && ddz <= zhi && ddx >= xlo && ddx <= xhi) continue;  // p in mu(k0)
+    const cplx a = wq(circ, P, i0 + dx1 - pi, j0 + dz1 - pj);
+    const cplx b = wq(circ, P, i0 + dx2 - pi, j0 + dz2 - pj);
+    acc = cfmaconj(b, a, acc);  // a * conj(b)
+  }
+  __shared__ double sre[256], sim[256];
+  sre[threadIdx.x] = acc.x;
+  sim[threadIdx.x] = acc.y;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sre[threadIdx.x] += sre[threadIdx.x + s];
+      sim[threadIdx.x] += sim[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    gram[type * 81 + d1 * 9 + d2] = cmk(sre[0], sim[0]);
+    gram[type * 81 + d2 * 9 + d1] = cmk(sre[0], -sim[0]);
+  }
+}
+
+// One thread per type: smallest eigenvector of the Gram matrix, phase fix,
+// then beta.  Writes alpha/beta tables (81 each) and their transposes.
+__global__ void k_stencil_solve(const cplx* __restrict__ gram, const cplx* __restrict__ circ,
+                                int P, cplx* __restrict__ tables, int* __restrict__ status) {
+  const int type = threadIdx.x;
+  if (type >= 9) return;
+  const int tz = type / 3, tx = type % 3;
+  int zlo, zhi, xlo, xhi;
+  type_range(tz, zlo, zhi);
+  type_range(tx, xlo, xhi);
+  const int nx = xhi - xlo + 1, nz = zhi - zlo + 1, mt = nx * nz, M = 2 * mt;
+  double A[18][18], V[18][18];
+  for (int r = 0; r < M; ++r)
+    for (int c = 0; c < M; ++c) V[r][c] = (r == c) ? 1.0 : 0.0;
+  for (int r = 0; r < mt; ++r)
+    for (int c = 0; c < mt; ++c) {
+      const cplx g = gram[type * 81 + r * 9 + c];
+      A[r][c] = g.x;
+      A[r + mt][c + mt] = g.x;
+      A[r][c + mt] = -g.y;
+      A[r + mt][c] = g.y;
+    }
+  double scale = 0.0;
+  for (int r = 0; r < M; ++r) scale = fmax(scale, fabs(A[r][r]));
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < M; ++p)
+      for (int q = p + 1; q < M; ++q) off += A[p][q] * A[p][q];
+    if (off <= 1e-36 * scale * scale) break;
+    for (int p = 0; p < M; ++p)
+      for (int q = p + 1; q < M; ++q) {
+        const double apq = A[p][q];
+        if (fabs(apq) <= 1e-300) continue;
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < M; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < M; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < M; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  int imin = 0;
+  for (int r = 1; r < M; ++r)
+    if (A[r][r] < A[imin][imin]) imin = r;
+  // complex eigenvector u = x + i y; alpha = conj(u), phase-fixed.
+  cplx al[9];
+  double nrm = 0.0;
+  for (int r = 0; r < mt; ++r) {
+    al[r] = cmk(V[r][imin], -V[r + mt][imin]);
+    nrm += al[r].x * al[r].x + al[r].y * al[r].y;
+  }
+  nrm = sqrt(nrm);
+  const int centre = (0 - zlo) * nx + (0 - xlo);
+  const cplx cc = al[centre];
+  const double ac = sqrt(cc.x * cc.x + cc.y * cc.y);
+  if (!(ac > 0.0) || !(nrm > 0.0)) {
+    atomicOr(status, 1);
+    return;
+  }
+  const cplx ph = cmk(cc.x / ac / nrm, -cc.y / ac / nrm);  // conj(cc)/|cc| / nrm
+  for (int r = 0; r < mt; ++r) al[r] = cmul(al[r], ph);
+  al[centre].y = 0.0;
+  cplx* alpha = tables;
+  cplx* beta = tables + 81;
+  cplx* alphaT = tables + 162;
+  cplx* betaT = tables + 243;
+  const int typeT = tx * 3 + tz;
+  for (int e = 0; e < 9; ++e) {
+    alpha[type * 9 + e] = cmk(0.0, 0.0);
+    beta[type * 9 + e] = cmk(0.0, 0.0);
+    alphaT[typeT * 9 + e] = cmk(0.0, 0.0);
+    betaT[typeT * 9 + e] = cmk(0.0, 0.0);
+  }
+  for (int d = 0; d < mt; ++d) {
+    const int dz = zlo + d / nx, dx = xlo + d % nx;
+    cplx b = cmk(0.0, 0.0);
+    for (int e = 0; e < mt; ++e) {
+      const int ez = zlo + e / nx, ex = xlo + e % nx;
+      b = cfma(al[e], wq(circ, P, ex - dx, ez - dz), b);
+    }
+    const int slot = (dz + 1) * 3 + (dx + 1);
+    const int slotT = (dx + 1) * 3 + (dz + 1);
+    alpha[type * 9 + slot] = al[d];
+    beta[type * 9 + slot] = b;
+    alphaT[typeT * 9 + slotT] = al[d];
+    betaT[typeT * 9 + slotT] = b;
+  }
+}
+
+__device__ __forceinline__ int axis_type(int i, int n) { return i == 0 ? 0 : (i == n - 1 ? 2 : 1); }
+
+// y = A r (mode 0), y = C v (mode 1), y = g - C v (mode 2).
+template <int MODE>
+__global__ void k_stencil(const cplx* __restrict__ in, const cplx* __restrict__ g,
+                          cplx* __restrict__ out, const cplx* __restrict__ tables,
+                          const double* __restrict__ m, int n, double omega2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const size_t base = (size_t)blockIdx.z * n * n;
+  if (i >= n) return;
+  const int t = axis_type(j, n) * 3 + axis_type(i, n);
+  const cplx* al = tables + t * 9;
+  const cplx* be = tables + 81 + t * 9;
+  cplx acc = cmk(0.0, 0.0);
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int jj = j + dz;
+    if (jj < 0 || jj >= n) continue;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int ii = i + dx;
+      if (ii < 0 || ii >= n) continue;
+      const int s = (dz + 1) * 3 + dx + 1;
+      const size_t idx = (size_t)jj * n + ii;
+      cplx c = al[s];
+      if (MODE != 0) c = cadd(c, cscale(be[s], omega2 * m[idx]));
+      acc = cfma(c, in[base + idx], acc);
+    }
+  }
+  const size_t o = base + (size_t)j * n + i;
+  out[o] = (MODE == 2) ? csub(g[o], acc) : acc;
+}
+
+}  // namespace
+
+ls_status stencils_build(ls_plan* p, const cplx* circ) {
+  cplx* gram = nullptr;
+  int* status = nullptr;
+  LS_HIP(hipMalloc(&gram, sizeof(cplx) * 9 * 81));
+  LS_HIP(hipMalloc(&status, sizeof(int)));
+  LS_HIP(hipMemsetAsync(gram, 0, sizeof(cplx) * 9 * 81, p->stream));
+  LS_HIP(hipMemsetAsync(status, 0, sizeof(int), p->stream));
+  k_gram<<<dim3(81, 9), 256, 0, p->stream>>>(circ, p->n, p->P, gram);
+  LS_HIP(hipGetLastError());
+  k_stencil_solve<<<1, 64, 0, p->stream>>>(gram, circ, p->P, p->stencil_d, status);
+  LS_HIP(hipGetLastError());
+  int st = 0;
+  LS_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  LS_HIP(hipMemcpyAsync(p->alpha_h, p->stencil_d, sizeof(cplx) * 81, hipMemcpyDeviceToHost, p->stream));
+  LS_HIP(hipMemcpyAsync(p->beta_h, p->stencil_d + 81, sizeof(cplx) * 81, hipMemcpyDeviceToHost, p->stream));
+  LS_HIP(hipStreamSynchronize(p->stream));
+  LS_HIP(hipFree(gram));
+  LS_HIP(hipFree(status));
+  if (st != 0) {
+    ls_set_error("stencil construction: degenerate singular vector");
+    return LS_ESINGULAR;
+  }
+  return LS_OK;
+}
+
+static ls_status launch_stencil(ls_plan* p, int mode, const cplx* in, const cplx* g, cplx* out, int batch) {
+  const int n = p->n;
+  dim3 grid((n + 127) / 128, n, batch);
+  const double w2 = p->omega * p->omega;
+  if (mode == 0)
+    k_stencil<0><<<grid, 128, 0, p->stream>>>(in, g, out, p->stencil_d, p->m, n, w2);
+  else if (mode == 1)
+    k_stencil<1><<<grid, 128, 0, p->stream>>>(in, g, out, p->stencil_d, p->m, n, w2);
+  else
+    k_stencil<2><<<grid, 128, 0, p->stream>>>(in, g, out, p->stencil_d, p->m, n, w2);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+ls_status stencil_apply_A(ls_plan* p, const cplx* r, cplx* y, int batch) {
+  return launch_stencil(p, 0, r, nullptr, y, batch);
+}
+ls_status stencil_apply_C(ls_plan* p, const cplx* v, cplx* y, int batch) {
+  return launch_stencil(p, 1, v, nullptr, y, batch);
+}
+ls_status stencil_residual_C(ls_plan* p, const cplx* g, const cplx* u, cplx* e) {
+  return launch_stencil(p, 2, u, g, e, 1);
+}

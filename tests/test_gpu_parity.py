@@ -1,0 +1,180 @@
+"""GPU parity: every step of the HIP path against the FP64 CPU oracle.
+
+Inputs are seeded (ls_inputs); all calls go through the C ABI (via the thin
+binding).  Tolerances are stated per test; they follow from FP64 rounding
+(FFT ~ eps log P, GEMV/BCR ~ eps * cond) and, for everything downstream of
+the stencils, from the stencil construction: the GPU forms the Gram matrix
+M M^* (eigenvector error ~ eps ||M||^2 / gap ~ 1e-11) while the oracle takes
+the SVD of M.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernel, sparsify, slabs, solver
+import ls_inputs as li
+from gpu_helpers import dev, host, rel, banner
+
+pytestmark = pytest.mark.gpu
+
+
+def make_plan(n, f, m, **kw):
+    from paper_1602_07652_amd import Plan
+    omega = 2 * np.pi * f
+    banner(f"plan n={n} f={f} opts={kw}")
+    return Plan(n, 1.0 / n, omega, dev(m, torch.float64), **kw), omega
+
+
+@pytest.mark.parametrize("n", [8, 37, 64, 1024])
+def test_kernel_samples_and_spectrum(n):
+    f = n / 10.0
+    p, omega = make_plan(n, f, np.zeros((n, n)), precond=2)
+    w_gpu = host(p.kernel_samples())
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    err = np.max(np.abs(w_gpu - W)) / np.max(np.abs(W))
+    banner(f"kernel samples n={n} max rel err {err:.3e}")
+    assert err < 1e-13
+    # pointwise relative error on the off-diagonal samples
+    assert np.max(np.abs(w_gpu - W) / np.abs(W)) < 1e-12
+    S_gpu = host(p.spectrum())
+    P = p.P
+    Gh = kernel.circulant_spectrum(W, P) * omega**2 / P**2
+    S = Gh[:P // 2 + 1, :P // 2 + 1]
+    err = np.max(np.abs(S_gpu - S)) / np.max(np.abs(S))
+    banner(f"spectrum n={n} P={P} max rel err {err:.3e}")
+    assert err < 1e-12
+    p.close()
+
+
+@pytest.mark.parametrize("n,batch", [(8, 1), (37, 3), (64, 2), (100, 1), (129, 2), (256, 1), (1024, 2)])
+def test_apply_matches_oracle(n, batch):
+    m, _ = li.gaussian_bumps_medium(n, seed=n)
+    p, omega = make_plan(n, n / 10.0, m, precond=2, max_batch=batch)
+    v = li.random_complex((batch, n, n), seed=100 + n)
+    y = host(p.apply(dev(v)))
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    y_ref = kernel.apply_H(W, m, v, omega)
+    e = rel(y, y_ref)
+    banner(f"apply n={n} batch={batch} rel err {e:.3e}")
+    assert e < 1e-13
+    # in place, and the right-hand side
+    vt = dev(v)
+    p.apply(vt, out=vt)
+    assert rel(host(vt), y_ref) < 1e-13
+    uI = np.stack([li.plane_wave(n, omega, 0.3 * k) for k in range(batch)])
+    f = host(p.rhs_from_incident(dev(uI)))
+    e = rel(f, kernel.rhs_from_incident(W, m, uI, omega))
+    banner(f"rhs n={n} rel err {e:.3e}")
+    assert e < 1e-13
+    p.close()
+
+
+def test_apply_zero_medium_is_identity():
+    n = 48
+    p, _ = make_plan(n, 4.8, np.zeros((n, n)), precond=2)
+    v = li.random_complex((n, n), 5)
+    assert rel(host(p.apply(dev(v))), v) == 0.0
+    p.close()
+
+
+@pytest.mark.parametrize("n", [37, 64])
+def test_stencils_and_sparse_operators(n):
+    m = li.gaussian_disk_medium(n)
+    p, omega = make_plan(n, n / 10.0, m, precond=2)
+    al_g, be_g = p.stencils()
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    al, be, _ = sparsify.stencils(W, n)
+    ea = np.max(np.abs(al_g - al))
+    eb = np.max(np.abs(be_g - be)) / np.max(np.abs(be))
+    banner(f"stencils n={n} alpha err {ea:.3e} beta rel err {eb:.3e}")
+    assert ea < 1e-9 and eb < 1e-9
+    r = li.random_complex((2, n, n), 7)
+    Ar = host(p.stencil_A(dev(r)))
+    assert rel(Ar, sparsify.apply_A(al, r)) < 1e-9
+    C = sparsify.assemble_C(al, be, m, omega)
+    Cv = host(p.stencil_C(dev(r)))
+    Cv_ref = np.stack([(C @ r[k].reshape(-1)).reshape(n, n) for k in range(2)])
+    e = rel(Cv, Cv_ref)
+    banner(f"C v n={n} rel err {e:.3e}")
+    assert e < 1e-9
+    p.close()
+
+
+SLAB_CASES = [(64, 6.0, 4, 10, 0.0, None), (100, 10.0, 3, 8, 1.0, 3), (130, 13.0, 4, 10, 0.0, 1)]
+
+
+def oracle_problem(n, f, L, ext, shift, seed):
+    omega = 2 * np.pi * f
+    m = li.gaussian_disk_medium(n) if seed is None else li.gaussian_bumps_medium(n, seed)[0]
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    al, be, _ = sparsify.stencils(W, n)
+    return m, omega, al, be
+
+
+@pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES)
+def test_slab_solves(n, f, L, ext, shift, seed):
+    m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
+    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift)
+    parts = slabs.layer_partition(n, L, ext)
+    for orient in (0, 1):
+        a_, b_ = (al, be) if orient == 0 else (al.transpose(1, 0, 3, 2), be.transpose(1, 0, 3, 2))
+        mm = m if orient == 0 else m.T.copy()
+        for l in range(L):
+            assert p.slab_info(orient, l) == parts[l]
+            Cl = slabs.assemble_slab(a_, b_, mm, omega, parts[l], ext, shift)
+            q = parts[l][3] - parts[l][2] + 1
+            b = li.random_complex((n, q), seed=10 * l + orient)      # frame [long][short]
+            x = host(p.slab_solve(orient, l, dev(b)))
+            import scipy.sparse.linalg as spla
+            x_ref = spla.spsolve(Cl.tocsc(), b.T.reshape(-1)).reshape(q, n).T
+            e = rel(x, x_ref)
+            banner(f"slab n={n} orient={orient} l={l} q={q} rel err {e:.3e}")
+            assert e < 1e-9
+    p.close()
+
+
+@pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES)
+def test_sweeps_and_bidirectional(n, f, L, ext, shift, seed):
+    m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
+    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift)
+    bd = slabs.BiDirectional(al, be, m, omega, L, ext, shift)
+    g = li.random_complex((n, n), 3)
+    vh = host(p.sweep(0, dev(g)))
+    e0 = rel(vh, bd.prec_h(g))
+    vv = host(p.sweep(1, dev(g)))
+    e1 = rel(vv, bd.prec_v(g))
+    vb = host(p.bidirectional(dev(g)))
+    e2 = rel(vb, bd.apply(g))
+    banner(f"sweeps n={n} L={L} H {e0:.3e} V {e1:.3e} BD {e2:.3e}")
+    assert e0 < 1e-8 and e1 < 1e-8 and e2 < 1e-8
+    p.close()
+
+
+def test_precond_fixed_iterations():
+    n, f, L = 64, 6.0, 4
+    m = li.gaussian_disk_medium(n)
+    p, omega = make_plan(n, f, m, slabs=L, ext=10, inner_fixed_iters=2)
+    P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=L, ext=10, inner_fixed_iters=2)
+    r = li.random_complex((n, n), 11)
+    z = host(p.precond_apply(dev(r)))
+    e = rel(z, P.precond_apply(r))
+    banner(f"precond fixed=2 rel err {e:.3e}")
+    assert e < 1e-8
+    p.close()
+
+
+def test_solve_c1_matches_dense_solution():
+    cfg = li.config_inputs("c1_64_gauss_disk")
+    n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
+    p, _ = make_plan(n, 6.0, m, slabs=4, ext=10)
+    f = p.rhs_from_incident(dev(cfg["uI"]))
+    u, info = p.solve(f, tol=1e-8)
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    f_ref = kernel.rhs_from_incident(W, m, cfg["uI"], omega)
+    u_star = solver.dense_solve(W, m, omega, f_ref)
+    e = rel(host(u), u_star)
+    banner(f"solve c1 info={info[0]} rel err vs dense {e:.3e}")
+    assert info[0]["converged"] == 1 and info[0]["relres_true"] < 1e-8
+    assert e < 1e-6
+    assert info[0]["outer_its"] <= 6
+    p.close()
