@@ -50,8 +50,15 @@ typedef enum {
   LS_EUNSUPPORTED = 6 /* valid request outside what this build implements */
 } ls_status;
 
-/* Arithmetic of the on-line stage. */
-enum { LS_FP64 = 0 };
+/* Arithmetic of the on-line stage.
+ * LS_FP64: everything in FP64.
+ * LS_FP32_REFINE: FP32 FFT convolution, stencils, slab solves and sweeps
+ *   (slab factors computed in FP64, stored in FP32), FP64 inner products and
+ *   Hessenberg least squares, and an FP64 iterative-refinement loop around
+ *   an FP32 flexible GMRES (residuals f - H u in FP64).  The flexible outer
+ *   loop the paper suggests (Section 6) is what lets the preconditioned
+ *   solve run in reduced precision. */
+enum { LS_FP64 = 0, LS_FP32_REFINE = 1 };
 
 /* Inner preconditioner used inside Alg. 3. */
 enum {
@@ -71,6 +78,8 @@ typedef struct {
   int precond;           /* LS_PREC_* */
   int inner_fixed_iters; /* > 0: inner GMRES runs exactly this many iterations */
   int max_batch;         /* largest `batch` passed to ls_apply / ls_rhs_from_incident */
+  double lowp_tol;       /* LS_FP32_REFINE: relative tolerance of each FP32 correction solve */
+  int max_refine;        /* LS_FP32_REFINE: refinement sweeps limit */
 } ls_options;
 
 typedef struct {
@@ -84,7 +93,7 @@ typedef struct {
 
 /* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,
  * max_inner 50, shift_c 0, LS_FP64, LS_PREC_BD, inner_fixed_iters 0,
- * max_batch 1.  Never fails. */
+ * max_batch 1, lowp_tol 1e-5, max_refine 10.  Never fails. */
 void ls_options_default(ls_options* opt);
 
 /* Off-line stage (Section 4.1): builds everything that depends on the
@@ -119,8 +128,11 @@ ls_status ls_precond_apply(ls_plan* plan, const double* r, double* z, int batch)
 
 /* u ~= H^{-1} f by flexible GMRES (x0 = 0, no restart) preconditioned by
  * ls_precond_apply, until the relative residual estimate is <= tol.
+ * LS_FP32_REFINE plans: FP64 refinement sweeps r = f - H u, each solving
+ * H d = r with the FP32 flexible GMRES to max(lowp_tol, tol/||r||) and
+ * adding d, until ||f - H u|| / ||f|| <= tol; f and u stay FP64.
  * info: HOST array of `batch` records or NULL.  Synchronises.
- * LS_ENOCONV if some right-hand side hit max_outer. */
+ * LS_ENOCONV if some right-hand side hit max_outer (or max_refine). */
 ls_status ls_solve(ls_plan* plan, const double* f, double* u, int batch, double tol,
                    ls_solve_info* info);
 
@@ -162,11 +174,18 @@ ls_status ls_stencil_C(ls_plan* plan, const double* v, double* y, int batch);
  * axis.  HOST array. */
 ls_status ls_slab_info(const ls_plan* plan, int orient, int slab, int* lims);
 
+/* FP32 operator of an LS_FP32_REFINE plan: Hv = v + omega^2 G (m . v) with
+ * interleaved complex FP32 vectors [batch][n][n] (Section 2; the
+ * refinement loop's low-precision operator).  LS_EINVAL on FP64 plans. */
+ls_status ls_apply_c64(ls_plan* plan, const float* v, float* Hv, int batch);
+
 /* x = (C^l)^{-1} b for one extended slab (Section 3.3 matrix, factored off
  * line).  b, x: DEVICE arrays of n*q complex in the slab frame
  * [long][short]: element (i, r) at index i*q + r is the grid point at long
  * coordinate i and short coordinate z0 + r (horizontal: x = i, z = z0 + r;
- * vertical: z = i, x = z0 + r).  b == x allowed. */
+ * vertical: z = i, x = z0 + r).  b == x allowed.  LS_FP32_REFINE plans
+ * solve with the FP32 factors (b, x stay FP64 arrays); the same holds for
+ * ls_sweep, ls_bidirectional and ls_precond_apply. */
 ls_status ls_slab_solve(ls_plan* plan, int orient, int slab, const double* b, double* x);
 
 /* v = Preconditioner(g) (Alg. 1) on horizontal (orient 0) or vertical

@@ -20,10 +20,11 @@ from .build import lib_path
 
 __all__ = [
     "Options", "SolveInfo", "LSError", "Plan", "lib",
-    "LS_PREC_BD", "LS_PREC_PT1", "LS_PREC_NONE",
+    "LS_PREC_BD", "LS_PREC_PT1", "LS_PREC_NONE", "LS_FP64", "LS_FP32_REFINE",
 ]
 
 LS_PREC_BD, LS_PREC_PT1, LS_PREC_NONE = 0, 1, 2
+LS_FP64, LS_FP32_REFINE = 0, 1
 _STATUS = {0: "LS_OK", 1: "LS_EINVAL", 2: "LS_ENOMEM", 3: "LS_EDEVICE", 4: "LS_ENOCONV",
            5: "LS_ESINGULAR", 6: "LS_EUNSUPPORTED"}
 
@@ -40,6 +41,7 @@ class Options(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("shift_c", ctypes.c_double),
         ("precision", ctypes.c_int), ("precond", ctypes.c_int),
         ("inner_fixed_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
+        ("lowp_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
     ]
 
 
@@ -74,6 +76,7 @@ def lib():
         "ls_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _vp, ctypes.POINTER(Options), _vp]),
         "ls_plan_destroy": (_i, [_vp]),
         "ls_apply": (_i, [_vp, _vp, _vp, _i]),
+        "ls_apply_c64": (_i, [_vp, _vp, _vp, _i]),
         "ls_rhs_from_incident": (_i, [_vp, _vp, _vp, _i]),
         "ls_precond_apply": (_i, [_vp, _vp, _vp, _i]),
         "ls_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(SolveInfo)]),
@@ -170,6 +173,15 @@ class Plan:
         out = torch.empty_like(v) if out is None else out
         N = self.n * self.n * b
         _check("ls_apply", lib().ls_apply(self.handle, _ptr(v, N, "v"), _ptr(out, N, "Hv"), b))
+        return out
+
+    def apply_c64(self, v, out=None):
+        """FP32 operator (LS_FP32_REFINE plans); v complex64."""
+        b = self._batch(v)
+        out = torch.empty_like(v) if out is None else out
+        N = self.n * self.n * b
+        _check("ls_apply_c64", lib().ls_apply_c64(
+            self.handle, _ptr(v, N, "v", torch.complex64), _ptr(out, N, "Hv", torch.complex64), b))
         return out
 
     def rhs_from_incident(self, uI, out=None):

@@ -15,6 +15,7 @@
 #include <complex>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 namespace {
 thread_local std::string g_last_error;
@@ -35,15 +36,26 @@ struct DeviceGuard {
   }
 };
 
-ls_status ensure_krylov(ls_plan* p, KrylovSpace& K, int nvec) {
+// Grows a Krylov set to hold nvec vectors of `stride` elements each,
+// keeping its contents (capacity doubles; the old block is released).
+template <typename T>
+ls_status ensure_krylov(ls_plan* p, KrylovSpaceT<T>& K, int nvec, size_t stride) {
   if (K.cap >= nvec) return LS_OK;
-  const size_t N = (size_t)p->n * p->n;
-  cplx* nb = nullptr;
-  // a larger basis replaces the old one (which stays owned by the plan and
-  // is freed with it); bases hold no state across calls
-  LS_TRY(plan_alloc(p, (void**)&nb, sizeof(cplx) * N * nvec));
+  const int ncap = std::max(nvec, std::max(4, 2 * K.cap));
+  T* nb = nullptr;
+  LS_TRY(plan_alloc(p, (void**)&nb, sizeof(T) * stride * ncap));
+  if (K.base) {
+    LS_HIP(hipMemcpyAsync(nb, K.base, sizeof(T) * stride * K.cap, hipMemcpyDeviceToDevice, p->stream));
+    LS_HIP(hipStreamSynchronize(p->stream));
+    for (auto it = p->allocs.begin(); it != p->allocs.end(); ++it)
+      if (*it == K.base) {
+        p->allocs.erase(it);
+        break;
+      }
+    LS_HIP(hipFree(K.base));
+  }
   K.base = nb;
-  K.cap = nvec;
+  K.cap = ncap;
   return LS_OK;
 }
 
@@ -53,120 +65,187 @@ struct GmresResult {
   bool converged = false;
 };
 
-// Flexible GMRES: op and prec are callables (in, out) -> ls_status.
-template <class Op, class Prec>
-ls_status fgmres(ls_plan* p, Op op, Prec prec, const cplx* b, cplx* x, double tol, int maxit,
-                 int fixed, KrylovSpace& KV, KrylovSpace& KZ, GmresResult& res) {
+// Flexible GMRES on B right-hand sides in lockstep (each with its own Krylov
+// space, Hessenberg matrix and stopping test; vectors [B][N] of type T, the
+// Krylov index slowest).  op and prec are callables (in, out, B) -> status.
+// Inner products and the Hessenberg least squares are FP64.  A right-hand
+// side that has converged keeps a zero next basis vector, so it costs work
+// but never divides by zero.
+template <typename T, class Op, class Prec>
+ls_status fgmres(ls_plan* p, Op op, Prec prec, const T* b, T* x, int B, double tol, int maxit,
+                 int fixed, KrylovSpaceT<T>& KV, KrylovSpaceT<T>& KZ, std::vector<GmresResult>& res) {
   const size_t N = (size_t)p->n * p->n;
+  // Krylov index stride: always max_batch vectors, so a set allocated for one
+  // call fits every later call whatever its B
+  const size_t stride = (size_t)p->opt.max_batch * N;
   const int limit = fixed > 0 ? fixed : maxit;
-  double beta = 0.0;
-  LS_TRY(vec_norm(p, b, N, &beta));
-  res = GmresResult{};
-  if (beta == 0.0) {
-    LS_TRY(vec_zero(p, x, N));
-    res.converged = true;
-    return LS_OK;
+  res.assign(B, GmresResult{});
+  std::vector<double> beta(B), hn(B), sc(B);
+  LS_TRY(vec_norms(p, b, N, B, beta.data()));
+  std::vector<char> active(B);
+  int nactive = 0;
+  for (int i = 0; i < B; ++i) {
+    active[i] = beta[i] > 0.0;
+    nactive += active[i];
+    if (!active[i]) res[i].converged = true;
+    sc[i] = active[i] ? 1.0 / beta[i] : 0.0;
   }
-  LS_TRY(ensure_krylov(p, KV, limit + 1));
-  LS_TRY(ensure_krylov(p, KZ, limit));
-  auto V = [&](int i) { return KV.base + (size_t)i * N; };
-  auto Z = [&](int i) { return KZ.base + (size_t)i * N; };
-  LS_TRY(vec_scale_copy(p, V(0), b, 1.0 / beta, N));
-  std::vector<std::vector<zc>> H;  // columns
-  std::vector<double> cs;
-  std::vector<zc> sn;
-  std::vector<zc> gv{zc(beta, 0.0)};
-  std::vector<cplx> h1(limit + 1), h2(limit + 1);
-  int jdone = 0;
-  double rel = 1.0;
+  if (nactive == 0) return vec_zero(p, x, (size_t)B * N);
+  LS_TRY(ensure_krylov(p, KV, 2, stride));
+  LS_TRY(ensure_krylov(p, KZ, 1, stride));
+  LS_TRY(vec_scale_b(p, KV.base, b, sc.data(), N, B));
+  std::vector<std::vector<std::vector<zc>>> H(B);  // [b][column]
+  std::vector<std::vector<double>> cs(B);
+  std::vector<std::vector<zc>> sn(B), gv(B);
+  for (int i = 0; i < B; ++i) gv[i].assign(1, zc(beta[i], 0.0));
+  std::vector<cplx> h1, h2;
+  int jlast = 0;
   for (int j = 0; j < limit; ++j) {
-    LS_TRY(prec(V(j), Z(j)));
-    cplx* w = V(j + 1);
-    LS_TRY(op(Z(j), w));
-    LS_TRY(vec_multidot(p, KV.base, j + 1, N, w, N, h1.data()));
-    LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, N, h1.data(), N));
-    LS_TRY(vec_multidot(p, KV.base, j + 1, N, w, N, h2.data()));
-    LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, N, h2.data(), N));
-    double hn = 0.0;
-    LS_TRY(vec_norm(p, w, N, &hn));
-    std::vector<zc> col(j + 2);
-    for (int i = 0; i <= j; ++i) col[i] = toz(h1[i]) + toz(h2[i]);
-    col[j + 1] = zc(hn, 0.0);
-    for (int i = 0; i < j; ++i) {
-      const zc a = col[i], bb = col[i + 1];
-      col[i] = cs[i] * a + sn[i] * bb;
-      col[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
+    LS_TRY(ensure_krylov(p, KV, j + 2, stride));
+    LS_TRY(ensure_krylov(p, KZ, j + 1, stride));
+    T* Vj = KV.base + (size_t)j * stride;
+    T* Zj = KZ.base + (size_t)j * stride;
+    T* w = KV.base + (size_t)(j + 1) * stride;
+    LS_TRY(prec(Vj, Zj, B));
+    LS_TRY(op(Zj, w, B));
+    h1.resize((size_t)B * (j + 1));
+    h2.resize((size_t)B * (j + 1));
+    LS_TRY(vec_multidot(p, KV.base, j + 1, stride, w, N, B, h1.data()));
+    LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, stride, h1.data(), N, B));
+    LS_TRY(vec_multidot(p, KV.base, j + 1, stride, w, N, B, h2.data()));
+    LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, stride, h2.data(), N, B));
+    LS_TRY(vec_norms(p, w, N, B, hn.data()));
+    jlast = j + 1;
+    for (int i = 0; i < B; ++i) {
+      if (!active[i]) continue;
+      std::vector<zc> col(j + 2);
+      for (int k = 0; k <= j; ++k)
+        col[k] = toz(h1[(size_t)i * (j + 1) + k]) + toz(h2[(size_t)i * (j + 1) + k]);
+      col[j + 1] = zc(hn[i], 0.0);
+      for (int k = 0; k < j; ++k) {
+        const zc a0 = col[k], b0 = col[k + 1];
+        col[k] = cs[i][k] * a0 + sn[i][k] * b0;
+        col[k + 1] = -std::conj(sn[i][k]) * a0 + cs[i][k] * b0;
+      }
+      const zc a0 = col[j];
+      const double bb = col[j + 1].real();
+      const double r = std::hypot(std::abs(a0), bb);
+      double c;
+      zc s;
+      if (std::abs(a0) == 0.0) {
+        c = 0.0;
+        s = zc(1.0, 0.0);
+        col[j] = zc(bb, 0.0);
+      } else {
+        const zc ph = a0 / std::abs(a0);
+        c = std::abs(a0) / r;
+        s = ph * bb / r;
+        col[j] = ph * r;
+      }
+      col[j + 1] = 0.0;
+      cs[i].push_back(c);
+      sn[i].push_back(s);
+      gv[i].push_back(-std::conj(s) * gv[i][j]);
+      gv[i][j] = c * gv[i][j];
+      H[i].push_back(col);
+      const double rel = std::abs(gv[i][j + 1]) / beta[i];
+      res[i].iters = j + 1;
+      res[i].relres = rel;
+      res[i].converged = rel <= tol;
+      if ((fixed == 0 && rel <= tol) || rel <= 1e-15 || hn[i] == 0.0) {
+        active[i] = 0;
+        --nactive;
+      }
     }
-    const zc a = col[j];
-    const double bb = col[j + 1].real();
-    const double r = std::hypot(std::abs(a), bb);
-    double c;
-    zc s;
-    if (std::abs(a) == 0.0) {
-      c = 0.0;
-      s = zc(1.0, 0.0);
-      col[j] = zc(bb, 0.0);
-    } else {
-      const zc ph = a / std::abs(a);
-      c = std::abs(a) / r;
-      s = ph * bb / r;
-      col[j] = ph * r;
+    if (nactive == 0 || j + 1 == limit) break;
+    for (int i = 0; i < B; ++i) sc[i] = (active[i] && hn[i] > 0.0) ? 1.0 / hn[i] : 0.0;
+    LS_TRY(vec_scale_b(p, w, w, sc.data(), N, B));
+  }
+  // R y = g per right-hand side, padded with zeros to jlast columns
+  std::vector<cplx> yc((size_t)B * jlast, cmk(0.0, 0.0));
+  for (int i = 0; i < B; ++i) {
+    const int jd = (int)H[i].size();
+    std::vector<zc> y(jd);
+    for (int r = jd - 1; r >= 0; --r) {
+      zc s = gv[i][r];
+      for (int k = r + 1; k < jd; ++k) s -= H[i][k][r] * y[k];
+      y[r] = s / H[i][r][r];
     }
-    col[j + 1] = 0.0;
-    cs.push_back(c);
-    sn.push_back(s);
-    gv.push_back(-std::conj(s) * gv[j]);
-    gv[j] = c * gv[j];
-    H.push_back(col);
-    rel = std::abs(gv[j + 1]) / beta;
-    jdone = j + 1;
-    const bool done = (fixed == 0 && rel <= tol) || rel <= 1e-15 || hn == 0.0;
-    if (done || j + 1 == limit) break;
-    LS_TRY(vec_scale_copy(p, V(j + 1), w, 1.0 / hn, N));
+    for (int k = 0; k < jd; ++k) yc[(size_t)i * jlast + k] = fromz(y[k]);
   }
-  // R y = g
-  std::vector<zc> y(jdone);
-  for (int i = jdone - 1; i >= 0; --i) {
-    zc s = gv[i];
-    for (int k = i + 1; k < jdone; ++k) s -= H[k][i] * y[k];
-    y[i] = s / H[i][i];
-  }
-  std::vector<cplx> yc(jdone);
-  for (int i = 0; i < jdone; ++i) yc[i] = fromz(y[i]);
-  LS_TRY(vec_lincomb(p, x, KZ.base, jdone, N, yc.data(), N));
-  res.iters = jdone;
-  res.relres = rel;
-  res.converged = rel <= tol;
-  return LS_OK;
+  return vec_lincomb(p, x, KZ.base, jlast, stride, yc.data(), N, B);
 }
 
-ls_status inner_prec(ls_plan* p, const cplx* in, cplx* out) {
+template <typename T>
+ls_status inner_prec(ls_plan* p, const T* in, T* out, int B) {
   const size_t N = (size_t)p->n * p->n;
   switch (p->opt.precond) {
     case LS_PREC_BD:
-      return bidirectional_apply(p, in, out);
+      return bidirectional_apply(p, in, out, B);
     case LS_PREC_PT1:
-      return sweep_apply(p, 0, in, out, false);
+      return sweep_apply(p, 0, in, out, false, B);
     default:
-      return vec_copy(p, out, in, N);
+      return vec_copy(p, out, in, N * B);
   }
 }
 
-// Alg. 3 for one right-hand side.
-ls_status precond_one(ls_plan* p, const cplx* r, cplx* z, GmresResult& res) {
+template <typename T>
+struct PK;
+template <>
+struct PK<cplx> {
+  static cplx*& rhs(ls_plan* p) { return p->inner_rhs; }
+  static KrylovSpaceT<cplx>& iV(ls_plan* p) { return p->innerV; }
+  static KrylovSpaceT<cplx>& iZ(ls_plan* p) { return p->innerZ; }
+  static KrylovSpaceT<cplx>& oV(ls_plan* p) { return p->outerV; }
+  static KrylovSpaceT<cplx>& oZ(ls_plan* p) { return p->outerZ; }
+};
+template <>
+struct PK<fcplx> {
+  static fcplx*& rhs(ls_plan* p) { return p->inner_rhs32; }
+  static KrylovSpaceT<fcplx>& iV(ls_plan* p) { return p->innerV32; }
+  static KrylovSpaceT<fcplx>& iZ(ls_plan* p) { return p->innerZ32; }
+  static KrylovSpaceT<fcplx>& oV(ls_plan* p) { return p->outerV32; }
+  static KrylovSpaceT<fcplx>& oZ(ls_plan* p) { return p->outerZ32; }
+};
+
+// Alg. 3 for B right-hand sides, in the precision of T.
+template <typename T>
+ls_status precond_batch(ls_plan* p, const T* r, T* z, int B, std::vector<GmresResult>& res) {
   const size_t N = (size_t)p->n * p->n;
-  if (!p->inner_rhs) LS_TRY(plan_alloc(p, (void**)&p->inner_rhs, sizeof(cplx) * N));
-  LS_TRY(stencil_apply_A(p, r, p->inner_rhs, 1));
-  auto op = [&](const cplx* in, cplx* out) { return stencil_apply_C(p, in, out, 1); };
-  auto pr = [&](const cplx* in, cplx* out) { return inner_prec(p, in, out); };
-  return fgmres(p, op, pr, p->inner_rhs, z, p->opt.inner_tol, p->opt.max_inner,
-                p->opt.inner_fixed_iters, p->innerV, p->innerZ, res);
+  T*& g = PK<T>::rhs(p);
+  if (!g) LS_TRY(plan_alloc(p, (void**)&g, sizeof(T) * N * p->opt.max_batch));
+  LS_TRY(stencil_apply_A(p, r, g, B));
+  auto op = [&](const T* in, T* out, int nb) { return stencil_apply_C(p, in, out, nb); };
+  auto pr = [&](const T* in, T* out, int nb) { return inner_prec<T>(p, in, out, nb); };
+  return fgmres<T>(p, op, pr, g, z, B, p->opt.inner_tol, p->opt.max_inner,
+                   p->opt.inner_fixed_iters, PK<T>::iV(p), PK<T>::iZ(p), res);
+}
+
+__global__ void k_real_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t cnt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = (float)a[i];
+}
+
+// Runs fn on FP32 copies of FP64 device arrays (FP32 plans).
+struct F32Scratch {
+  fcplx* a = nullptr;
+  fcplx* b = nullptr;
+};
+
+ls_status f32_scratch(ls_plan* p, F32Scratch& s) {
+  // vtmp32 holds 3 batches of grid vectors; slots 1 and 2 are free outside
+  // Alg. 2's residual (slot 0)
+  const size_t BN = (size_t)p->n * p->n * p->opt.max_batch;
+  s.a = p->vtmp32 + BN;
+  s.b = p->vtmp32 + 2 * BN;
+  return LS_OK;
 }
 
 bool valid_opts(const ls_options& o) {
   return o.ext >= 0 && o.inner_tol > 0 && o.max_outer >= 1 && o.max_inner >= 1 &&
-         o.precision == LS_FP64 && o.precond >= LS_PREC_BD && o.precond <= LS_PREC_NONE &&
-         o.inner_fixed_iters >= 0 && o.max_batch >= 1 && o.slabs >= 0 && std::isfinite(o.shift_c);
+         (o.precision == LS_FP64 || o.precision == LS_FP32_REFINE) && o.precond >= LS_PREC_BD &&
+         o.precond <= LS_PREC_NONE && o.inner_fixed_iters >= 0 && o.max_batch >= 1 &&
+         o.slabs >= 0 && std::isfinite(o.shift_c) && o.lowp_tol > 0 && o.max_refine >= 1;
 }
 
 }  // namespace
@@ -187,6 +266,54 @@ ls_status plan_alloc(ls_plan* p, void** ptr, size_t bytes) {
   return LS_OK;
 }
 
+// Runs an FP32 operation on B grid vectors given and returned in FP64
+// (FP32 plans).
+template <class F>
+static ls_status via_f32(ls_plan* p, const double* in, double* out, int B, F fn) {
+  const size_t N = (size_t)p->n * p->n;
+  F32Scratch sc;
+  LS_TRY(f32_scratch(p, sc));
+  std::vector<double> one(B, 1.0);
+  LS_TRY(vec_to_f32_b(p, sc.a, reinterpret_cast<const cplx*>(in), one.data(), N, B));
+  LS_TRY(fn(sc.a, sc.b));
+  return vec_from_f32_b(p, reinterpret_cast<cplx*>(out), nullptr, sc.b, one.data(), N, B);
+}
+
+// Outer flexible GMRES in the precision of T on H u = f for B right-hand sides.
+template <typename T>
+static ls_status outer_fgmres(ls_plan* p, const T* f, T* u, int B, const std::vector<double>& tol,
+                              std::vector<GmresResult>& res, std::vector<int>& inner_total) {
+  auto op = [&](const T* in, T* out, int nb) -> ls_status {
+    if constexpr (std::is_same<T, cplx>::value) return apply_H(p, in, out, nb, 1.0, 1.0);
+    else return apply_H32(p, in, out, nb, 1.0, 1.0);
+  };
+  auto pr = [&](const T* in, T* out, int nb) -> ls_status {
+    std::vector<GmresResult> r;
+    ls_status s = precond_batch<T>(p, in, out, nb, r);
+    for (int i = 0; i < nb; ++i) inner_total[i] += r[i].iters;
+    return s;
+  };
+  // one tolerance for the lockstep loop: the largest requested (the others
+  // are met when the loop continues for the slowest right-hand side)
+  double t = 0.0;
+  for (double x : tol) t = std::max(t, x);
+  return fgmres<T>(p, op, pr, f, u, B, t, p->opt.max_outer, 0, PK<T>::oV(p), PK<T>::oZ(p), res);
+}
+
+// r = f - H u and ||r|| / ||f|| per right-hand side, FP64.
+static ls_status true_residual(ls_plan* p, const cplx* f, const cplx* u, cplx* r, int B,
+                               const std::vector<double>& nf, std::vector<double>& rel) {
+  const size_t N = (size_t)p->n * p->n;
+  std::vector<double> nr(B);
+  LS_TRY(apply_H(p, u, r, B, 1.0, 1.0));
+  LS_TRY(vec_axpy(p, r, f, cmk(-1.0, 0.0), N * B));   // r = H u - f
+  LS_TRY(vec_scale_copy(p, r, r, -1.0, N * B));       // r = f - H u
+  LS_TRY(vec_norms(p, r, N, B, nr.data()));
+  rel.resize(B);
+  for (int i = 0; i < B; ++i) rel[i] = nf[i] > 0 ? nr[i] / nf[i] : 0.0;
+  return LS_OK;
+}
+
 extern "C" {
 
 void ls_options_default(ls_options* o) {
@@ -202,6 +329,8 @@ void ls_options_default(ls_options* o) {
   o->precond = LS_PREC_BD;
   o->inner_fixed_iters = 0;
   o->max_batch = 1;
+  o->lowp_tol = 1e-5;
+  o->max_refine = 10;
 }
 
 const char* ls_status_str(ls_status s) {
@@ -235,11 +364,22 @@ static ls_status create_impl(ls_plan* p, const double* m) {
   LS_TRY(fft_setup_twiddles(p));
   LS_TRY(plan_alloc(p, (void**)&p->stencil_d, sizeof(cplx) * 324));
   LS_TRY(plan_alloc(p, (void**)&p->spec, sizeof(cplx) * p->spec_side * p->spec_side));
+  if (p->fp32) {
+    LS_TRY(plan_alloc(p, (void**)&p->f32.m, sizeof(float) * n * n));
+    k_real_to_f32<<<(unsigned)(((size_t)n * n + 255) / 256), 256, 0, p->stream>>>(p->m, p->f32.m,
+                                                                                (size_t)n * n);
+    LS_HIP(hipGetLastError());
+    LS_TRY(plan_alloc(p, (void**)&p->f32.stencil, sizeof(fcplx) * 324));
+    LS_TRY(plan_alloc(p, (void**)&p->f32.spec, sizeof(fcplx) * p->spec_side * p->spec_side));
+    LS_TRY(plan_alloc(p, (void**)&p->f32.fft_work, sizeof(fcplx) * (size_t)p->opt.max_batch * n * p->P));
+    LS_TRY(plan_alloc(p, (void**)&p->vtmp32, sizeof(fcplx) * (size_t)3 * n * n * p->opt.max_batch));
+  }
   {
     cplx* circ = nullptr;
     LS_HIP(hipMalloc(&circ, sizeof(cplx) * (size_t)p->P * p->P));
     ls_status s = launch_circulant(p, circ);
     if (s == LS_OK) s = stencils_build(p, circ);
+    if (s == LS_OK && p->fp32) s = stencils_to_f32(p);
     if (s == LS_OK) s = fft2_full_forward(p, circ);
     if (s == LS_OK) s = spectrum_extract(p, circ);
     if (s == LS_OK && hipStreamSynchronize(p->stream) != hipSuccess) s = LS_EDEVICE;
@@ -247,7 +387,7 @@ static ls_status create_impl(ls_plan* p, const double* m) {
     if (s != LS_OK) return s;
   }
   LS_TRY(plan_alloc(p, (void**)&p->fft_work, sizeof(cplx) * (size_t)p->opt.max_batch * n * p->P));
-  LS_TRY(plan_alloc(p, (void**)&p->vtmp, sizeof(cplx) * (size_t)3 * n * n));
+  LS_TRY(plan_alloc(p, (void**)&p->vtmp, sizeof(cplx) * (size_t)3 * n * n * p->opt.max_batch));
   if (p->opt.precond != LS_PREC_NONE) LS_TRY(slabs_build(p));
   LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
@@ -284,6 +424,7 @@ ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const dou
   p->omega = omega;
   p->opt = o;
   p->L = L;
+  p->fp32 = (o.precision == LS_FP32_REFINE);
   p->stream = reinterpret_cast<hipStream_t>(stream);
   int P = 1, logP = 0;
   while (P < 2 * n - 1) { P <<= 1; ++logP; }
@@ -387,9 +528,17 @@ ls_status ls_slab_solve(ls_plan* p, int orient, int slab, const double* b, doubl
   }
   DeviceGuard dg(p->device);
   Slab& s = p->slabs[orient][slab];
-  LS_TRY(vec_copy(p, reinterpret_cast<cplx*>(x), reinterpret_cast<const cplx*>(b),
-                  (size_t)p->n * s.q));
-  return slab_solve_frame(p, s, reinterpret_cast<cplx*>(x));
+  const size_t cnt = (size_t)p->n * s.q;
+  const cplx* bb = reinterpret_cast<const cplx*>(b);
+  cplx* xx = reinterpret_cast<cplx*>(x);
+  if (p->fp32) {
+    fcplx* t = p->vtmp32;  // n*q <= n*n
+    LS_TRY(vec_to_f32(p, t, bb, 1.0, cnt));
+    LS_TRY(slab_solve_frame(p, s, t));
+    return vec_from_f32(p, xx, nullptr, t, 1.0, cnt);
+  }
+  LS_TRY(vec_copy(p, xx, bb, cnt));
+  return slab_solve_frame(p, s, xx);
 }
 
 ls_status ls_sweep(ls_plan* p, int orient, const double* g, double* v) {
@@ -398,7 +547,9 @@ ls_status ls_sweep(ls_plan* p, int orient, const double* g, double* v) {
     return LS_EINVAL;
   }
   DeviceGuard dg(p->device);
-  return sweep_apply(p, orient, reinterpret_cast<const cplx*>(g), reinterpret_cast<cplx*>(v), false);
+  if (p->fp32)
+    return via_f32(p, g, v, 1, [&](const fcplx* a, fcplx* b) { return sweep_apply(p, orient, a, b, false, 1); });
+  return sweep_apply(p, orient, reinterpret_cast<const cplx*>(g), reinterpret_cast<cplx*>(v), false, 1);
 }
 
 ls_status ls_bidirectional(ls_plan* p, const double* g, double* v) {
@@ -407,7 +558,18 @@ ls_status ls_bidirectional(ls_plan* p, const double* g, double* v) {
     return LS_EINVAL;
   }
   DeviceGuard dg(p->device);
-  return bidirectional_apply(p, reinterpret_cast<const cplx*>(g), reinterpret_cast<cplx*>(v));
+  if (p->fp32)
+    return via_f32(p, g, v, 1, [&](const fcplx* a, fcplx* b) { return bidirectional_apply(p, a, b, 1); });
+  return bidirectional_apply(p, reinterpret_cast<const cplx*>(g), reinterpret_cast<cplx*>(v), 1);
+}
+
+ls_status ls_apply_c64(ls_plan* p, const float* v, float* Hv, int batch) {
+  if (!p || !v || !Hv || batch < 1 || batch > p->opt.max_batch || !p->fp32) {
+    ls_set_error("ls_apply_c64: needs an LS_FP32_REFINE plan and batch in [1, max_batch]");
+    return LS_EINVAL;
+  }
+  DeviceGuard dg(p->device);
+  return apply_H32(p, reinterpret_cast<const fcplx*>(v), reinterpret_cast<fcplx*>(Hv), batch, 1.0, 1.0);
 }
 
 ls_status ls_precond_apply(ls_plan* p, const double* r, double* z, int batch) {
@@ -418,11 +580,18 @@ ls_status ls_precond_apply(ls_plan* p, const double* r, double* z, int batch) {
   DeviceGuard dg(p->device);
   const size_t N = (size_t)p->n * p->n;
   bool all = true;
-  for (int b = 0; b < batch; ++b) {
-    GmresResult res;
-    LS_TRY(precond_one(p, reinterpret_cast<const cplx*>(r) + b * N,
-                       reinterpret_cast<cplx*>(z) + b * N, res));
-    if (p->opt.inner_fixed_iters == 0 && !res.converged) all = false;
+  for (int b0 = 0; b0 < batch; b0 += p->opt.max_batch) {
+    const int B = std::min(p->opt.max_batch, batch - b0);
+    std::vector<GmresResult> res;
+    const double* rb = r + 2 * b0 * N;
+    double* zb = z + 2 * b0 * N;
+    if (p->fp32) {
+      LS_TRY(via_f32(p, rb, zb, B, [&](const fcplx* a, fcplx* o) { return precond_batch<fcplx>(p, a, o, B, res); }));
+    } else {
+      LS_TRY(precond_batch<cplx>(p, reinterpret_cast<const cplx*>(rb), reinterpret_cast<cplx*>(zb), B, res));
+    }
+    if (p->opt.inner_fixed_iters == 0)
+      for (auto& x : res) all = all && x.converged;
   }
   LS_HIP(hipStreamSynchronize(p->stream));
   if (!all) {
@@ -441,41 +610,78 @@ ls_status ls_solve(ls_plan* p, const double* f, double* u, int batch, double tol
   DeviceGuard dg(p->device);
   const size_t N = (size_t)p->n * p->n;
   bool all = true;
-  for (int b = 0; b < batch; ++b) {
+  for (int b0 = 0; b0 < batch; b0 += p->opt.max_batch) {
+    const int B = std::min(p->opt.max_batch, batch - b0);
     const auto t0 = std::chrono::steady_clock::now();
-    const cplx* fb = reinterpret_cast<const cplx*>(f) + b * N;
-    cplx* ub = reinterpret_cast<cplx*>(u) + b * N;
-    int inner_total = 0;
-    auto op = [&](const cplx* in, cplx* out) { return apply_H(p, in, out, 1, 1.0, 1.0); };
-    auto pr = [&](const cplx* in, cplx* out) -> ls_status {
-      GmresResult r;
-      ls_status s = precond_one(p, in, out, r);
-      inner_total += r.iters;
-      return s;
-    };
-    GmresResult res;
-    LS_TRY(fgmres(p, op, pr, fb, ub, tol, p->opt.max_outer, 0, p->outerV, p->outerZ, res));
-    // true residual ||f - H u|| / ||f||
-    double nf = 0.0, nr = 0.0;
-    cplx* rbuf = p->vtmp + N;
-    LS_TRY(apply_H(p, ub, rbuf, 1, 1.0, 1.0));
-    LS_TRY(vec_axpy(p, rbuf, fb, cmk(-1.0, 0.0), N));
-    LS_TRY(vec_norm(p, rbuf, N, &nr));
-    LS_TRY(vec_norm(p, fb, N, &nf));
+    const cplx* fb = reinterpret_cast<const cplx*>(f) + b0 * N;
+    cplx* ub = reinterpret_cast<cplx*>(u) + b0 * N;
+    cplx* rbuf = p->vtmp + (size_t)p->opt.max_batch * N;
+    std::vector<int> inner_total(B, 0), outer_total(B, 0);
+    std::vector<double> nf(B), rel(B, 0.0), est(B, 0.0);
+    std::vector<char> conv(B, 0);
+    LS_TRY(vec_norms(p, fb, N, B, nf.data()));
+    if (!p->fp32) {
+      std::vector<GmresResult> res;
+      LS_TRY(outer_fgmres<cplx>(p, fb, ub, B, std::vector<double>(B, tol), res, inner_total));
+      for (int i = 0; i < B; ++i) {
+        outer_total[i] = res[i].iters;
+        est[i] = res[i].relres;
+        conv[i] = res[i].converged;
+      }
+      LS_TRY(true_residual(p, fb, ub, rbuf, B, nf, rel));
+    } else {
+      // Iterative refinement: r = f - H u in FP64, d ~ H^{-1} r by FP32
+      // flexible GMRES to max(lowp_tol, tol / ||r||_rel), u += d, until
+      // ||r|| / ||f|| <= tol for every right-hand side.
+      LS_TRY(vec_zero(p, ub, N * B));
+      LS_TRY(vec_copy(p, rbuf, fb, N * B));
+      for (int i = 0; i < B; ++i) rel[i] = nf[i] > 0 ? 1.0 : 0.0;
+      F32Scratch sc;
+      LS_TRY(f32_scratch(p, sc));
+      for (int it = 0; it < p->opt.max_refine; ++it) {
+        bool done = true;
+        std::vector<double> scale(B), back(B), tgt(B);
+        for (int i = 0; i < B; ++i) {
+          const bool act = rel[i] > tol;
+          done = done && !act;
+          const double nr = rel[i] * nf[i];
+          scale[i] = act ? 1.0 / nr : 0.0;   // finished right-hand sides get a zero correction
+          back[i] = act ? nr : 0.0;
+          tgt[i] = act ? std::max(p->opt.lowp_tol, 0.5 * tol / rel[i]) : 1.0;
+        }
+        if (done) break;
+        LS_TRY(vec_to_f32_b(p, sc.a, rbuf, scale.data(), N, B));
+        std::vector<GmresResult> res;
+        double tmin = 1.0;
+        for (int i = 0; i < B; ++i) if (rel[i] > tol) tmin = std::min(tmin, tgt[i]);
+        LS_TRY(outer_fgmres<fcplx>(p, sc.a, sc.b, B, std::vector<double>(B, tmin), res, inner_total));
+        for (int i = 0; i < B; ++i) outer_total[i] += (rel[i] > tol) ? res[i].iters : 0;
+        LS_TRY(vec_from_f32_b(p, ub, ub, sc.b, back.data(), N, B));
+        LS_TRY(true_residual(p, fb, ub, rbuf, B, nf, rel));
+      }
+      for (int i = 0; i < B; ++i) {
+        est[i] = rel[i];
+        conv[i] = rel[i] <= tol;
+      }
+    }
     const auto t1 = std::chrono::steady_clock::now();
-    if (!res.converged) all = false;
-    if (info) {
-      info[b].outer_its = res.iters;
-      info[b].inner_its_total = inner_total;
-      info[b].relres_est = res.relres;
-      info[b].relres_true = nf > 0 ? nr / nf : 0.0;
-      info[b].converged = res.converged ? 1 : 0;
-      info[b].t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    for (int i = 0; i < B; ++i) {
+      if (!conv[i]) all = false;
+      if (info) {
+        ls_solve_info& I = info[b0 + i];
+        I.outer_its = outer_total[i];
+        I.inner_its_total = inner_total[i];
+        I.relres_est = est[i];
+        I.relres_true = rel[i];
+        I.converged = conv[i] ? 1 : 0;
+        I.t_ms = ms / B;
+      }
     }
   }
   LS_HIP(hipStreamSynchronize(p->stream));
   if (!all) {
-    ls_set_error("ls_solve: outer flexible GMRES hit max_outer");
+    ls_set_error("ls_solve: hit max_outer / max_refine before tol");
     return LS_ENOCONV;
   }
   return LS_OK;

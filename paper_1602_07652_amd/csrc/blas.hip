@@ -1,7 +1,8 @@
 // Level-1 kernels for the GMRES drivers (Section 4, Alg. 3 and the outer
 // loop): multi-vector inner products with a deterministic two-stage
-// reduction, multi-vector updates and linear combinations.  Vectors are
-// complex FP64; a set of k vectors is stored with a fixed stride.
+// reduction (always accumulated in FP64), multi-vector updates and linear
+// combinations, and the FP64 <-> FP32 conversions of the refinement loop.
+// Vectors are complex FP64 or FP32; a set of k vectors has a fixed stride.
 #include "ls_internal.h"
 
 #include <vector>
@@ -12,20 +13,30 @@ constexpr int kDotBlocks = 512;
 constexpr int kDotThreads = 256;
 constexpr int kGroup = 8;  // vectors per pass over w
 
-// partial[blk][i] = sum over this block's strided slice of conj(V_i) w
-__global__ __launch_bounds__(kDotThreads) void k_multidot(const cplx* __restrict__ V, int k,
+template <typename T>
+__device__ __forceinline__ cplx up(T a) { return cmk((double)a.x, (double)a.y); }
+
+// partial[b][blk][i] = sum over this block's strided slice of
+// conj(V_i[b]) w[b] for right-hand side b = blockIdx.y (V_i[b] at
+// V + i*stride + b*N, w[b] at w + b*N), accumulated in FP64 whatever the
+// storage precision T.
+template <typename T>
+__global__ __launch_bounds__(kDotThreads) void k_multidot(const T* __restrict__ V, int k,
                                                           size_t stride,
-                                                          const cplx* __restrict__ w, size_t N,
+                                                          const T* __restrict__ w, size_t N,
                                                           cplx* __restrict__ partial) {
+  V += (size_t)blockIdx.y * N;
+  w += (size_t)blockIdx.y * N;
+  partial += (size_t)blockIdx.y * gridDim.x * kGroup;
   cplx acc[kGroup];
 #pragma unroll
   for (int i = 0; i < kGroup; ++i) acc[i] = cmk(0, 0);
   for (size_t t = (size_t)blockIdx.x * kDotThreads + threadIdx.x; t < N;
        t += (size_t)gridDim.x * kDotThreads) {
-    const cplx wv = w[t];
+    const cplx wv = up(w[t]);
 #pragma unroll
     for (int i = 0; i < kGroup; ++i)
-      if (i < k) acc[i] = cfmaconj(V[i * stride + t], wv, acc[i]);
+      if (i < k) acc[i] = cfmaconj(up(V[i * stride + t]), wv, acc[i]);
   }
   __shared__ cplx red[kDotThreads];
   for (int i = 0; i < k; ++i) {
@@ -40,129 +51,240 @@ __global__ __launch_bounds__(kDotThreads) void k_multidot(const cplx* __restrict
   }
 }
 
-__global__ void k_finish_dot(const cplx* __restrict__ partial, int nblk, int k,
-                             cplx* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i >= k) return;
+// out[b][i] = sum_blk partial[b][blk][i]: one workgroup per (i, b), fixed
+// tree order.  out row stride ldo.
+__global__ __launch_bounds__(256) void k_finish_dot(const cplx* __restrict__ partial, int nblk,
+                                                    cplx* __restrict__ out, int ldo) {
+  const int i = blockIdx.x;
+  partial += (size_t)blockIdx.y * nblk * kGroup;
+  out += (size_t)blockIdx.y * ldo;
+  __shared__ cplx red[256];
   cplx s = cmk(0, 0);
-  for (int b = 0; b < nblk; ++b) s = cadd(s, partial[(size_t)b * kGroup + i]);
-  out[i] = s;
+  for (int b = threadIdx.x; b < nblk; b += 256) s = cadd(s, partial[(size_t)b * kGroup + i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 
-// y = y0 - sum_i c_i V_i  (sign = -1) or y = y0 + sum (sign = +1); y0 may
-// be null (treated as 0).
-__global__ void k_multiaxpy(cplx* __restrict__ y, const cplx* __restrict__ y0,
-                            const cplx* __restrict__ V, int k, size_t stride,
-                            const cplx* __restrict__ c, size_t N, double sign) {
+// y[b] = y0[b] + sign * sum_i c[b][i] V_i[b] (y0 may be null: 0), in the
+// precision of T; b = blockIdx.y, c row stride ldc.
+template <typename T>
+__global__ void k_multiaxpy(T* __restrict__ y, const T* __restrict__ y0, const T* __restrict__ V,
+                            int k, size_t stride, const cplx* __restrict__ c, int ldc, size_t N,
+                            double sign) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
-  cplx acc = y0 ? y0[t] : cmk(0, 0);
-  for (int i = 0; i < k; ++i) {
-    const cplx ci = cscale(c[i], sign);
-    acc = cfma(ci, V[i * stride + t], acc);
-  }
-  y[t] = acc;
+  const size_t off = (size_t)blockIdx.y * N + t;
+  c += (size_t)blockIdx.y * ldc;
+  T acc = y0 ? y0[off] : tmk<T>(0, 0);
+  for (int i = 0; i < k; ++i) acc = tfma(tmk<T>(sign * c[i].x, sign * c[i].y), V[i * stride + off], acc);
+  y[off] = acc;
 }
 
-__global__ void k_scale_copy(cplx* __restrict__ y, const cplx* __restrict__ x, double s, size_t N) {
+// y[b] = s[b] * x[b]
+template <typename T>
+__global__ void k_scale_b(T* __restrict__ y, const T* __restrict__ x, const double* __restrict__ s,
+                          size_t N) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < N) y[t] = cscale(x[t], s);
+  if (t >= N) return;
+  const size_t off = (size_t)blockIdx.y * N + t;
+  const double f = s[blockIdx.y];
+  y[off] = tmk<T>(x[off].x * f, x[off].y * f);
 }
 
-__global__ void k_axpy(cplx* __restrict__ y, const cplx* __restrict__ x, cplx a, size_t N) {
+template <typename T>
+__global__ void k_scale_copy(T* __restrict__ y, const T* __restrict__ x, double s, size_t N) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < N) y[t] = cfma(a, x[t], y[t]);
+  if (t < N) y[t] = tmk<T>(x[t].x * s, x[t].y * s);
 }
 
-__global__ void k_fill_zero(cplx* __restrict__ y, size_t N) {
+template <typename T>
+__global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, cplx a, size_t N) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < N) y[t] = cmk(0, 0);
+  if (t < N) y[t] = tfma(tmk<T>(a.x, a.y), x[t], y[t]);
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* __restrict__ y, size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) y[t] = tmk<T>(0, 0);
+}
+
+// y[b] (FP32) = s[b] * x[b] (FP64)
+__global__ void k_down(fcplx* __restrict__ y, const cplx* __restrict__ x,
+                       const double* __restrict__ s, size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const size_t o = (size_t)blockIdx.y * N + t;
+  const double f = s[blockIdx.y];
+  y[o] = make_float2((float)(x[o].x * f), (float)(x[o].y * f));
+}
+
+// y[b] (FP64) = y0[b] + s[b] * x[b] (FP32); y0 may be null
+__global__ void k_up_axpy(cplx* __restrict__ y, const cplx* __restrict__ y0,
+                          const fcplx* __restrict__ x, const double* __restrict__ s, size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const size_t o = (size_t)blockIdx.y * N + t;
+  const double f = s[blockIdx.y];
+  cplx v = cmk((double)x[o].x * f, (double)x[o].y * f);
+  if (y0) v = cadd(y0[o], v);
+  y[o] = v;
 }
 
 ls_status ensure_red(ls_plan* p) {
   if (!p->red) {
-    LS_TRY(plan_alloc(p, (void**)&p->red, sizeof(cplx) * kDotBlocks * kGroup));
-    LS_TRY(plan_alloc(p, (void**)&p->dotbuf, sizeof(cplx) * 256));
+    const int B = p->opt.max_batch;
+    LS_TRY(plan_alloc(p, (void**)&p->red, sizeof(cplx) * kDotBlocks * kGroup * B));
+    LS_TRY(plan_alloc(p, (void**)&p->dotbuf, sizeof(cplx) * 256 * B));
   }
   return LS_OK;
 }
 
 inline int blocks_for(size_t N, int t) { return (int)((N + t - 1) / t); }
 
-}  // namespace
-
-ls_status vec_multidot(ls_plan* p, const cplx* V, int k, size_t stride, const cplx* w, size_t N,
-                       cplx* out_host) {
+ls_status upload_coef(ls_plan* p, const cplx* coef_host, size_t cnt) {
   LS_TRY(ensure_red(p));
-  if (k > 256) {
-    ls_set_error("too many Krylov vectors");
+  LS_HIP(hipMemcpyAsync(p->dotbuf, coef_host, sizeof(cplx) * cnt, hipMemcpyHostToDevice, p->stream));
+  return LS_OK;
+}
+
+// out_host[b*k + i] = <V_i[b], w[b]> for i < k, b < B.
+template <typename T>
+ls_status multidot_t(ls_plan* p, const T* V, int k, size_t stride, const T* w, size_t N, int B,
+                     cplx* out_host) {
+  LS_TRY(ensure_red(p));
+  if (k > 256 || B > p->opt.max_batch) {
+    ls_set_error("too many Krylov vectors or right-hand sides");
     return LS_EUNSUPPORTED;
   }
   const int nblk = (int)std::min<size_t>(kDotBlocks, (N + kDotThreads - 1) / kDotThreads);
   for (int g0 = 0; g0 < k; g0 += kGroup) {
     const int kk = std::min(kGroup, k - g0);
-    k_multidot<<<nblk, kDotThreads, 0, p->stream>>>(V + g0 * stride, kk, stride, w, N, p->red);
-    k_finish_dot<<<1, 64, 0, p->stream>>>(p->red, nblk, kk, p->dotbuf + g0);
+    k_multidot<T><<<dim3(nblk, B), kDotThreads, 0, p->stream>>>(V + g0 * stride, kk, stride, w, N, p->red);
+    k_finish_dot<<<dim3(kk, B), 256, 0, p->stream>>>(p->red, nblk, p->dotbuf + g0, k);
   }
   LS_HIP(hipGetLastError());
-  LS_HIP(hipMemcpyAsync(out_host, p->dotbuf, sizeof(cplx) * k, hipMemcpyDeviceToHost, p->stream));
+  LS_HIP(hipMemcpyAsync(out_host, p->dotbuf, sizeof(cplx) * k * B, hipMemcpyDeviceToHost, p->stream));
   LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
 
-static ls_status upload_coef(ls_plan* p, const cplx* coef_host, int k) {
-  LS_TRY(ensure_red(p));
-  LS_HIP(hipMemcpyAsync(p->dotbuf, coef_host, sizeof(cplx) * k, hipMemcpyHostToDevice, p->stream));
-  return LS_OK;
-}
-
-ls_status vec_multiaxpy(ls_plan* p, cplx* w, const cplx* V, int k, size_t stride,
-                        const cplx* coef_host, size_t N) {
-  if (k == 0) return LS_OK;
-  LS_TRY(upload_coef(p, coef_host, k));
-  k_multiaxpy<<<blocks_for(N, 256), 256, 0, p->stream>>>(w, w, V, k, stride, p->dotbuf, N, -1.0);
+template <typename T>
+ls_status multiaxpy_t(ls_plan* p, T* y, const T* y0, const T* V, int k, size_t stride,
+                      const cplx* coef_host, size_t N, int B, double sign) {
+  if (k == 0) {
+    if (y0 == nullptr) {
+      k_fill_zero<T><<<blocks_for(N * B, 256), 256, 0, p->stream>>>(y, N * B);
+      LS_HIP(hipGetLastError());
+    }
+    return LS_OK;
+  }
+  LS_TRY(upload_coef(p, coef_host, (size_t)k * B));
+  k_multiaxpy<T><<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, y0, V, k, stride, p->dotbuf,
+                                                                     k, N, sign);
   LS_HIP(hipGetLastError());
   // the coefficient buffer is reused by the next call
   LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
 
-ls_status vec_lincomb(ls_plan* p, cplx* x, const cplx* Z, int k, size_t stride,
-                      const cplx* coef_host, size_t N) {
-  LS_TRY(upload_coef(p, coef_host, k));
-  k_multiaxpy<<<blocks_for(N, 256), 256, 0, p->stream>>>(x, nullptr, Z, k, stride, p->dotbuf, N, 1.0);
+template <typename T>
+ls_status scale_b_t(ls_plan* p, T* y, const T* x, const double* s_host, size_t N, int B) {
+  LS_TRY(ensure_red(p));
+  double* sd = reinterpret_cast<double*>(p->dotbuf);
+  LS_HIP(hipMemcpyAsync(sd, s_host, sizeof(double) * B, hipMemcpyHostToDevice, p->stream));
+  k_scale_b<T><<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, x, sd, N);
   LS_HIP(hipGetLastError());
   LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
 
-ls_status vec_norm(ls_plan* p, const cplx* w, size_t N, double* out_host) {
-  cplx d;
-  LS_TRY(vec_multidot(p, w, 1, 0, w, N, &d));
-  *out_host = sqrt(fmax(d.x, 0.0));
+}  // namespace
+
+#define LS_BLAS_INSTANCES(T)                                                                     \
+  ls_status vec_multidot(ls_plan* p, const T* V, int k, size_t stride, const T* w, size_t N,      \
+                         int B, cplx* out_host) {                                                  \
+    return multidot_t<T>(p, V, k, stride, w, N, B, out_host);                                      \
+  }                                                                                                \
+  ls_status vec_multiaxpy(ls_plan* p, T* w, const T* V, int k, size_t stride,                     \
+                          const cplx* coef_host, size_t N, int B) {                                \
+    return multiaxpy_t<T>(p, w, w, V, k, stride, coef_host, N, B, -1.0);                           \
+  }                                                                                                \
+  ls_status vec_lincomb(ls_plan* p, T* x, const T* Z, int k, size_t stride,                       \
+                        const cplx* coef_host, size_t N, int B) {                                  \
+    return multiaxpy_t<T>(p, x, nullptr, Z, k, stride, coef_host, N, B, 1.0);                      \
+  }                                                                                                \
+  ls_status vec_norms(ls_plan* p, const T* w, size_t N, int B, double* out_host) {                \
+    std::vector<cplx> d(B);                                                                        \
+    LS_TRY(multidot_t<T>(p, w, 1, 0, w, N, B, d.data()));                                          \
+    for (int b = 0; b < B; ++b) out_host[b] = sqrt(fmax(d[b].x, 0.0));                             \
+    return LS_OK;                                                                                  \
+  }                                                                                                \
+  ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host) {                        \
+    return vec_norms(p, w, N, 1, out_host);                                                        \
+  }                                                                                                \
+  ls_status vec_scale_b(ls_plan* p, T* y, const T* x, const double* s_host, size_t N, int B) {    \
+    return scale_b_t<T>(p, y, x, s_host, N, B);                                                    \
+  }                                                                                                \
+  ls_status vec_scale_copy(ls_plan* p, T* y, const T* x, double s, size_t N) {                    \
+    k_scale_copy<T><<<blocks_for(N, 256), 256, 0, p->stream>>>(y, x, s, N);                        \
+    LS_HIP(hipGetLastError());                                                                     \
+    return LS_OK;                                                                                  \
+  }                                                                                                \
+  ls_status vec_axpy(ls_plan* p, T* y, const T* x, cplx a, size_t N) {                            \
+    k_axpy<T><<<blocks_for(N, 256), 256, 0, p->stream>>>(y, x, a, N);                              \
+    LS_HIP(hipGetLastError());                                                                     \
+    return LS_OK;                                                                                  \
+  }                                                                                                \
+  ls_status vec_zero(ls_plan* p, T* y, size_t N) {                                                 \
+    k_fill_zero<T><<<blocks_for(N, 256), 256, 0, p->stream>>>(y, N);                               \
+    LS_HIP(hipGetLastError());                                                                     \
+    return LS_OK;                                                                                  \
+  }                                                                                                \
+  ls_status vec_copy(ls_plan* p, T* y, const T* x, size_t N) {                                     \
+    if (y == x) return LS_OK;                                                                      \
+    LS_HIP(hipMemcpyAsync(y, x, N * sizeof(T), hipMemcpyDeviceToDevice, p->stream));               \
+    return LS_OK;                                                                                  \
+  }
+
+LS_BLAS_INSTANCES(cplx)
+LS_BLAS_INSTANCES(fcplx)
+
+static ls_status upload_scales(ls_plan* p, const double* s_host, int B, double** dev) {
+  LS_TRY(ensure_red(p));
+  *dev = reinterpret_cast<double*>(p->dotbuf);
+  LS_HIP(hipMemcpyAsync(*dev, s_host, sizeof(double) * B, hipMemcpyHostToDevice, p->stream));
   return LS_OK;
 }
 
-ls_status vec_scale_copy(ls_plan* p, cplx* y, const cplx* x, double s, size_t N) {
-  k_scale_copy<<<blocks_for(N, 256), 256, 0, p->stream>>>(y, x, s, N);
+ls_status vec_to_f32_b(ls_plan* p, fcplx* y, const cplx* x, const double* s_host, size_t N, int B) {
+  double* sd;
+  LS_TRY(upload_scales(p, s_host, B, &sd));
+  k_down<<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, x, sd, N);
   LS_HIP(hipGetLastError());
+  LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
 
-ls_status vec_axpy(ls_plan* p, cplx* y, const cplx* x, cplx a, size_t N) {
-  k_axpy<<<blocks_for(N, 256), 256, 0, p->stream>>>(y, x, a, N);
+ls_status vec_from_f32_b(ls_plan* p, cplx* y, const cplx* y0, const fcplx* x, const double* s_host,
+                         size_t N, int B) {
+  double* sd;
+  LS_TRY(upload_scales(p, s_host, B, &sd));
+  k_up_axpy<<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, y0, x, sd, N);
   LS_HIP(hipGetLastError());
+  LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
 
-ls_status vec_zero(ls_plan* p, cplx* y, size_t N) {
-  k_fill_zero<<<blocks_for(N, 256), 256, 0, p->stream>>>(y, N);
-  LS_HIP(hipGetLastError());
-  return LS_OK;
+ls_status vec_to_f32(ls_plan* p, fcplx* y, const cplx* x, double s, size_t N) {
+  return vec_to_f32_b(p, y, x, &s, N, 1);
 }
 
-ls_status vec_copy(ls_plan* p, cplx* y, const cplx* x, size_t N) {
-  if (y == x) return LS_OK;
-  LS_HIP(hipMemcpyAsync(y, x, N * sizeof(cplx), hipMemcpyDeviceToDevice, p->stream));
-  return LS_OK;
+ls_status vec_from_f32(ls_plan* p, cplx* y, const cplx* y0, const fcplx* x, double s, size_t N) {
+  return vec_from_f32_b(p, y, y0, x, &s, N, 1);
 }

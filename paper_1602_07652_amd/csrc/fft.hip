@@ -5,10 +5,11 @@
 //
 // Layout on the device (FP64 complex):
 //   v, y           [batch][n][n]          x fastest
-//   X (work)       [batch][P/8][n][8]     row spectra, tiled by 8 columns so
-//                                         that every row pass moves whole
-//                                         128-byte lines and a column pass
-//                                         reads 8 (or 4, 2) adjacent columns
+//   X (work)       [batch][P/T][n][T]     row spectra, tiled by T columns
+//                                         (T = 8 for FP64, 16 for FP32: one
+//                                         128-byte line) so every row pass
+//                                         moves whole lines and a column pass
+//                                         reads up to T adjacent columns
 //   spec           [P/2+1][P/2+1]         quarter of FFT2(circulant w),
 //                                         scaled by omega^2 / P^2
 // Passes (one HBM round trip of the n x P intermediate each way):
@@ -17,35 +18,41 @@
 //   K3 rows:    y_j = a v_j + b (first n of IFFT_P(Y_j))    (pruned output)
 // Each transform is a radix-4 Stockham FFT (one radix-2 pass first when
 // log2 P is odd) done in LDS, with the twiddles read from a P-entry table.
+// Everything is templated on the complex type (double2: FP64 path; float2:
+// the FP32 operator of the refinement loop).
 #include "ls_internal.h"
 
 #include <cmath>
 
 namespace {
 
-constexpr int kTile = 8;  // columns per 128-byte line of the intermediate
+template <typename T>
+struct Tile {
+  static constexpr int W = 128 / (int)sizeof(T);  // columns per 128-byte line
+};
 
-template <bool INV>
-__device__ __forceinline__ void radix4(cplx& a0, cplx& a1, cplx& a2, cplx& a3) {
-  const cplx t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+template <typename T, bool INV>
+__device__ __forceinline__ void radix4(T& a0, T& a1, T& a2, T& a3) {
+  const T t0 = tadd(a0, a2), t1 = tsub(a0, a2), t2 = tadd(a1, a3), t3 = tsub(a1, a3);
   // forward: X1 = t1 - i t3, X3 = t1 + i t3 ; inverse: conjugate roots
-  const cplx it3 = INV ? cmk(-t3.y, t3.x) : cmk(t3.y, -t3.x);
-  a0 = cadd(t0, t2);
-  a2 = csub(t0, t2);
-  a1 = cadd(t1, it3);
-  a3 = csub(t1, it3);
+  T it3;
+  if (INV) { it3.x = -t3.y; it3.y = t3.x; } else { it3.x = t3.y; it3.y = -t3.x; }
+  a0 = tadd(t0, t2);
+  a2 = tsub(t0, t2);
+  a1 = tadd(t1, it3);
+  a3 = tsub(t1, it3);
 }
 
 // COUNT transforms of length 2^LOGN held in LDS at buf + c*STRIDE, done by
 // NT threads in place (every thread keeps its butterflies in registers
 // between the read and the write of a pass).
-template <int LOGN, int COUNT, int STRIDE, int NT, bool INV>
-__device__ __forceinline__ void fft_lds(cplx* buf, const cplx* __restrict__ tw, int tid) {
+template <typename T, int LOGN, int COUNT, int STRIDE, int NT, bool INV>
+__device__ __forceinline__ void fft_lds(T* buf, const T* __restrict__ tw, int tid) {
   constexpr int N = 1 << LOGN;
   if constexpr ((LOGN & 1) != 0) {
     constexpr int NB = COUNT * (N / 2);
     constexpr int K = (NB + NT - 1) / NT;
-    cplx a[K], b[K];
+    T a[K], b[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int bi = tid + k * NT;
@@ -61,8 +68,8 @@ __device__ __forceinline__ void fft_lds(cplx* buf, const cplx* __restrict__ tw, 
       const int bi = tid + k * NT;
       if (bi < NB) {
         const int c = bi / (N / 2), j = bi % (N / 2);
-        buf[c * STRIDE + 2 * j] = cadd(a[k], b[k]);
-        buf[c * STRIDE + 2 * j + 1] = csub(a[k], b[k]);
+        buf[c * STRIDE + 2 * j] = tadd(a[k], b[k]);
+        buf[c * STRIDE + 2 * j + 1] = tsub(a[k], b[k]);
       }
     }
     __syncthreads();
@@ -72,13 +79,13 @@ __device__ __forceinline__ void fft_lds(cplx* buf, const cplx* __restrict__ tw, 
   constexpr int K = (NB + NT - 1) / NT;
 #pragma unroll
   for (int Ns = NS0; Ns < N; Ns *= 4) {
-    cplx v[K][4];
+    T v[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int bi = tid + k * NT;
       if (bi < NB) {
         const int c = bi / (N / 4), j = bi % (N / 4);
-        const cplx* src = buf + c * STRIDE + j;
+        const T* src = buf + c * STRIDE + j;
         v[k][0] = src[0];
         v[k][1] = src[N / 4];
         v[k][2] = src[2 * (N / 4)];
@@ -86,13 +93,13 @@ __device__ __forceinline__ void fft_lds(cplx* buf, const cplx* __restrict__ tw, 
         if (Ns > 1) {
           const int jm = j & (Ns - 1);
           const int st = N / (Ns * 4);
-          cplx w1 = tw[jm * st], w2 = tw[2 * jm * st], w3 = tw[3 * jm * st];
+          T w1 = tw[jm * st], w2 = tw[2 * jm * st], w3 = tw[3 * jm * st];
           if (INV) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
-          v[k][1] = cmul(v[k][1], w1);
-          v[k][2] = cmul(v[k][2], w2);
-          v[k][3] = cmul(v[k][3], w3);
+          v[k][1] = tmul(v[k][1], w1);
+          v[k][2] = tmul(v[k][2], w2);
+          v[k][3] = tmul(v[k][3], w3);
         }
-        radix4<INV>(v[k][0], v[k][1], v[k][2], v[k][3]);
+        radix4<T, INV>(v[k][0], v[k][1], v[k][2], v[k][3]);
       }
     }
     __syncthreads();
@@ -102,7 +109,7 @@ __device__ __forceinline__ void fft_lds(cplx* buf, const cplx* __restrict__ tw, 
       if (bi < NB) {
         const int c = bi / (N / 4), j = bi % (N / 4);
         const int jm = j & (Ns - 1);
-        cplx* dst = buf + c * STRIDE + (j / Ns) * Ns * 4 + jm;
+        T* dst = buf + c * STRIDE + (j / Ns) * Ns * 4 + jm;
         dst[0] = v[k][0];
         dst[Ns] = v[k][1];
         dst[2 * Ns] = v[k][2];
@@ -122,46 +129,54 @@ struct RowCfg {
 };
 
 // Column pass: CPW adjacent columns per workgroup (<= 128 KB of LDS).
-template <int LOGN>
+template <typename T, int LOGN>
 struct ColCfg {
   static constexpr int N = 1 << LOGN;
-  static constexpr int CPW = (8192 / N < kTile) ? 8192 / N : kTile;
+  static constexpr int LIM = (131072 / (int)sizeof(T)) / N;
+  static constexpr int CPW = (LIM < Tile<T>::W) ? LIM : Tile<T>::W;
   static constexpr int NT0 = CPW * N / 4;
   static constexpr int NT = NT0 > 1024 ? 1024 : (NT0 < 64 ? 64 : NT0);
   static constexpr int STRIDE = N + 1;  // pad: adjacent columns in different banks
 };
 
-// K1: X = FFT_rows(pad(m . v)) for rows `row` of the whole batch.
-template <int LOGN>
-__global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_rows_fwd(const cplx* __restrict__ v,
-                                                             const double* __restrict__ m,
-                                                             cplx* __restrict__ X,
-                                                             const cplx* __restrict__ tw, int n,
+template <typename T>
+__device__ __forceinline__ size_t tiled(int b, int n, int N, int j, int kx) {
+  constexpr int W = Tile<T>::W;
+  return (size_t)b * n * N + ((size_t)(kx / W) * n + j) * W + (kx % W);
+}
+
+// K1: X = FFT_rows(pad(m . v)).
+template <typename T, typename R, int LOGN>
+__global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_rows_fwd(const T* __restrict__ v,
+                                                             const R* __restrict__ m,
+                                                             T* __restrict__ X,
+                                                             const T* __restrict__ tw, int n,
                                                              int total_rows) {
   using C = RowCfg<LOGN>;
   constexpr int N = C::N;
-  extern __shared__ cplx buf[];
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   const int row0 = blockIdx.x * C::COUNT;
   for (int e = tid; e < C::COUNT * N; e += C::NT) {
     const int c = e / N, i = e % N;
     const int row = row0 + c;
-    cplx val = cmk(0.0, 0.0);
+    T val = tmk<T>(0, 0);
     if (row < total_rows && i < n) {
       const int j = row % n;
-      val = cscale(v[(size_t)row * n + i], m[(size_t)j * n + i]);
+      const T vv = v[(size_t)row * n + i];
+      const R mm = m[(size_t)j * n + i];
+      val.x = vv.x * mm;
+      val.y = vv.y * mm;
     }
     buf[e] = val;
   }
   __syncthreads();
-  fft_lds<LOGN, C::COUNT, N, C::NT, false>(buf, tw, tid);
+  fft_lds<T, LOGN, C::COUNT, N, C::NT, false>(buf, tw, tid);
   for (int e = tid; e < C::COUNT * N; e += C::NT) {
     const int c = e / N, kx = e % N;
     const int row = row0 + c;
-    if (row < total_rows) {
-      const int b = row / n, j = row % n;
-      X[(size_t)b * n * N + ((size_t)(kx / kTile) * n + j) * kTile + (kx % kTile)] = buf[e];
-    }
+    if (row < total_rows) X[tiled<T>(row / n, n, N, row % n, kx)] = buf[e];
   }
 }
 
@@ -175,75 +190,81 @@ __device__ __forceinline__ int xcd_remap(int id, int total) {
 }
 
 // K2: per column c of X: FFT, multiply by the spectrum, IFFT, keep n.
-template <int LOGN>
-__global__ __launch_bounds__(ColCfg<LOGN>::NT) void k_cols_conv(cplx* __restrict__ X,
-                                                              const cplx* __restrict__ spec,
-                                                              const cplx* __restrict__ tw, int n,
-                                                              int ss, int groups_per_rhs,
-                                                              int total_groups) {
-  using C = ColCfg<LOGN>;
-  constexpr int N = C::N, CPW = C::CPW, S = C::STRIDE;
-  extern __shared__ cplx buf[];
+template <typename T, int LOGN>
+__global__ __launch_bounds__((ColCfg<T, LOGN>::NT)) void k_cols_conv(T* __restrict__ X,
+                                                                 const T* __restrict__ spec,
+                                                                 const T* __restrict__ tw, int n,
+                                                                 int ss, int groups_per_rhs,
+                                                                 int total_groups) {
+  using C = ColCfg<T, LOGN>;
+  constexpr int N = C::N, CPW = C::CPW, S = C::STRIDE, W = Tile<T>::W;
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   const int g = xcd_remap(blockIdx.x, total_groups);
   const int b = g / groups_per_rhs;
   const int c0 = (g % groups_per_rhs) * CPW;
-  cplx* Xb = X + (size_t)b * n * N + (size_t)(c0 / kTile) * n * kTile + (c0 % kTile);
+  T* Xb = X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
   for (int e = tid; e < CPW * n; e += C::NT) {
     const int j = e / CPW, cc = e % CPW;
-    buf[cc * S + j] = Xb[(size_t)j * kTile + cc];
+    buf[cc * S + j] = Xb[(size_t)j * W + cc];
   }
   for (int e = tid; e < CPW * (N - n); e += C::NT) {
     const int cc = e / (N - n), j = n + e % (N - n);
-    buf[cc * S + j] = cmk(0.0, 0.0);
+    buf[cc * S + j] = tmk<T>(0, 0);
   }
   __syncthreads();
-  fft_lds<LOGN, CPW, S, C::NT, false>(buf, tw, tid);
+  fft_lds<T, LOGN, CPW, S, C::NT, false>(buf, tw, tid);
   for (int e = tid; e < CPW * N; e += C::NT) {
     const int cc = e / N, ky = e % N;
     const int kx = c0 + cc;
     const int kxq = kx <= N / 2 ? kx : N - kx;
     const int kyq = ky <= N / 2 ? ky : N - ky;
-    buf[cc * S + ky] = cmul(buf[cc * S + ky], spec[(size_t)kxq * ss + kyq]);
+    buf[cc * S + ky] = tmul(buf[cc * S + ky], spec[(size_t)kxq * ss + kyq]);
   }
   __syncthreads();
-  fft_lds<LOGN, CPW, S, C::NT, true>(buf, tw, tid);
+  fft_lds<T, LOGN, CPW, S, C::NT, true>(buf, tw, tid);
   for (int e = tid; e < CPW * n; e += C::NT) {
     const int j = e / CPW, cc = e % CPW;
-    Xb[(size_t)j * kTile + cc] = buf[cc * S + j];
+    Xb[(size_t)j * W + cc] = buf[cc * S + j];
   }
 }
 
 // K3: y = a v + b * (first n of IFFT_rows(X)).
-template <int LOGN>
-__global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_rows_inv(const cplx* __restrict__ X,
-                                                             const cplx* v, cplx* y,
-                                                             const cplx* __restrict__ tw, int n,
+template <typename T, int LOGN>
+__global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_rows_inv(const T* __restrict__ X,
+                                                             const T* v, T* y,
+                                                             const T* __restrict__ tw, int n,
                                                              int total_rows, double a, double bsc) {
   using C = RowCfg<LOGN>;
   constexpr int N = C::N;
-  extern __shared__ cplx buf[];
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   const int row0 = blockIdx.x * C::COUNT;
   for (int e = tid; e < C::COUNT * N; e += C::NT) {
     const int c = e / N, kx = e % N;
     const int row = row0 + c;
-    cplx val = cmk(0.0, 0.0);
-    if (row < total_rows) {
-      const int b = row / n, j = row % n;
-      val = X[(size_t)b * n * N + ((size_t)(kx / kTile) * n + j) * kTile + (kx % kTile)];
-    }
+    T val = tmk<T>(0, 0);
+    if (row < total_rows) val = X[tiled<T>(row / n, n, N, row % n, kx)];
     buf[e] = val;
   }
   __syncthreads();
-  fft_lds<LOGN, C::COUNT, N, C::NT, true>(buf, tw, tid);
+  fft_lds<T, LOGN, C::COUNT, N, C::NT, true>(buf, tw, tid);
   for (int e = tid; e < C::COUNT * n; e += C::NT) {
     const int c = e / n, i = e % n;
     const int row = row0 + c;
     if (row < total_rows) {
       const size_t idx = (size_t)row * n + i;
-      cplx conv = cscale(buf[c * N + i], bsc);
-      y[idx] = (a != 0.0) ? cadd(cscale(v[idx], a), conv) : conv;
+      T conv = buf[c * N + i];
+      conv.x *= bsc;
+      conv.y *= bsc;
+      if (a != 0.0) {
+        const T vv = v[idx];
+        conv.x = fma((decltype(conv.x))a, vv.x, conv.x);
+        conv.y = fma((decltype(conv.y))a, vv.y, conv.y);
+      }
+      y[idx] = conv;
     }
   }
 }
@@ -254,24 +275,26 @@ __global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_full_rows(cplx* __restrict
                                                               const cplx* __restrict__ tw) {
   using C = RowCfg<LOGN>;
   constexpr int N = C::N;
-  extern __shared__ cplx buf[];
+  extern __shared__ unsigned char lds_raw[];
+  cplx* buf = reinterpret_cast<cplx*>(lds_raw);
   const int tid = threadIdx.x;
   const int row0 = blockIdx.x * C::COUNT;
   for (int e = tid; e < C::COUNT * N; e += C::NT)
     buf[e] = (row0 + e / N < N) ? c[(size_t)row0 * N + e] : cmk(0.0, 0.0);
   __syncthreads();
-  fft_lds<LOGN, C::COUNT, N, C::NT, false>(buf, tw, tid);
+  fft_lds<cplx, LOGN, C::COUNT, N, C::NT, false>(buf, tw, tid);
   for (int e = tid; e < C::COUNT * N; e += C::NT)
     if (row0 + e / N < N) c[(size_t)row0 * N + e] = buf[e];
 }
 
 // Setup: forward FFT of every column, in place.
 template <int LOGN>
-__global__ __launch_bounds__(ColCfg<LOGN>::NT) void k_full_cols(cplx* __restrict__ c,
-                                                              const cplx* __restrict__ tw) {
-  using C = ColCfg<LOGN>;
+__global__ __launch_bounds__((ColCfg<cplx, LOGN>::NT)) void k_full_cols(cplx* __restrict__ c,
+                                                                    const cplx* __restrict__ tw) {
+  using C = ColCfg<cplx, LOGN>;
   constexpr int N = C::N, CPW = C::CPW, S = C::STRIDE;
-  extern __shared__ cplx buf[];
+  extern __shared__ unsigned char lds_raw[];
+  cplx* buf = reinterpret_cast<cplx*>(lds_raw);
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * CPW;
   for (int e = tid; e < CPW * N; e += C::NT) {
@@ -279,20 +302,22 @@ __global__ __launch_bounds__(ColCfg<LOGN>::NT) void k_full_cols(cplx* __restrict
     buf[cc * S + j] = c[(size_t)j * N + c0 + cc];
   }
   __syncthreads();
-  fft_lds<LOGN, CPW, S, C::NT, false>(buf, tw, tid);
+  fft_lds<cplx, LOGN, CPW, S, C::NT, false>(buf, tw, tid);
   for (int e = tid; e < CPW * N; e += C::NT) {
     const int j = e / CPW, cc = e % CPW;
     c[(size_t)j * N + c0 + cc] = buf[cc * S + j];
   }
 }
 
-__global__ void k_extract_quarter(const cplx* __restrict__ c, cplx* __restrict__ spec, int P,
+template <typename T>
+__global__ void k_extract_quarter(const cplx* __restrict__ c, T* __restrict__ spec, int P,
                                   double scale) {
   const int ss = P / 2 + 1;
   const int kx = blockIdx.x * blockDim.x + threadIdx.x;
   const int ky = blockIdx.y;
   if (kx >= ss) return;
-  spec[(size_t)ky * ss + kx] = cscale(c[(size_t)ky * P + kx], scale);
+  const cplx v = c[(size_t)ky * P + kx];
+  spec[(size_t)ky * ss + kx] = tmk<T>(v.x * scale, v.y * scale);
 }
 
 template <typename K>
@@ -302,65 +327,72 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int LOGN>
-ls_status run_apply(ls_plan* p, const cplx* v, cplx* y, int batch, double a, double b) {
-  using R = RowCfg<LOGN>;
-  using C = ColCfg<LOGN>;
+template <typename T, typename R, int LOGN>
+ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, double a, double b) {
+  using RC = RowCfg<LOGN>;
+  using CC = ColCfg<T, LOGN>;
   constexpr int N = 1 << LOGN;
-  const int n = p->n;
+  const int n = av.n;
   const int rows = batch * n;
-  const size_t lds_r = (size_t)R::COUNT * N * sizeof(cplx);
-  const size_t lds_c = (size_t)C::CPW * C::STRIDE * sizeof(cplx);
+  const size_t lds_r = (size_t)RC::COUNT * N * sizeof(T);
+  const size_t lds_c = (size_t)CC::CPW * CC::STRIDE * sizeof(T);
   static bool attr_done = false;
   if (!attr_done) {
-    LS_HIP(set_lds(k_rows_fwd<LOGN>, lds_r));
-    LS_HIP(set_lds(k_rows_inv<LOGN>, lds_r));
-    LS_HIP(set_lds(k_cols_conv<LOGN>, lds_c));
+    LS_HIP(set_lds(k_rows_fwd<T, R, LOGN>, lds_r));
+    LS_HIP(set_lds(k_rows_inv<T, LOGN>, lds_r));
+    LS_HIP(set_lds(k_cols_conv<T, LOGN>, lds_c));
     attr_done = true;
   }
-  k_rows_fwd<LOGN><<<(rows + R::COUNT - 1) / R::COUNT, R::NT, lds_r, p->stream>>>(
-      v, p->m, p->fft_work, p->tw, n, rows);
+  k_rows_fwd<T, R, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
+      v, av.m, av.work, av.tw, n, rows);
   LS_HIP(hipGetLastError());
-  const int gpr = N / C::CPW;
+  const int gpr = N / CC::CPW;
   const int groups = gpr * batch;
-  k_cols_conv<LOGN><<<groups, C::NT, lds_c, p->stream>>>(p->fft_work, p->spec, p->tw, n,
-                                                         p->spec_side, gpr, groups);
+  k_cols_conv<T, LOGN><<<groups, CC::NT, lds_c, av.stream>>>(av.work, av.spec, av.tw, n, av.ss,
+                                                            gpr, groups);
   LS_HIP(hipGetLastError());
-  k_rows_inv<LOGN><<<(rows + R::COUNT - 1) / R::COUNT, R::NT, lds_r, p->stream>>>(
-      p->fft_work, v, y, p->tw, n, rows, a, b);
+  k_rows_inv<T, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
+      av.work, v, y, av.tw, n, rows, a, b);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
 template <int LOGN>
 ls_status run_full_forward(ls_plan* p, cplx* c) {
-  using R = RowCfg<LOGN>;
-  using C = ColCfg<LOGN>;
+  using RC = RowCfg<LOGN>;
+  using CC = ColCfg<cplx, LOGN>;
   constexpr int N = 1 << LOGN;
-  const size_t lds_r = (size_t)R::COUNT * N * sizeof(cplx);
-  const size_t lds_c = (size_t)C::CPW * C::STRIDE * sizeof(cplx);
+  const size_t lds_r = (size_t)RC::COUNT * N * sizeof(cplx);
+  const size_t lds_c = (size_t)CC::CPW * CC::STRIDE * sizeof(cplx);
   LS_HIP(set_lds(k_full_rows<LOGN>, lds_r));
   LS_HIP(set_lds(k_full_cols<LOGN>, lds_c));
-  k_full_rows<LOGN><<<(N + R::COUNT - 1) / R::COUNT, R::NT, lds_r, p->stream>>>(c, p->tw);
+  k_full_rows<LOGN><<<(N + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, p->stream>>>(c, p->tw);
   LS_HIP(hipGetLastError());
-  k_full_cols<LOGN><<<N / C::CPW, C::NT, lds_c, p->stream>>>(c, p->tw);
+  k_full_cols<LOGN><<<N / CC::CPW, CC::NT, lds_c, p->stream>>>(c, p->tw);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
 }  // namespace
 
-ls_status fft_setup_twiddles(ls_plan* p) {
+template <typename T>
+static ls_status twiddles_to(ls_plan* p, T** dst) {
   const int P = p->P;
-  std::vector<cplx> h(P);
+  std::vector<T> h(P);
   const long double twopi = 6.283185307179586476925286766559005768L;
   for (int k = 0; k < P; ++k) {
     const long double ang = -twopi * (long double)k / (long double)P;
-    h[k] = cmk((double)cosl(ang), (double)sinl(ang));
+    h[k] = tmk<T>((double)cosl(ang), (double)sinl(ang));
   }
-  LS_TRY(plan_alloc(p, (void**)&p->tw, sizeof(cplx) * P));
-  LS_HIP(hipMemcpyAsync(p->tw, h.data(), sizeof(cplx) * P, hipMemcpyHostToDevice, p->stream));
+  LS_TRY(plan_alloc(p, (void**)dst, sizeof(T) * P));
+  LS_HIP(hipMemcpyAsync(*dst, h.data(), sizeof(T) * P, hipMemcpyHostToDevice, p->stream));
   LS_HIP(hipStreamSynchronize(p->stream));
+  return LS_OK;
+}
+
+ls_status fft_setup_twiddles(ls_plan* p) {
+  LS_TRY(twiddles_to<cplx>(p, &p->tw));
+  if (p->fp32) LS_TRY(twiddles_to<fcplx>(p, &p->f32.tw));
   return LS_OK;
 }
 
@@ -390,15 +422,26 @@ ls_status spectrum_extract(ls_plan* p, const cplx* c) {
   const int ss = p->P / 2 + 1;
   const double scale = p->omega * p->omega / ((double)p->P * (double)p->P);
   dim3 grid((ss + 255) / 256, ss);
-  k_extract_quarter<<<grid, 256, 0, p->stream>>>(c, p->spec, p->P, scale);
+  k_extract_quarter<cplx><<<grid, 256, 0, p->stream>>>(c, p->spec, p->P, scale);
+  if (p->fp32) k_extract_quarter<fcplx><<<grid, 256, 0, p->stream>>>(c, p->f32.spec, p->P, scale);
   LS_HIP(hipGetLastError());
   return LS_OK;
+}
+
+template <typename T, typename R>
+ls_status apply_H_t(const ApplyView<T, R>& av, int logP, const T* v, T* y, int batch, double a,
+                    double b) {
+#define CALL_APPLY(L) run_apply<T, R, L>(av, v, y, batch, a, b)
+  LS_DISPATCH_LOGP(logP, CALL_APPLY)
+#undef CALL_APPLY
 }
 
 // y = a v + b (omega^2 G (m v)); a = 1, b = 1 gives H v; a = 0, b = -1 gives
 // f = -omega^2 G (m u_I).
 ls_status apply_H(ls_plan* p, const cplx* v, cplx* y, int batch, double a, double b) {
-#define CALL_APPLY(L) run_apply<L>(p, v, y, batch, a, b)
-  LS_DISPATCH_LOGP(p->logP, CALL_APPLY)
-#undef CALL_APPLY
+  return apply_H_t<cplx, double>(view64(p), p->logP, v, y, batch, a, b);
+}
+
+ls_status apply_H32(ls_plan* p, const fcplx* v, fcplx* y, int batch, double a, double b) {
+  return apply_H_t<fcplx, float>(view32(p), p->logP, v, y, batch, a, b);
 }

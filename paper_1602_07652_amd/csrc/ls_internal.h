@@ -13,6 +13,7 @@
 #include "../../include/ls.h"
 
 typedef double2 cplx;
+typedef float2 fcplx;
 
 // ---------------------------------------------------------------- errors
 void ls_set_error(const std::string& msg);
@@ -50,6 +51,36 @@ __host__ __device__ __forceinline__ cplx cfmaconj(cplx a, cplx b, cplx acc) {
   return cmk(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y)));
 }
 
+// Precision-generic complex helpers (C = double2 or float2; arithmetic in
+// the precision of C).
+template <typename C>
+__host__ __device__ __forceinline__ C tmk(double re, double im) {
+  C r;
+  r.x = re;
+  r.y = im;
+  return r;
+}
+template <typename C>
+__host__ __device__ __forceinline__ C tadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C>
+__host__ __device__ __forceinline__ C tsub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C>
+__host__ __device__ __forceinline__ C tmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__host__ __device__ __forceinline__ C tfma(C a, C b, C acc) {  // acc + a*b
+  C r;
+  r.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  r.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+  return r;
+}
+template <typename C>
+__host__ __device__ __forceinline__ C tneg(C a) { C r; r.x = -a.x; r.y = -a.y; return r; }
+
 // ---------------------------------------------------------------- slabs
 // One extended layer in its own frame: long axis index i in [0, n) (x for
 // horizontal layers, z for vertical ones), short axis index r in [0, q)
@@ -74,12 +105,39 @@ struct Slab {
   std::vector<SlabLevel> levels;  // levels[0] .. levels[nlev-1]; last has nl == 1
   cplx* g;           // right-hand side g^l kept across the two sweeps [n][q]
   cplx* w;           // downward-sweep solution w^l [n][q]
+  // FP32 plans: FP32 copies used by the solves (factors computed in FP64)
+  fcplx* coef32;
+  fcplx* fac32;
+  fcplx* g32;
+  fcplx* w32;
 };
 
 // Contiguous set of grid vectors used as a Krylov basis.
-struct KrylovSpace {
-  cplx* base = nullptr;
+template <typename T>
+struct KrylovSpaceT {
+  T* base = nullptr;
   int cap = 0;
+};
+typedef KrylovSpaceT<cplx> KrylovSpace;
+
+// Device state of the FP32 operator (refinement path).
+struct Fp32State {
+  float* m = nullptr;
+  fcplx* spec = nullptr;
+  fcplx* tw = nullptr;
+  fcplx* fft_work = nullptr;
+  fcplx* stencil = nullptr;   // alpha, beta, alphaT, betaT as float2
+};
+
+// Everything the FFT convolution needs, for one precision.
+template <typename T, typename R>
+struct ApplyView {
+  const R* m;
+  const T* spec;
+  const T* tw;
+  T* work;
+  int n, ss;
+  hipStream_t stream;
 };
 
 // ---------------------------------------------------------------- plan
@@ -102,14 +160,30 @@ struct ls_plan {
   cplx* slab_work = nullptr;     // [n][qmax] scratch for one slab solve
   cplx* slab_work2 = nullptr;    // second scratch
   cplx* vtmp = nullptr;          // grid vectors for Alg. 2 [3][n*n]
+  fcplx* slab_work32 = nullptr;  // FP32 plans: the two slab scratch vectors
+  fcplx* slab_work32b = nullptr;
+  fcplx* vtmp32 = nullptr;       // FP32 plans: grid vectors [3][n*n]
 
   // Krylov workspace (grid vectors), grown on demand
   KrylovSpace innerV, innerZ, outerV, outerZ;
   cplx* inner_rhs = nullptr;     // A r of the inner level
+  KrylovSpaceT<fcplx> innerV32, innerZ32, outerV32, outerZ32;
+  fcplx* inner_rhs32 = nullptr;
   cplx* red = nullptr;           // reduction partials
   cplx* dotbuf = nullptr;        // device results of multi-dots
   std::vector<void*> allocs;     // every device allocation, freed at destroy
+
+  bool fp32 = false;             // FP32 operator + FP64 refinement
+  Fp32State f32;
 };
+
+inline ApplyView<cplx, double> view64(ls_plan* p) {
+  return ApplyView<cplx, double>{p->m, p->spec, p->tw, p->fft_work, p->n, p->spec_side, p->stream};
+}
+inline ApplyView<fcplx, float> view32(ls_plan* p) {
+  return ApplyView<fcplx, float>{p->f32.m, p->f32.spec, p->f32.tw, p->f32.fft_work, p->n,
+                                 p->spec_side, p->stream};
+}
 
 // device memory helpers (record in plan->allocs)
 ls_status plan_alloc(ls_plan* p, void** ptr, size_t bytes);
@@ -123,22 +197,49 @@ ls_status fft_setup_twiddles(ls_plan* p);
 ls_status fft2_full_forward(ls_plan* p, cplx* c);                // in place, P x P row-major
 ls_status spectrum_extract(ls_plan* p, const cplx* c);           // -> p->spec
 ls_status apply_H(ls_plan* p, const cplx* v, cplx* y, int batch, double sign_identity, double scale_conv);
+ls_status apply_H32(ls_plan* p, const fcplx* v, fcplx* y, int batch, double sign_identity, double scale_conv);
 // stencil.hip
 ls_status stencils_build(ls_plan* p, const cplx* circ);
 ls_status stencil_apply_A(ls_plan* p, const cplx* r, cplx* y, int batch);
 ls_status stencil_apply_C(ls_plan* p, const cplx* v, cplx* y, int batch);
-ls_status stencil_residual_C(ls_plan* p, const cplx* g, const cplx* u, cplx* e);  // e = g - C u
+ls_status stencil_residual_C(ls_plan* p, const cplx* g, const cplx* u, cplx* e, int batch = 1);  // e = g - C u
+ls_status stencil_apply_A(ls_plan* p, const fcplx* r, fcplx* y, int batch);
+ls_status stencil_apply_C(ls_plan* p, const fcplx* v, fcplx* y, int batch);
+ls_status stencil_residual_C(ls_plan* p, const fcplx* g, const fcplx* u, fcplx* e, int batch = 1);
+ls_status stencils_to_f32(ls_plan* p);
 // slab.hip
 ls_status slabs_build(ls_plan* p);
 ls_status slab_solve_frame(ls_plan* p, Slab& s, cplx* x);        // in place on x [n][q]
-ls_status sweep_apply(ls_plan* p, int orient, const cplx* g, cplx* v, bool accumulate);
-ls_status bidirectional_apply(ls_plan* p, const cplx* g, cplx* v);
-// blas.hip
-ls_status vec_multidot(ls_plan* p, const cplx* V, int k, size_t stride, const cplx* w, size_t N, cplx* out_host);
-ls_status vec_multiaxpy(ls_plan* p, cplx* w, const cplx* V, int k, size_t stride, const cplx* coef_host, size_t N);
-ls_status vec_norm(ls_plan* p, const cplx* w, size_t N, double* out_host);
-ls_status vec_scale_copy(ls_plan* p, cplx* y, const cplx* x, double s, size_t N);
-ls_status vec_lincomb(ls_plan* p, cplx* x, const cplx* Z, int k, size_t stride, const cplx* coef_host, size_t N);
-ls_status vec_axpy(ls_plan* p, cplx* y, const cplx* x, cplx a, size_t N);  // y += a x
-ls_status vec_zero(ls_plan* p, cplx* y, size_t N);
-ls_status vec_copy(ls_plan* p, cplx* y, const cplx* x, size_t N);
+ls_status slab_solve_frame(ls_plan* p, Slab& s, fcplx* x);
+ls_status slab_solve_batch(ls_plan* p, Slab& s, cplx* x, int B);  // x [B][n][q]
+ls_status slab_solve_batch(ls_plan* p, Slab& s, fcplx* x, int B);
+// B right-hand sides [B][n][n] at once
+ls_status sweep_apply(ls_plan* p, int orient, const cplx* g, cplx* v, bool accumulate, int B = 1);
+ls_status sweep_apply(ls_plan* p, int orient, const fcplx* g, fcplx* v, bool accumulate, int B = 1);
+ls_status bidirectional_apply(ls_plan* p, const cplx* g, cplx* v, int B = 1);
+ls_status bidirectional_apply(ls_plan* p, const fcplx* g, fcplx* v, int B = 1);
+// blas.hip (each for T = cplx and T = fcplx; inner products in FP64)
+// Batched forms act on B right-hand sides stored [B][N] (vector i of a
+// Krylov set at V + i*stride, stride >= B*N); coefficient arrays are [B][k].
+#define LS_BLAS_DECLS(T)                                                                           \
+  ls_status vec_multidot(ls_plan* p, const T* V, int k, size_t stride, const T* w, size_t N,      \
+                         int B, cplx* out_host);                                                   \
+  ls_status vec_multiaxpy(ls_plan* p, T* w, const T* V, int k, size_t stride,                     \
+                          const cplx* coef_host, size_t N, int B);                                 \
+  ls_status vec_lincomb(ls_plan* p, T* x, const T* Z, int k, size_t stride,                       \
+                        const cplx* coef_host, size_t N, int B);                                   \
+  ls_status vec_norms(ls_plan* p, const T* w, size_t N, int B, double* out_host);                 \
+  ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host);                         \
+  ls_status vec_scale_b(ls_plan* p, T* y, const T* x, const double* s_host, size_t N, int B);     \
+  ls_status vec_scale_copy(ls_plan* p, T* y, const T* x, double s, size_t N);                     \
+  ls_status vec_axpy(ls_plan* p, T* y, const T* x, cplx a, size_t N);                            \
+  ls_status vec_zero(ls_plan* p, T* y, size_t N);                                                 \
+  ls_status vec_copy(ls_plan* p, T* y, const T* x, size_t N);
+LS_BLAS_DECLS(cplx)
+LS_BLAS_DECLS(fcplx)
+ls_status vec_to_f32(ls_plan* p, fcplx* y, const cplx* x, double s, size_t N);          // y = s x
+ls_status vec_to_f32_b(ls_plan* p, fcplx* y, const cplx* x, const double* s_host, size_t N, int B);
+ls_status vec_from_f32_b(ls_plan* p, cplx* y, const cplx* y0, const fcplx* x, const double* s_host,
+                         size_t N, int B);
+ls_status vec_from_f32(ls_plan* p, cplx* y, const cplx* y0, const fcplx* x, double s,  // y = y0 + s x
+                       size_t N);

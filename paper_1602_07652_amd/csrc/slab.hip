@@ -41,7 +41,6 @@
 namespace {
 
 constexpr int kMaxQ = 96;
-constexpr int kSolveThreads = 256;
 
 __device__ __forceinline__ int axis_type(int i, int n) { return i == 0 ? 0 : (i == n - 1 ? 2 : 1); }
 
@@ -238,212 +237,390 @@ __global__ __launch_bounds__(256) void k_gemm(const cplx* const* __restrict__ Ap
 }
 
 // ------------------------------------------------------------ solve kernels
-struct GemvLane {
-  int r, c0, c1, cs, CS;
+// Every level step is y = sum_t M_t x_t over up to three q x q column-major
+// matrices of one block (x_t staged in LDS).  The t*q "virtual columns" are
+// split evenly over the waves of the workgroup (rows over lanes), each lane
+// streams its slice of matrix columns with 8 independent loads in flight,
+// and the column splits are summed through LDS.  Levels with few blocks run
+// 1024-thread workgroups so that one block is read by 16 waves.
+template <typename C, int NT>
+struct GemvCtx {
+  int r, s, CS, v0, v1;
+  // virtual columns [base, base + len) of this workgroup
+  __device__ __forceinline__ GemvCtx(int q, int base, int len, int tid) {
+    const int RH = (q + 63) / 64;
+    CS = (NT / 64) / RH;
+    const int w = tid >> 6, lane = tid & 63;
+    r = (w % RH) * 64 + lane;
+    s = w / RH;
+    const int chunk = (len + CS - 1) / CS;
+    v0 = base + min(len, s * chunk);
+    v1 = base + min(len, s * chunk + chunk);
+  }
+  __device__ __forceinline__ GemvCtx(int q, int terms, int tid) : GemvCtx(q, 0, terms * q, tid) {}
 };
 
-__device__ __forceinline__ GemvLane gemv_lane(int q, int tid) {
-  GemvLane g;
-  const int RH = (q + 63) / 64;
-  g.CS = 4 / RH;
-  const int w = tid >> 6, lane = tid & 63;
-  const int rh = w % RH;
-  g.cs = w / RH;
-  g.r = rh * 64 + lane;
-  const int chunk = (q + g.CS - 1) / g.CS;
-  g.c0 = g.cs * chunk;
-  g.c1 = min(q, g.c0 + chunk);
-  return g;
-}
-
-// acc += M(r, c0:c1) * x(c0:c1), M column-major q x q.
-__device__ __forceinline__ cplx gemv_part(const cplx* __restrict__ M, const cplx* x, int q,
-                                          const GemvLane& g, cplx acc) {
-  if (g.r < q) {
-    const cplx* col = M + g.r;
-#pragma unroll 8
-    for (int c = g.c0; c < g.c1; ++c) acc = cfma(col[(size_t)c * q], x[c], acc);
+template <typename C, int NT>
+__device__ __forceinline__ C gemv_terms(const GemvCtx<C, NT>& g, const C* const* M, const C* xs,
+                                        int q, C acc) {
+  if (g.r >= q || g.v0 >= g.v1) return acc;
+  int t = g.v0 / q, c = g.v0 % q;
+  int vc = g.v0;
+  for (; vc + 8 <= g.v1; vc += 8) {
+    C mv[8], xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      mv[u] = M[t][(size_t)c * q + g.r];
+      xv[u] = xs[t * kMaxQ + c];
+      if (++c == q) { c = 0; ++t; }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = tfma(mv[u], xv[u], acc);
+  }
+  for (; vc < g.v1; ++vc) {
+    acc = tfma(M[t][(size_t)c * q + g.r], xs[t * kMaxQ + c], acc);
+    if (++c == q) { c = 0; ++t; }
   }
   return acc;
 }
 
-// Sum the column splits; returns the result for row tid (valid if tid < q).
-__device__ __forceinline__ cplx gemv_reduce(cplx acc, const GemvLane& g, cplx* part, int q) {
-  if (g.r < q) part[g.cs * 128 + g.r] = acc;
+// Sum of the column splits; the result is valid in threads tid < q.
+template <typename C, int NT>
+__device__ __forceinline__ C gemv_sum(const GemvCtx<C, NT>& g, C acc, C* part, int q) {
+  if (g.r < q) part[g.s * 128 + g.r] = acc;
   __syncthreads();
-  cplx y = cmk(0, 0);
-  if (threadIdx.x < q)
-    for (int s = 0; s < g.CS; ++s) y = cadd(y, part[s * 128 + threadIdx.x]);
+  C y = tmk<C>(0, 0);
+  if ((int)threadIdx.x < q)
+    for (int s = 0; s < g.CS; ++s) y = tadd(y, part[s * 128 + threadIdx.x]);
   return y;
 }
 
-__global__ __launch_bounds__(kSolveThreads) void k_fwd0_odd(cplx* __restrict__ x,
-                                                            const cplx* __restrict__ dinv, int q) {
-  __shared__ cplx xs[kMaxQ];
-  __shared__ cplx part[4 * 128];
-  const int k = 2 * blockIdx.x + 1;
+// One level step of blocks k (even: forward, odd: backward, or the single
+// last block): one workgroup per block; NT = 1024 for levels with few
+// blocks so that the block's matrices are streamed by 16 waves.  (Spreading
+// one block over several workgroups needs a device-scope fence per
+// workgroup to publish partial sums, which costs more than it saves here.)
+enum { STEP_FWD = 0, STEP_BWD = 1, STEP_LAST = 2 };
+
+template <typename C, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_step(C* __restrict__ x, const C* __restrict__ m0,
+                                             const C* __restrict__ m1, const C* __restrict__ m2,
+                                             int q, int nl, int shift) {
+  __shared__ C xs[3 * kMaxQ];
+  __shared__ C part[(NT / 64) * 128];
+  const int blk = blockIdx.x;
   const size_t qq = (size_t)q * q;
-  if (threadIdx.x < q) xs[threadIdx.x] = x[(size_t)k * q + threadIdx.x];
+  const int tid = threadIdx.x;
+  int k, T = 0;
+  const C* M[3];
+  if (MODE == STEP_FWD) {
+    k = 2 * blk;
+    const bool hm = k >= 1, hp = k + 1 < nl;
+    if (tid < q) {
+      int t = 0;
+      if (hm) xs[(t++) * kMaxQ + tid] = x[((size_t)(k - 1) << shift) * q + tid];
+      if (hp) xs[t * kMaxQ + tid] = x[((size_t)(k + 1) << shift) * q + tid];
+    }
+    if (hm) M[T++] = m0 + blk * qq;
+    if (hp) M[T++] = m1 + blk * qq;
+  } else if (MODE == STEP_BWD) {
+    k = 2 * blk + 1;
+    const bool hp = k + 1 < nl;
+    if (tid < q) {
+      xs[tid] = x[((size_t)k << shift) * q + tid];
+      xs[kMaxQ + tid] = tneg(x[((size_t)(k - 1) << shift) * q + tid]);
+      if (hp) xs[2 * kMaxQ + tid] = tneg(x[((size_t)(k + 1) << shift) * q + tid]);
+    }
+    M[0] = m0 + blk * qq;
+    M[1] = m1 + blk * qq;
+    M[2] = m2 + blk * qq;
+    T = hp ? 3 : 2;
+  } else {
+    k = 0;
+    if (tid < q) xs[tid] = x[tid];
+    M[0] = m0;
+    T = 1;
+  }
   __syncthreads();
-  const GemvLane g = gemv_lane(q, threadIdx.x);
-  cplx acc = gemv_part(dinv + blockIdx.x * qq, xs, q, g, cmk(0, 0));
-  const cplx y = gemv_reduce(acc, g, part, q);
-  if (threadIdx.x < q) x[(size_t)k * q + threadIdx.x] = y;
+  const GemvCtx<C, NT> g(q, T, tid);
+  const C y = gemv_sum(g, gemv_terms(g, M, xs, q, tmk<C>(0, 0)), part, q);
+  const size_t o = ((size_t)k << shift) * q + tid;
+  if (tid < q) {
+    if (MODE == STEP_FWD)
+      x[o] = tsub(x[o], y);
+    else
+      x[o] = y;
+  }
 }
 
-__global__ void k_fwd0_even(cplx* __restrict__ x, const cplx* __restrict__ coef, int n, int q) {
+// ---------------------------------------------------------------- batched
+// The same level steps for B right-hand sides x[b][n][q] (stride xs_b):
+// a workgroup takes one block (or one slice of its virtual columns, S per
+// block) and a tile of up to BT right-hand sides, stages the tile's input
+// vectors in LDS, and streams each matrix column once for the whole tile
+// (y(r, b) += M(r, c) x(c, b)): the factors are read once per tile instead
+// of once per right-hand side.  Threads: row r = tid % 128, right-hand sides
+// b = tid / 128, tid / 128 + 2, ...
+enum { BSTEP_FWD = 0, BSTEP_BWD = 1, BSTEP_LAST = 2, BSTEP_ODD0 = 3, BSTEP_BWD0 = 4 };
+// right-hand sides per tile: 8 (FP64) or 16 (FP32), i.e. 128 bytes per row
+template <typename C>
+struct BTile {
+  static constexpr int V = 128 / (int)sizeof(C);
+};
+
+template <typename C, int MODE>
+__global__ __launch_bounds__(256) void k_bstep(C* __restrict__ x, size_t xs_b, int B,
+                                               const C* __restrict__ m0, const C* __restrict__ m1,
+                                               const C* __restrict__ m2,
+                                               const C* __restrict__ coef, int n, int q, int nl,
+                                               int shift) {
+  constexpr int kBT = BTile<C>::V;
+  __shared__ C xs[3][kMaxQ][kBT];
+  const int blk = blockIdx.x;
+  const int b0 = blockIdx.y * kBT;
+  const int nbt = min(kBT, B - b0);
+  const size_t qq = (size_t)q * q;
+  const int tid = threadIdx.x;
+  int k = 0, T = 0;
+  const C* M[3];
+  // stage inputs
+  for (int e = tid; e < q * nbt; e += 256) {
+    const int r = e % q, bb = e / q;
+    C* xb = x + (size_t)(b0 + bb) * xs_b;
+    if (MODE == BSTEP_FWD) {
+      const int kk = 2 * blk;
+      int t = 0;
+      if (kk >= 1) xs[t++][r][bb] = xb[((size_t)(kk - 1) << shift) * q + r];
+      if (kk + 1 < nl) xs[t][r][bb] = xb[((size_t)(kk + 1) << shift) * q + r];
+    } else if (MODE == BSTEP_BWD) {
+      const int kk = 2 * blk + 1;
+      xs[0][r][bb] = xb[((size_t)kk << shift) * q + r];
+      xs[1][r][bb] = tneg(xb[((size_t)(kk - 1) << shift) * q + r]);
+      if (kk + 1 < nl) xs[2][r][bb] = tneg(xb[((size_t)(kk + 1) << shift) * q + r]);
+    } else if (MODE == BSTEP_LAST) {
+      xs[0][r][bb] = xb[r];
+    } else if (MODE == BSTEP_ODD0) {
+      xs[0][r][bb] = xb[(size_t)(2 * blk + 1) * q + r];
+    } else {  // BWD0: t = L_k x_{k-1} + U_k x_{k+1}
+      const int kk = 2 * blk + 1;
+      const C* cf = coef + ((size_t)kk * q + r) * 9;
+      C acc = tmk<C>(0, 0);
+      for (int dZ = -1; dZ <= 1; ++dZ) {
+        const int rr = r + dZ;
+        if (rr < 0 || rr >= q) continue;
+        acc = tfma(cf[(dZ + 1) * 3 + 0], xb[(size_t)(kk - 1) * q + rr], acc);
+        if (kk + 1 < n) acc = tfma(cf[(dZ + 1) * 3 + 2], xb[(size_t)(kk + 1) * q + rr], acc);
+      }
+      xs[0][r][bb] = acc;
+    }
+  }
+  if (MODE == BSTEP_FWD) {
+    k = 2 * blk;
+    if (k >= 1) M[T++] = m0 + blk * qq;
+    if (k + 1 < nl) M[T++] = m1 + blk * qq;
+  } else if (MODE == BSTEP_BWD) {
+    k = 2 * blk + 1;
+    M[0] = m0 + blk * qq;
+    M[1] = m1 + blk * qq;
+    M[2] = m2 + blk * qq;
+    T = (k + 1 < nl) ? 3 : 2;
+  } else if (MODE == BSTEP_LAST) {
+    k = 0;
+    M[0] = m0;
+    T = 1;
+  } else {
+    k = 2 * blk + 1;
+    M[0] = m0 + blk * qq;
+    T = 1;
+  }
+  __syncthreads();
+  const int v0 = 0, v1 = T * q;
+  const int r = tid & 127, bh = tid >> 7;
+  C acc[kBT / 2];
+#pragma unroll
+  for (int j = 0; j < kBT / 2; ++j) acc[j] = tmk<C>(0, 0);
+  if (r < q) {
+    int t = v0 / q, c = v0 % q;
+#pragma unroll 4
+    for (int vc = v0; vc < v1; ++vc) {
+      const C mv = M[t][(size_t)c * q + r];
+#pragma unroll
+      for (int j = 0; j < kBT / 2; ++j) {
+        const int bb = bh + 2 * j;
+        if (bb < nbt) acc[j] = tfma(mv, xs[t][c][bb], acc[j]);
+      }
+      if (++c == q) { c = 0; ++t; }
+    }
+  }
+  const size_t okq = ((MODE == BSTEP_FWD || MODE == BSTEP_BWD) ? ((size_t)k << shift) : (size_t)k) * q;
+  if (r < q)
+#pragma unroll
+    for (int j = 0; j < kBT / 2; ++j) {
+      const int bb = bh + 2 * j;
+      if (bb >= nbt) continue;
+      C* o = x + (size_t)(b0 + bb) * xs_b + okq + r;
+      if (MODE == BSTEP_FWD || MODE == BSTEP_BWD0)
+        *o = tsub(*o, acc[j]);
+      else
+        *o = acc[j];
+    }
+}
+
+template <typename C>
+__global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restrict__ coef, int n,
+                              int q) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 2 * blockIdx.y;
   if (r >= q) return;
-  const cplx* cf = coef + ((size_t)k * q + r) * 9;
-  cplx acc = x[(size_t)k * q + r];
+  C* xb = x + (size_t)blockIdx.z * xs_b;
+  const C* cf = coef + ((size_t)k * q + r) * 9;
+  C acc = xb[(size_t)k * q + r];
   for (int dZ = -1; dZ <= 1; ++dZ) {
     const int rr = r + dZ;
     if (rr < 0 || rr >= q) continue;
-    if (k >= 1) acc = csub(acc, cmul(cf[(dZ + 1) * 3 + 0], x[(size_t)(k - 1) * q + rr]));
-    if (k + 1 < n) acc = csub(acc, cmul(cf[(dZ + 1) * 3 + 2], x[(size_t)(k + 1) * q + rr]));
+    if (k >= 1) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 0], xb[(size_t)(k - 1) * q + rr]));
+    if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr]));
+  }
+  xb[(size_t)k * q + r] = acc;
+}
+
+// level 0, odd blocks: z_k = Dinv_k b_k (in place)
+template <typename C, int NT>
+__global__ __launch_bounds__(NT) void k_fwd0_odd(C* __restrict__ x, const C* __restrict__ dinv, int q) {
+  __shared__ C xs[kMaxQ];
+  __shared__ C part[(NT / 64) * 128];
+  const int k = 2 * blockIdx.x + 1;
+  if ((int)threadIdx.x < q) xs[threadIdx.x] = x[(size_t)k * q + threadIdx.x];
+  __syncthreads();
+  const GemvCtx<C, NT> g(q, 1, threadIdx.x);
+  const C* M[1] = {dinv + blockIdx.x * (size_t)q * q};
+  const C y = gemv_sum(g, gemv_terms(g, M, xs, q, tmk<C>(0, 0)), part, q);
+  if ((int)threadIdx.x < q) x[(size_t)k * q + threadIdx.x] = y;
+}
+
+// level 0, even blocks: b_k -= L_k z_{k-1} + U_k z_{k+1} (L, U from coef)
+template <typename C>
+__global__ void k_fwd0_even(C* __restrict__ x, const C* __restrict__ coef, int n, int q) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = 2 * blockIdx.y;
+  if (r >= q) return;
+  const C* cf = coef + ((size_t)k * q + r) * 9;
+  C acc = x[(size_t)k * q + r];
+  for (int dZ = -1; dZ <= 1; ++dZ) {
+    const int rr = r + dZ;
+    if (rr < 0 || rr >= q) continue;
+    if (k >= 1) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 0], x[(size_t)(k - 1) * q + rr]));
+    if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], x[(size_t)(k + 1) * q + rr]));
   }
   x[(size_t)k * q + r] = acc;
 }
 
-__global__ __launch_bounds__(kSolveThreads) void k_fwd(cplx* __restrict__ x,
-                                                       const cplx* __restrict__ pm,
-                                                       const cplx* __restrict__ pp, int q, int nl,
-                                                       int shift) {
-  __shared__ cplx xm[kMaxQ], xp[kMaxQ];
-  __shared__ cplx part[4 * 128];
-  const int k = 2 * blockIdx.x;
-  const size_t qq = (size_t)q * q;
-  const bool hm = k >= 1, hp = k + 1 < nl;
-  if (threadIdx.x < q) {
-    xm[threadIdx.x] = hm ? x[((size_t)(k - 1) << shift) * q + threadIdx.x] : cmk(0, 0);
-    xp[threadIdx.x] = hp ? x[((size_t)(k + 1) << shift) * q + threadIdx.x] : cmk(0, 0);
-  }
-  __syncthreads();
-  const GemvLane g = gemv_lane(q, threadIdx.x);
-  cplx acc = cmk(0, 0);
-  if (hm) acc = gemv_part(pm + blockIdx.x * qq, xm, q, g, acc);
-  if (hp) acc = gemv_part(pp + blockIdx.x * qq, xp, q, g, acc);
-  const cplx y = gemv_reduce(acc, g, part, q);
-  if (threadIdx.x < q) {
-    const size_t o = ((size_t)k << shift) * q + threadIdx.x;
-    x[o] = csub(x[o], y);
-  }
-}
-
-__global__ __launch_bounds__(kSolveThreads) void k_last(cplx* __restrict__ x,
-                                                        const cplx* __restrict__ dinv, int q) {
-  __shared__ cplx xs[kMaxQ];
-  __shared__ cplx part[4 * 128];
-  if (threadIdx.x < q) xs[threadIdx.x] = x[threadIdx.x];
-  __syncthreads();
-  const GemvLane g = gemv_lane(q, threadIdx.x);
-  const cplx y = gemv_reduce(gemv_part(dinv, xs, q, g, cmk(0, 0)), g, part, q);
-  if (threadIdx.x < q) x[threadIdx.x] = y;
-}
-
-__global__ __launch_bounds__(kSolveThreads) void k_bwd(cplx* __restrict__ x,
-                                                       const cplx* __restrict__ dinv,
-                                                       const cplx* __restrict__ dinvl,
-                                                       const cplx* __restrict__ dinvu, int q,
-                                                       int nl, int shift) {
-  __shared__ cplx xb[kMaxQ], xm[kMaxQ], xp[kMaxQ];
-  __shared__ cplx part[4 * 128];
+// level 0, odd blocks: x_k = z_k - Dinv_k (L_k x_{k-1} + U_k x_{k+1})
+template <typename C, int NT>
+__global__ __launch_bounds__(NT) void k_bwd0(C* __restrict__ x, const C* __restrict__ dinv,
+                                             const C* __restrict__ coef, int n, int q) {
+  __shared__ C t[kMaxQ];
+  __shared__ C part[(NT / 64) * 128];
   const int k = 2 * blockIdx.x + 1;
-  const size_t qq = (size_t)q * q;
-  const bool hp = k + 1 < nl;
-  if (threadIdx.x < q) {
-    xb[threadIdx.x] = x[((size_t)k << shift) * q + threadIdx.x];
-    const cplx a = x[((size_t)(k - 1) << shift) * q + threadIdx.x];
-    xm[threadIdx.x] = cmk(-a.x, -a.y);
-    if (hp) {
-      const cplx c = x[((size_t)(k + 1) << shift) * q + threadIdx.x];
-      xp[threadIdx.x] = cmk(-c.x, -c.y);
-    }
-  }
-  __syncthreads();
-  const GemvLane g = gemv_lane(q, threadIdx.x);
-  cplx acc = gemv_part(dinv + blockIdx.x * qq, xb, q, g, cmk(0, 0));
-  acc = gemv_part(dinvl + blockIdx.x * qq, xm, q, g, acc);
-  if (hp) acc = gemv_part(dinvu + blockIdx.x * qq, xp, q, g, acc);
-  const cplx y = gemv_reduce(acc, g, part, q);
-  if (threadIdx.x < q) x[((size_t)k << shift) * q + threadIdx.x] = y;
-}
-
-__global__ __launch_bounds__(kSolveThreads) void k_bwd0(cplx* __restrict__ x,
-                                                        const cplx* __restrict__ dinv,
-                                                        const cplx* __restrict__ coef, int n,
-                                                        int q) {
-  __shared__ cplx t[kMaxQ];
-  __shared__ cplx part[4 * 128];
-  const int k = 2 * blockIdx.x + 1;
-  const size_t qq = (size_t)q * q;
   const int r = threadIdx.x;
   if (r < q) {
-    const cplx* cf = coef + ((size_t)k * q + r) * 9;
-    cplx acc = cmk(0, 0);
+    const C* cf = coef + ((size_t)k * q + r) * 9;
+    C acc = tmk<C>(0, 0);
     for (int dZ = -1; dZ <= 1; ++dZ) {
       const int rr = r + dZ;
       if (rr < 0 || rr >= q) continue;
-      acc = cfma(cf[(dZ + 1) * 3 + 0], x[(size_t)(k - 1) * q + rr], acc);
-      if (k + 1 < n) acc = cfma(cf[(dZ + 1) * 3 + 2], x[(size_t)(k + 1) * q + rr], acc);
+      acc = tfma(cf[(dZ + 1) * 3 + 0], x[(size_t)(k - 1) * q + rr], acc);
+      if (k + 1 < n) acc = tfma(cf[(dZ + 1) * 3 + 2], x[(size_t)(k + 1) * q + rr], acc);
     }
     t[r] = acc;
   }
   __syncthreads();
-  const GemvLane g = gemv_lane(q, threadIdx.x);
-  const cplx y = gemv_reduce(gemv_part(dinv + blockIdx.x * qq, t, q, g, cmk(0, 0)), g, part, q);
-  if (threadIdx.x < q) {
+  const GemvCtx<C, NT> g(q, 1, threadIdx.x);
+  const C* M[1] = {dinv + blockIdx.x * (size_t)q * q};
+  const C y = gemv_sum(g, gemv_terms(g, M, t, q, tmk<C>(0, 0)), part, q);
+  if ((int)threadIdx.x < q) {
     const size_t o = (size_t)k * q + threadIdx.x;
-    x[o] = csub(x[o], y);
+    x[o] = tsub(x[o], y);
   }
 }
 
 // ------------------------------------------------------- sweep helpers
 // dst[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere.
-__global__ void k_gather(const cplx* __restrict__ g, cplx* __restrict__ dst, int n, int q, int z0,
+template <typename T>
+__global__ void k_gather(const T* __restrict__ g, T* __restrict__ dst, int n, int q, int z0,
                          int a, int b, int orient) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * q) return;
+  g += (size_t)blockIdx.y * n * n;
+  dst += (size_t)blockIdx.y * n * q;
   int i, r;
   if (orient == 0) { r = t / n; i = t % n; } else { i = t / q; r = t % q; }
   const int Z = z0 + r;
-  cplx v = cmk(0, 0);
+  T v = tmk<T>(0, 0);
   if (Z >= a && Z <= b) v = (orient == 0) ? g[(size_t)Z * n + i] : g[(size_t)i * n + Z];
   dst[(size_t)i * q + r] = v;
 }
 
 // out(i, Z) (+)= src[i][Z - z0] for Z in [a, b].
-__global__ void k_scatter(const cplx* __restrict__ src, cplx* __restrict__ out, int n, int q,
-                          int z0, int a, int b, int orient, int accumulate) {
+template <typename T>
+__global__ void k_scatter(const T* __restrict__ src, T* __restrict__ out, int n, int q, int z0,
+                          int a, int b, int orient, int accumulate) {
   const int rows = b - a + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * rows) return;
+  src += (size_t)blockIdx.y * n * q;
+  out += (size_t)blockIdx.y * n * n;
   int i, Z;
   if (orient == 0) { Z = a + t / n; i = t % n; } else { i = t / rows; Z = a + t % rows; }
-  const cplx v = src[(size_t)i * q + (Z - z0)];
+  const T v = src[(size_t)i * q + (Z - z0)];
   const size_t o = (orient == 0) ? (size_t)Z * n + i : (size_t)i * n + Z;
-  out[o] = accumulate ? cadd(out[o], v) : v;
+  out[o] = accumulate ? tadd(out[o], v) : v;
 }
 
-// GRF source: rhs[i][rt] += sgn * sum_dX coef[i][rt][(dZ+1)*3 + dX+1] *
-// (s1[(i+dX)*q1 + r1] + s2[(i+dX)*q2 + r2]).
-__global__ void k_inject(cplx* __restrict__ rhs, const cplx* __restrict__ coef, int n, int q,
-                         int rt, int dZ, double sgn, const cplx* __restrict__ s1, int q1, int r1,
-                         const cplx* __restrict__ s2, int q2, int r2) {
+// GRF sources on two lines of one slab (eq. pde_GRF_real):
+// rhs[i][rt_j] += sgn_j * sum_dX coef[i][rt_j][(dZ_j+1)*3 + dX+1] * src_j(i+dX),
+// src_j(i) = s1_j[i*q1_j + r1_j] (+ s2[i*q2 + r2] for the second line).
+template <typename T>
+__global__ void k_inject2(T* __restrict__ rhs, const T* __restrict__ coef, int n, int q,
+                          int rtA, int dZA, double sgnA, const T* __restrict__ sA, int qA, int rA,
+                          int rtB, int dZB, double sgnB, const T* __restrict__ sB, int qB, int rB,
+                          const T* __restrict__ s2, int q2, int r2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const cplx* cf = coef + ((size_t)i * q + rt) * 9 + (dZ + 1) * 3;
-  cplx acc = cmk(0, 0);
-  for (int dX = -1; dX <= 1; ++dX) {
-    const int ii = i + dX;
-    if (ii < 0 || ii >= n) continue;
-    cplx s = s1[(size_t)ii * q1 + r1];
-    if (s2) s = cadd(s, s2[(size_t)ii * q2 + r2]);
-    acc = cfma(cf[dX + 1], s, acc);
+  // right-hand side blockIdx.y: every slab array has stride n * (its q)
+  rhs += (size_t)blockIdx.y * n * q;
+  sA += (size_t)blockIdx.y * n * qA;
+  sB += (size_t)blockIdx.y * n * qB;
+  if (s2) s2 += (size_t)blockIdx.y * n * q2;
+  {
+    const T* cf = coef + ((size_t)i * q + rtA) * 9 + (dZA + 1) * 3;
+    T acc = tmk<T>(0, 0);
+    for (int dX = -1; dX <= 1; ++dX) {
+      const int ii = i + dX;
+      if (ii < 0 || ii >= n) continue;
+      acc = tfma(cf[dX + 1], sA[(size_t)ii * qA + rA], acc);
+    }
+    T* o = rhs + (size_t)i * q + rtA;
+    *o = tadd(*o, tmk<T>(acc.x * sgnA, acc.y * sgnA));
   }
-  cplx* o = rhs + (size_t)i * q + rt;
-  *o = cadd(*o, cscale(acc, sgn));
+  {
+    const T* cf = coef + ((size_t)i * q + rtB) * 9 + (dZB + 1) * 3;
+    T acc = tmk<T>(0, 0);
+    for (int dX = -1; dX <= 1; ++dX) {
+      const int ii = i + dX;
+      if (ii < 0 || ii >= n) continue;
+      T sv = sB[(size_t)ii * qB + rB];
+      if (s2) sv = tadd(sv, s2[(size_t)ii * q2 + r2]);
+      acc = tfma(cf[dX + 1], sv, acc);
+    }
+    T* o = rhs + (size_t)i * q + rtB;
+    *o = tadd(*o, tmk<T>(acc.x * sgnB, acc.y * sgnB));
+  }
+}
+
+__global__ void k_down_copy(const cplx* __restrict__ a, fcplx* __restrict__ b, size_t cnt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
 template <typename K>
@@ -711,8 +888,15 @@ ls_status slabs_build(ls_plan* p) {
   const size_t qq = (size_t)qmax * qmax;
   const size_t work_elems = 3 * (size_t)n * qq + 5 * (size_t)(n / 2 + 1) * qq;
   cplx* work = nullptr;
+  cplx* fac64 = nullptr;  // FP32 plans: FP64 factors of one slab before rounding
   int* status = nullptr;
   LS_HIP(hipMalloc(&work, work_elems * sizeof(cplx)));
+  if (p->fp32) {
+    size_t mx = 0;
+    for (int o = 0; o < 2; ++o)
+      for (Slab& s : p->slabs[o]) mx = std::max(mx, plan_levels(s, n));
+    LS_HIP(hipMalloc(&fac64, mx * sizeof(cplx)));
+  }
   LS_HIP(hipMalloc(&status, sizeof(int)));
   LS_HIP(hipMemsetAsync(status, 0, sizeof(int), p->stream));
   const double w2 = p->omega * p->omega;
@@ -721,16 +905,39 @@ ls_status slabs_build(ls_plan* p) {
   for (int o = 0; o < 2 && st == LS_OK; ++o) {
     for (Slab& s : p->slabs[o]) {
       const size_t cbytes = (size_t)n * s.q * 9 * sizeof(cplx);
+      const size_t vec = (size_t)n * s.q;
+      const size_t bvec = vec * p->opt.max_batch;
       if ((st = plan_alloc(p, (void**)&s.coef, cbytes)) != LS_OK) break;
-      if ((st = plan_alloc(p, (void**)&s.g, (size_t)n * s.q * sizeof(cplx))) != LS_OK) break;
-      if ((st = plan_alloc(p, (void**)&s.w, (size_t)n * s.q * sizeof(cplx))) != LS_OK) break;
       s.fac_elems = plan_levels(s, n);
-      if ((st = plan_alloc(p, (void**)&s.fac, s.fac_elems * sizeof(cplx))) != LS_OK) break;
+      if (p->fp32) {
+        if ((st = plan_alloc(p, (void**)&s.coef32, cbytes / 2)) != LS_OK) break;
+        if ((st = plan_alloc(p, (void**)&s.g32, bvec * sizeof(fcplx))) != LS_OK) break;
+        if ((st = plan_alloc(p, (void**)&s.w32, bvec * sizeof(fcplx))) != LS_OK) break;
+        if ((st = plan_alloc(p, (void**)&s.fac32, s.fac_elems * sizeof(fcplx))) != LS_OK) break;
+        s.fac = fac64;
+      } else {
+        if ((st = plan_alloc(p, (void**)&s.g, bvec * sizeof(cplx))) != LS_OK) break;
+        if ((st = plan_alloc(p, (void**)&s.w, bvec * sizeof(cplx))) != LS_OK) break;
+        if ((st = plan_alloc(p, (void**)&s.fac, s.fac_elems * sizeof(cplx))) != LS_OK) break;
+      }
       const cplx* tables = p->stencil_d + (o == 0 ? 0 : 162);
       k_assemble<<<dim3((s.q + 63) / 64, n), 64, 0, p->stream>>>(
           s.coef, tables, p->m, n, s.q, s.z0, s.a, s.b, std::max(ext, 2), o, w2, sigma);
       if (hipGetLastError() != hipSuccess) { ls_set_error("assembly launch failed"); st = LS_EDEVICE; break; }
       if ((st = factor_slab(p, s, work, status)) != LS_OK) break;
+      if (p->fp32) {
+        // FP64 factorisation, FP32 storage for the solves
+        k_down_copy<<<(unsigned)((s.fac_elems + 255) / 256), 256, 0, p->stream>>>(s.fac, s.fac32,
+                                                                              s.fac_elems);
+        k_down_copy<<<(unsigned)((vec * 9 + 255) / 256), 256, 0, p->stream>>>(s.coef, s.coef32,
+                                                                            vec * 9);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(p->stream) != hipSuccess) {
+          ls_set_error("factor conversion failed");
+          st = LS_EDEVICE;
+          break;
+        }
+        s.fac = nullptr;
+      }
     }
   }
   int bad = 0;
@@ -738,124 +945,217 @@ ls_status slabs_build(ls_plan* p) {
     if (hipMemcpy(&bad, status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) st = LS_EDEVICE;
   }
   (void)hipFree(work);
+  if (fac64) (void)hipFree(fac64);
   (void)hipFree(status);
   if (st != LS_OK) return st;
   if (bad) {
     ls_set_error("slab factorisation: zero or non-finite pivot");
     return LS_ESINGULAR;
   }
-  LS_TRY(plan_alloc(p, (void**)&p->slab_work, (size_t)n * qmax * sizeof(cplx)));
-  LS_TRY(plan_alloc(p, (void**)&p->slab_work2, (size_t)n * qmax * sizeof(cplx)));
+  const size_t wv = (size_t)n * qmax * p->opt.max_batch;
+  if (p->fp32) {
+    LS_TRY(plan_alloc(p, (void**)&p->slab_work32, wv * sizeof(fcplx)));
+    LS_TRY(plan_alloc(p, (void**)&p->slab_work32b, wv * sizeof(fcplx)));
+  } else {
+    LS_TRY(plan_alloc(p, (void**)&p->slab_work, wv * sizeof(cplx)));
+    LS_TRY(plan_alloc(p, (void**)&p->slab_work2, wv * sizeof(cplx)));
+  }
   return LS_OK;
 }
 
-ls_status slab_solve_frame(ls_plan* p, Slab& s, cplx* x) {
+// Workgroup size per level: 256 threads when the level has many blocks,
+// 1024 when it has few (the deep levels are latency bound).
+template <typename C, int MODE>
+static void launch_step(ls_plan* p, int nb, C* x, const C* m0, const C* m1, const C* m2, int q,
+                        int nl, int shift) {
+  if (nb >= 128)
+    k_step<C, MODE, 256><<<nb, 256, 0, p->stream>>>(x, m0, m1, m2, q, nl, shift);
+  else
+    k_step<C, MODE, 1024><<<nb, 1024, 0, p->stream>>>(x, m0, m1, m2, q, nl, shift);
+}
+
+template <typename C>
+static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C* coef, C* x,
+                                size_t xs_b, int B) {
   const int n = p->n, q = s.q;
-  const size_t qq = (size_t)q * q;
-  const cplx* fac = s.fac;
   const int nlev = (int)s.levels.size();
+  constexpr int kBT = BTile<C>::V;
+  const int tiles = (B + kBT - 1) / kBT;
+  auto launch = [&](auto kern, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
+    kern<<<dim3(nb, tiles), 256, 0, p->stream>>>(x, xs_b, B, a0, a1, a2, coef, n, q, nl, shift);
+  };
   if (nlev == 1) {
-    k_last<<<1, kSolveThreads, 0, p->stream>>>(x, fac + s.levels[0].off_dinv, q);
+    launch(k_bstep<C, BSTEP_LAST>, 1, fac + s.levels[0].off_dinv, nullptr, nullptr, 1, 0);
     LS_HIP(hipGetLastError());
     return LS_OK;
   }
-  (void)qq;
-  // forward
   const SlabLevel& L0 = s.levels[0];
-  k_fwd0_odd<<<L0.nl / 2, kSolveThreads, 0, p->stream>>>(x, fac + L0.off_dinv, q);
-  k_fwd0_even<<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(x, s.coef, n, q);
+  launch(k_bstep<C, BSTEP_ODD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  k_fwd0_even_b<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, B), 128, 0, p->stream>>>(x, xs_b, coef, n, q);
   for (int l = 1; l < nlev - 1; ++l) {
     const SlabLevel& L = s.levels[l];
-    k_fwd<<<(L.nl + 1) / 2, kSolveThreads, 0, p->stream>>>(x, fac + L.off_pm, fac + L.off_pp, q,
-                                                         L.nl, l);
+    launch(k_bstep<C, BSTEP_FWD>, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
   }
-  k_last<<<1, kSolveThreads, 0, p->stream>>>(x, fac + s.levels[nlev - 1].off_dinv, q);
+  launch(k_bstep<C, BSTEP_LAST>, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
   for (int l = nlev - 2; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
-    k_bwd<<<L.nl / 2, kSolveThreads, 0, p->stream>>>(x, fac + L.off_dinv, fac + L.off_dinvl,
-                                                   fac + L.off_dinvu, q, L.nl, l);
+    launch(k_bstep<C, BSTEP_BWD>, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu,
+           L.nl, l);
   }
-  k_bwd0<<<L0.nl / 2, kSolveThreads, 0, p->stream>>>(x, fac + L0.off_dinv, s.coef, n, q);
+  launch(k_bstep<C, BSTEP_BWD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
-static ls_status gather(ls_plan* p, const Slab& s, const cplx* g, cplx* dst) {
+template <typename C>
+static ls_status solve_levels(ls_plan* p, const Slab& s, const C* fac, const C* coef, C* x) {
+  const int n = p->n, q = s.q;
+  const int nlev = (int)s.levels.size();
+  if (nlev == 1) {
+    launch_step<C, STEP_LAST>(p, 1, x, fac + s.levels[0].off_dinv, nullptr, nullptr, q, 1, 0);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+  }
+  const SlabLevel& L0 = s.levels[0];
+  k_fwd0_odd<C, 256><<<L0.nl / 2, 256, 0, p->stream>>>(x, fac + L0.off_dinv, q);
+  k_fwd0_even<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(x, coef, n, q);
+  for (int l = 1; l < nlev - 1; ++l) {
+    const SlabLevel& L = s.levels[l];
+    launch_step<C, STEP_FWD>(p, (L.nl + 1) / 2, x, fac + L.off_pm, fac + L.off_pp, nullptr, q,
+                             L.nl, l);
+  }
+  launch_step<C, STEP_LAST>(p, 1, x, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, q, 1, 0);
+  for (int l = nlev - 2; l >= 1; --l) {
+    const SlabLevel& L = s.levels[l];
+    launch_step<C, STEP_BWD>(p, L.nl / 2, x, fac + L.off_dinv, fac + L.off_dinvl,
+                             fac + L.off_dinvu, q, L.nl, l);
+  }
+  k_bwd0<C, 256><<<L0.nl / 2, 256, 0, p->stream>>>(x, fac + L0.off_dinv, coef, n, q);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+// Per-precision views of the slab buffers.
+template <typename T>
+struct SB;
+template <>
+struct SB<cplx> {
+  static cplx* g(Slab& s) { return s.g; }
+  static cplx* w(Slab& s) { return s.w; }
+  static const cplx* fac(const Slab& s) { return s.fac; }
+  static const cplx* coef(const Slab& s) { return s.coef; }
+  static cplx* work(ls_plan* p, int k) { return k ? p->slab_work2 : p->slab_work; }
+  static cplx* vtmp(ls_plan* p) { return p->vtmp; }
+};
+template <>
+struct SB<fcplx> {
+  static fcplx* g(Slab& s) { return s.g32; }
+  static fcplx* w(Slab& s) { return s.w32; }
+  static const fcplx* fac(const Slab& s) { return s.fac32; }
+  static const fcplx* coef(const Slab& s) { return s.coef32; }
+  static fcplx* work(ls_plan* p, int k) { return k ? p->slab_work32b : p->slab_work32; }
+  static fcplx* vtmp(ls_plan* p) { return p->vtmp32; }
+};
+
+template <typename T>
+static ls_status solve_t(ls_plan* p, Slab& s, T* x, int B = 1) {
+  if (B == 1) return solve_levels<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), x);
+  return solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), x, (size_t)p->n * s.q, B);
+}
+
+ls_status slab_solve_frame(ls_plan* p, Slab& s, cplx* x) { return solve_t<cplx>(p, s, x); }
+ls_status slab_solve_frame(ls_plan* p, Slab& s, fcplx* x) { return solve_t<fcplx>(p, s, x); }
+ls_status slab_solve_batch(ls_plan* p, Slab& s, cplx* x, int B) { return solve_t<cplx>(p, s, x, B); }
+ls_status slab_solve_batch(ls_plan* p, Slab& s, fcplx* x, int B) { return solve_t<fcplx>(p, s, x, B); }
+
+template <typename T>
+static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B) {
   const int n = p->n, tot = n * s.q;
-  k_gather<<<(tot + 255) / 256, 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b, s.orient);
+  k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b,
+                                                                  s.orient);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
-static ls_status scatter(ls_plan* p, const Slab& s, const cplx* src, cplx* out, bool acc) {
+template <typename T>
+static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool acc, int B) {
   const int n = p->n, tot = n * (s.b - s.a + 1);
-  k_scatter<<<(tot + 255) / 256, 256, 0, p->stream>>>(src, out, n, s.q, s.z0, s.a, s.b,
-                                                      s.orient, acc ? 1 : 0);
+  k_scatter<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(src, out, n, s.q, s.z0, s.a, s.b,
+                                                                   s.orient, acc ? 1 : 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
-static ls_status inject(ls_plan* p, const Slab& s, cplx* rhs, int line, int dZ, double sgn,
-                        const cplx* s1, const Slab& o1, int line1, const cplx* s2,
-                        const Slab* o2, int line2) {
-  const int n = p->n;
-  k_inject<<<(n + 255) / 256, 256, 0, p->stream>>>(
-      rhs, s.coef, n, s.q, line - s.z0, dZ, sgn, s1, o1.q, line1 - o1.z0, s2,
-      o2 ? o2->q : 0, o2 ? line2 - o2->z0 : 0);
-  LS_HIP(hipGetLastError());
-  return LS_OK;
-}
-
-// Alg. 1 (Gauss-Seidel polarized traces) on layers of one orientation.
-// v receives the concatenated layer solutions (or has them added).
-ls_status sweep_apply(ls_plan* p, int orient, const cplx* g, cplx* v, bool accumulate) {
+// Alg. 1 (Gauss-Seidel polarized traces) on layers of one orientation, for
+// B right-hand sides at once.  v receives the concatenated layer solutions
+// (or has them added).
+template <typename T>
+static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumulate, int B) {
   std::vector<Slab>& S = p->slabs[orient];
   const int L = (int)S.size();
   const int n = p->n;
+  const dim3 grid((n + 255) / 256, B);
   // downward sweep: l = L-1 .. 0
   for (int l = L - 1; l >= 0; --l) {
     Slab& s = S[l];
-    LS_TRY(gather(p, s, g, s.g));
+    LS_TRY(gather<T>(p, s, g, SB<T>::g(s), B));
     if (l != L - 1) {
-      const Slab& up = S[l + 1];
+      Slab& up = S[l + 1];
       // g^l += -delta_b C^l_{b,b+1} w^{l+1}(b+1) + delta_{b+1} C^l_{b+1,b} w^{l+1}(b)
-      LS_TRY(inject(p, s, s.g, s.b, +1, -1.0, up.w, up, s.b + 1, nullptr, nullptr, 0));
-      LS_TRY(inject(p, s, s.g, s.b + 1, -1, +1.0, up.w, up, s.b, nullptr, nullptr, 0));
+      k_inject2<T><<<grid, 256, 0, p->stream>>>(
+          SB<T>::g(s), SB<T>::coef(s), n, s.q,
+          s.b - s.z0, +1, -1.0, SB<T>::w(up), up.q, s.b + 1 - up.z0,
+          s.b + 1 - s.z0, -1, +1.0, SB<T>::w(up), up.q, s.b - up.z0, nullptr, 0, 0);
+      LS_HIP(hipGetLastError());
     }
-    LS_HIP(hipMemcpyAsync(s.w, s.g, (size_t)n * s.q * sizeof(cplx), hipMemcpyDeviceToDevice,
-                          p->stream));
-    LS_TRY(slab_solve_frame(p, s, s.w));
+    LS_HIP(hipMemcpyAsync(SB<T>::w(s), SB<T>::g(s), (size_t)B * n * s.q * sizeof(T),
+                          hipMemcpyDeviceToDevice, p->stream));
+    LS_TRY(solve_t<T>(p, s, SB<T>::w(s), B));
   }
   // upward sweep: l = 0 .. L-1
-  cplx* vprev = p->slab_work;
-  cplx* vcur = p->slab_work2;
+  T* vprev = SB<T>::work(p, 0);
+  T* vcur = SB<T>::work(p, 1);
   for (int l = 0; l < L; ++l) {
     Slab& s = S[l];
     if (l == 0) {
       // g^0 is unchanged: v^0 = w^0
-      LS_HIP(hipMemcpyAsync(vcur, s.w, (size_t)n * s.q * sizeof(cplx), hipMemcpyDeviceToDevice,
-                            p->stream));
+      LS_HIP(hipMemcpyAsync(vcur, SB<T>::w(s), (size_t)B * n * s.q * sizeof(T),
+                            hipMemcpyDeviceToDevice, p->stream));
     } else {
       const Slab& dn = S[l - 1];
       // g^l += -delta_a C^l_{a,a-1} v0 + delta_{a-1} C^l_{a-1,a} v1 with
       // v0 = v^{l-1}(a-1), v1 = v^{l-1}(a) + w^l(a)
-      LS_TRY(inject(p, s, s.g, s.a, -1, -1.0, vprev, dn, s.a - 1, nullptr, nullptr, 0));
-      LS_TRY(inject(p, s, s.g, s.a - 1, +1, +1.0, vprev, dn, s.a, s.w, &s, s.a));
-      LS_HIP(hipMemcpyAsync(vcur, s.g, (size_t)n * s.q * sizeof(cplx), hipMemcpyDeviceToDevice,
-                            p->stream));
-      LS_TRY(slab_solve_frame(p, s, vcur));
+      k_inject2<T><<<grid, 256, 0, p->stream>>>(
+          SB<T>::g(s), SB<T>::coef(s), n, s.q,
+          s.a - s.z0, -1, -1.0, vprev, dn.q, s.a - 1 - dn.z0,
+          s.a - 1 - s.z0, +1, +1.0, vprev, dn.q, s.a - dn.z0, SB<T>::w(s), s.q, s.a - s.z0);
+      LS_HIP(hipGetLastError());
+      LS_HIP(hipMemcpyAsync(vcur, SB<T>::g(s), (size_t)B * n * s.q * sizeof(T),
+                            hipMemcpyDeviceToDevice, p->stream));
+      LS_TRY(solve_t<T>(p, s, vcur, B));
     }
-    LS_TRY(scatter(p, s, vcur, v, accumulate));
+    LS_TRY(scatter<T>(p, s, vcur, v, accumulate, B));
     std::swap(vprev, vcur);
   }
   return LS_OK;
 }
 
+ls_status sweep_apply(ls_plan* p, int orient, const cplx* g, cplx* v, bool accumulate, int B) {
+  return sweep_t<cplx>(p, orient, g, v, accumulate, B);
+}
+ls_status sweep_apply(ls_plan* p, int orient, const fcplx* g, fcplx* v, bool accumulate, int B) {
+  return sweep_t<fcplx>(p, orient, g, v, accumulate, B);
+}
+
 // Alg. 2: u1 = Prec_H(g); e = g - C u1; u2 = Prec_V(e); v = u1 + u2.
-ls_status bidirectional_apply(ls_plan* p, const cplx* g, cplx* v) {
-  cplx* e = p->vtmp;
-  LS_TRY(sweep_apply(p, 0, g, v, false));
-  LS_TRY(stencil_residual_C(p, g, v, e));
-  LS_TRY(sweep_apply(p, 1, e, v, true));
+template <typename T>
+static ls_status bidir_t(ls_plan* p, const T* g, T* v, int B) {
+  T* e = SB<T>::vtmp(p);
+  LS_TRY(sweep_t<T>(p, 0, g, v, false, B));
+  LS_TRY(stencil_residual_C(p, g, v, e, B));
+  LS_TRY(sweep_t<T>(p, 1, e, v, true, B));
   return LS_OK;
 }
+
+ls_status bidirectional_apply(ls_plan* p, const cplx* g, cplx* v, int B) { return bidir_t<cplx>(p, g, v, B); }
+ls_status bidirectional_apply(ls_plan* p, const fcplx* g, fcplx* v, int B) { return bidir_t<fcplx>(p, g, v, B); }

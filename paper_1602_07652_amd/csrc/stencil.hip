@@ -180,19 +180,19 @@ __global__ void k_stencil_solve(const cplx* __restrict__ gram, const cplx* __res
 
 __device__ __forceinline__ int axis_type(int i, int n) { return i == 0 ? 0 : (i == n - 1 ? 2 : 1); }
 
-// y = A r (mode 0), y = C v (mode 1), y = g - C v (mode 2).
-template <int MODE>
-__global__ void k_stencil(const cplx* __restrict__ in, const cplx* __restrict__ g,
-                          cplx* __restrict__ out, const cplx* __restrict__ tables,
-                          const double* __restrict__ m, int n, double omega2) {
+// y = A r (mode 0), y = C v (mode 1), y = g - C v (mode 2); T = double2
+// or float2 (tables and arithmetic in that precision).
+template <typename T, typename R, int MODE>
+__global__ void k_stencil(const T* __restrict__ in, const T* __restrict__ g, T* __restrict__ out,
+                          const T* __restrict__ tables, const R* __restrict__ m, int n, R omega2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const size_t base = (size_t)blockIdx.z * n * n;
   if (i >= n) return;
   const int t = axis_type(j, n) * 3 + axis_type(i, n);
-  const cplx* al = tables + t * 9;
-  const cplx* be = tables + 81 + t * 9;
-  cplx acc = cmk(0.0, 0.0);
+  const T* al = tables + t * 9;
+  const T* be = tables + 81 + t * 9;
+  T acc = tmk<T>(0, 0);
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
     const int jj = j + dz;
@@ -203,13 +203,22 @@ __global__ void k_stencil(const cplx* __restrict__ in, const cplx* __restrict__ 
       if (ii < 0 || ii >= n) continue;
       const int s = (dz + 1) * 3 + dx + 1;
       const size_t idx = (size_t)jj * n + ii;
-      cplx c = al[s];
-      if (MODE != 0) c = cadd(c, cscale(be[s], omega2 * m[idx]));
-      acc = cfma(c, in[base + idx], acc);
+      T c = al[s];
+      if (MODE != 0) {
+        const R f = omega2 * m[idx];
+        c.x = fma(be[s].x, f, c.x);
+        c.y = fma(be[s].y, f, c.y);
+      }
+      acc = tfma(c, in[base + idx], acc);
     }
   }
   const size_t o = base + (size_t)j * n + i;
-  out[o] = (MODE == 2) ? csub(g[o], acc) : acc;
+  out[o] = (MODE == 2) ? tsub(g[o], acc) : acc;
+}
+
+__global__ void k_to_f32(const cplx* __restrict__ a, fcplx* __restrict__ b, int cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
 }  // namespace
@@ -239,26 +248,43 @@ ls_status stencils_build(ls_plan* p, const cplx* circ) {
   return LS_OK;
 }
 
-static ls_status launch_stencil(ls_plan* p, int mode, const cplx* in, const cplx* g, cplx* out, int batch) {
+template <typename T, typename R>
+static ls_status launch_stencil(ls_plan* p, const T* tables, const R* m, int mode, const T* in,
+                                const T* g, T* out, int batch) {
   const int n = p->n;
   dim3 grid((n + 127) / 128, n, batch);
-  const double w2 = p->omega * p->omega;
+  const R w2 = (R)(p->omega * p->omega);
   if (mode == 0)
-    k_stencil<0><<<grid, 128, 0, p->stream>>>(in, g, out, p->stencil_d, p->m, n, w2);
+    k_stencil<T, R, 0><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
   else if (mode == 1)
-    k_stencil<1><<<grid, 128, 0, p->stream>>>(in, g, out, p->stencil_d, p->m, n, w2);
+    k_stencil<T, R, 1><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
   else
-    k_stencil<2><<<grid, 128, 0, p->stream>>>(in, g, out, p->stencil_d, p->m, n, w2);
+    k_stencil<T, R, 2><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+ls_status stencils_to_f32(ls_plan* p) {
+  k_to_f32<<<2, 256, 0, p->stream>>>(p->stencil_d, p->f32.stencil, 324);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
 ls_status stencil_apply_A(ls_plan* p, const cplx* r, cplx* y, int batch) {
-  return launch_stencil(p, 0, r, nullptr, y, batch);
+  return launch_stencil<cplx, double>(p, p->stencil_d, p->m, 0, r, nullptr, y, batch);
 }
 ls_status stencil_apply_C(ls_plan* p, const cplx* v, cplx* y, int batch) {
-  return launch_stencil(p, 1, v, nullptr, y, batch);
+  return launch_stencil<cplx, double>(p, p->stencil_d, p->m, 1, v, nullptr, y, batch);
 }
-ls_status stencil_residual_C(ls_plan* p, const cplx* g, const cplx* u, cplx* e) {
-  return launch_stencil(p, 2, u, g, e, 1);
+ls_status stencil_residual_C(ls_plan* p, const cplx* g, const cplx* u, cplx* e, int batch) {
+  return launch_stencil<cplx, double>(p, p->stencil_d, p->m, 2, u, g, e, batch);
+}
+ls_status stencil_apply_A(ls_plan* p, const fcplx* r, fcplx* y, int batch) {
+  return launch_stencil<fcplx, float>(p, p->f32.stencil, p->f32.m, 0, r, nullptr, y, batch);
+}
+ls_status stencil_apply_C(ls_plan* p, const fcplx* v, fcplx* y, int batch) {
+  return launch_stencil<fcplx, float>(p, p->f32.stencil, p->f32.m, 1, v, nullptr, y, batch);
+}
+ls_status stencil_residual_C(ls_plan* p, const fcplx* g, const fcplx* u, fcplx* e, int batch) {
+  return launch_stencil<fcplx, float>(p, p->f32.stencil, p->f32.m, 2, u, g, e, batch);
 }

@@ -1,0 +1,103 @@
+"""GPU parity of the FP32 + FP64-refinement path (LS_FP32_REFINE).
+
+Low-precision steps are compared with the FP64 oracle at FP32 tolerances
+(rounding ~6e-8 times the log of the FFT size or the local condition
+number); the refined solution is compared with the exact discrete solution
+to the 1e-8 target.  At the full 2048^2 size the oracle evaluates the FP64
+residual ||f - H u|| / ||f|| of the GPU solution (a property that holds at
+any size).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+from oracle import kernel, sparsify, slabs, solver
+import ls_inputs as li
+from gpu_helpers import dev, host, rel, banner
+
+pytestmark = pytest.mark.gpu
+
+
+def plan32(n, f, m, **kw):
+    from paper_1602_07652_amd import Plan, LS_FP32_REFINE
+    omega = 2 * np.pi * f
+    banner(f"fp32 plan n={n} f={f} opts={kw}")
+    return Plan(n, 1.0 / n, omega, dev(m, torch.float64), precision=LS_FP32_REFINE, **kw), omega
+
+
+@pytest.mark.parametrize("n,batch", [(37, 2), (256, 1), (1024, 1)])
+def test_fp32_operator(n, batch):
+    m, _ = li.gaussian_bumps_medium(n, seed=n)
+    p, omega = plan32(n, n / 10.0, m, precond=2, max_batch=batch)
+    v = li.random_complex((batch, n, n), seed=7 + n)
+    y = host(p.apply_c64(dev(v, torch.complex64)))
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    e = rel(y, kernel.apply_H(W, m, v.astype(np.complex64).astype(np.complex128), omega))
+    banner(f"fp32 apply n={n} rel err {e:.3e}")
+    assert e < 5e-6
+    # the FP64 operator of an FP32 plan stays FP64
+    y64 = host(p.apply(dev(v)))
+    assert rel(y64, kernel.apply_H(W, m, v, omega)) < 1e-13
+    p.close()
+
+
+def test_fp32_slabs_and_sweeps():
+    n, f, L, ext = 100, 10.0, 3, 8
+    omega = 2 * np.pi * f
+    m, _ = li.gaussian_bumps_medium(n, seed=3)
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    al, be, _ = sparsify.stencils(W, n)
+    p, _ = plan32(n, f, m, slabs=L, ext=ext)
+    parts = slabs.layer_partition(n, L, ext)
+    for l in range(L):
+        Cl = slabs.assemble_slab(al, be, m, omega, parts[l], ext)
+        q = parts[l][3] - parts[l][2] + 1
+        b = li.random_complex((n, q), seed=l)
+        x = host(p.slab_solve(0, l, dev(b)))
+        x_ref = spla.spsolve(Cl.tocsc(), b.T.reshape(-1)).reshape(q, n).T
+        e = rel(x, x_ref)
+        banner(f"fp32 slab l={l} rel err {e:.3e}")
+        assert e < 1e-4
+    bd = slabs.BiDirectional(al, be, m, omega, L, ext)
+    g = li.random_complex((n, n), 3)
+    e = rel(host(p.bidirectional(dev(g))), bd.apply(g))
+    banner(f"fp32 bidirectional rel err {e:.3e}")
+    assert e < 1e-4
+    p.close()
+
+
+def test_fp32_refined_solve_reaches_fp64_accuracy():
+    cfg = li.config_inputs("c1_64_gauss_disk")
+    n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
+    p, _ = plan32(n, 6.0, m, slabs=4, ext=10)
+    f = p.rhs_from_incident(dev(cfg["uI"]))
+    u, info = p.solve(f, tol=1e-10)
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    u_star = solver.dense_solve(W, m, omega, kernel.rhs_from_incident(W, m, cfg["uI"], omega))
+    e = rel(host(u), u_star)
+    banner(f"fp32+refine c1 info={info[0]} rel err vs dense {e:.3e}")
+    assert info[0]["converged"] == 1 and e < 1e-8
+    p.close()
+
+
+@pytest.mark.parametrize("name", ["c3_2048_grf"])
+def test_fp32_refined_solve_full_size_residual(name):
+    """2048^2 Gaussian-random-field workload: the oracle's FP64 residual of
+    the GPU solution is below the tolerance."""
+    cfg = li.config_inputs(name)
+    n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
+    p, _ = plan32(n, omega / (2 * np.pi), m, slabs=cfg["slabs"], ext=10)
+    uI = cfg["uI"]
+    f = p.rhs_from_incident(dev(uI))
+    u, info = p.solve(f, tol=1e-8)
+    banner(f"fp32+refine {name} info={info[0]}")
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    Gh = kernel.circulant_spectrum(W)
+    f_ref = kernel.rhs_from_incident(W, m, uI, omega, Gh)
+    uh = host(u)
+    r = f_ref - kernel.apply_H(W, m, uh, omega, Gh)
+    res = np.linalg.norm(r) / np.linalg.norm(f_ref)
+    banner(f"oracle FP64 residual of the GPU solution {res:.3e}")
+    assert info[0]["converged"] == 1 and res < 1.5e-8
+    p.close()
