@@ -80,6 +80,8 @@ typedef struct {
   int max_batch;         /* largest `batch` passed to ls_apply / ls_rhs_from_incident */
   double lowp_tol;       /* LS_FP32_REFINE: relative tolerance of each FP32 correction solve */
   int max_refine;        /* LS_FP32_REFINE: refinement sweeps limit */
+  int use_graphs;        /* 1: the inner preconditioner runs as a captured hipGraph */
+  int autotune;          /* 1: time the FFT column-pass tile variants at plan creation */
 } ls_options;
 
 typedef struct {
@@ -93,7 +95,8 @@ typedef struct {
 
 /* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,
  * max_inner 50, shift_c 0, LS_FP64, LS_PREC_BD, inner_fixed_iters 0,
- * max_batch 1, lowp_tol 1e-5, max_refine 10.  Never fails. */
+ * max_batch 1, lowp_tol 1e-5, max_refine 10, use_graphs 1, autotune 1.
+ * Never fails. */
 void ls_options_default(ls_options* opt);
 
 /* Off-line stage (Section 4.1): builds everything that depends on the
@@ -102,8 +105,9 @@ void ls_options_default(ls_options* opt);
  * (m(x_{i,j}) at index j*n + i), copied -- the caller keeps ownership.
  * Each extended layer must satisfy q = thickness + extensions <= 128 and
  * each layer must be at least ext rows thick.  opt may be NULL (defaults).
- * stream: hipStream_t as void*.  On success *out owns all device memory of
- * the plan.  Steps: kernel samples w and the circulant spectrum (Section 2),
+ * stream: hipStream_t as void*; NULL makes the plan create its own blocking
+ * stream (ordered with the null stream, and capturable into graphs).  On
+ * success *out owns all device memory of the plan.  Steps: kernel samples w and the circulant spectrum (Section 2),
  * stencils alpha/beta (Section 2), slab matrices (Section 3.3) and their
  * block-cyclic-reduction factors (Section 4.1). */
 ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const double* m,
@@ -135,6 +139,18 @@ ls_status ls_precond_apply(ls_plan* plan, const double* r, double* z, int batch)
  * LS_ENOCONV if some right-hand side hit max_outer (or max_refine). */
 ls_status ls_solve(ls_plan* plan, const double* f, double* u, int batch, double tol,
                    ls_solve_info* info);
+
+/* Several independent media (plans, possibly of different n) solved at
+ * once: one host thread per plan calls ls_solve on that plan's stream, so
+ * the GPU runs the plans' kernels concurrently (the paper solves 64
+ * incident waves per medium, Section 5).  Plans must be distinct and use
+ * distinct streams.  f[i], u[i]: DEVICE arrays of batch[i] grid vectors of
+ * plans[i]; info[i]: HOST arrays or info == NULL.  Returns the first
+ * error other than LS_ENOCONV, else LS_ENOCONV if any plan did not
+ * converge, else LS_OK. */
+ls_status ls_solve_multi(ls_plan* const* plans, int count, const double* const* f,
+                         double* const* u, const int* batch, double tol,
+                         ls_solve_info* const* info);
 
 const char* ls_status_str(ls_status s);
 const char* ls_last_error(void);

@@ -19,7 +19,7 @@ import torch
 from .build import lib_path
 
 __all__ = [
-    "Options", "SolveInfo", "LSError", "Plan", "lib",
+    "Options", "SolveInfo", "LSError", "Plan", "lib", "solve_multi",
     "LS_PREC_BD", "LS_PREC_PT1", "LS_PREC_NONE", "LS_FP64", "LS_FP32_REFINE",
 ]
 
@@ -42,6 +42,7 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int), ("precond", ctypes.c_int),
         ("inner_fixed_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("lowp_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
+        ("use_graphs", ctypes.c_int), ("autotune", ctypes.c_int),
     ]
 
 
@@ -92,6 +93,8 @@ def lib():
         "ls_slab_solve": (_i, [_vp, _i, _i, _vp, _vp]),
         "ls_sweep": (_i, [_vp, _i, _vp, _vp]),
         "ls_bidirectional": (_i, [_vp, _vp, _vp]),
+        "ls_solve_multi": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                ctypes.POINTER(_i), _d, ctypes.POINTER(ctypes.POINTER(SolveInfo))]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -270,3 +273,25 @@ class Plan:
         N = self.n * self.n
         _check("ls_bidirectional", lib().ls_bidirectional(self.handle, _ptr(g, N, "g"), _ptr(out, N, "v")))
         return out
+
+
+def solve_multi(plans, fs, tol=1e-8, outs=None):
+    """ls_solve_multi: solve several plans' right-hand sides concurrently.
+
+    plans: list of Plan (distinct streams); fs: list of complex128 device
+    tensors [batch_i, n_i, n_i] (or [n_i, n_i]).  Returns (us, infos)."""
+    k = len(plans)
+    outs = [torch.empty_like(f) for f in fs] if outs is None else outs
+    P = (_vp * k)(*[p.handle.value for p in plans])
+    F = (_vp * k)(*[f.data_ptr() for f in fs])
+    U = (_vp * k)(*[u.data_ptr() for u in outs])
+    bs = [Plan._batch(f) for f in fs]
+    for p, f, u, b in zip(plans, fs, outs, bs):
+        _ptr(f, p.n * p.n * b, "f")
+        _ptr(u, p.n * p.n * b, "u")
+    B = (_i * k)(*bs)
+    infos = [(SolveInfo * b)() for b in bs]
+    I = (ctypes.POINTER(SolveInfo) * k)(*[ctypes.cast(x, ctypes.POINTER(SolveInfo)) for x in infos])
+    code = lib().ls_solve_multi(P, k, F, U, B, float(tol), I)
+    _check("ls_solve_multi", code)
+    return outs, [[i.as_dict() for i in x] for x in infos]

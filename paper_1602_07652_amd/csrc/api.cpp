@@ -15,6 +15,7 @@
 #include <complex>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <type_traits>
 
 namespace {
@@ -177,7 +178,7 @@ ls_status fgmres(ls_plan* p, Op op, Prec prec, const T* b, T* x, int B, double t
 }
 
 template <typename T>
-ls_status inner_prec(ls_plan* p, const T* in, T* out, int B) {
+ls_status inner_prec_eager(ls_plan* p, const T* in, T* out, int B) {
   const size_t N = (size_t)p->n * p->n;
   switch (p->opt.precond) {
     case LS_PREC_BD:
@@ -187,6 +188,47 @@ ls_status inner_prec(ls_plan* p, const T* in, T* out, int B) {
     default:
       return vec_copy(p, out, in, N * B);
   }
+}
+
+// The inner preconditioner (Alg. 2 or Alg. 1) is a fixed sequence of
+// kernels and device copies for given (in, out, B): it is captured once into
+// a hipGraph and replayed.  Nothing in it synchronises or sets memory with
+// memset nodes; the graph only references plan-owned buffers besides in/out.
+template <typename T>
+ls_status inner_prec(ls_plan* p, const T* in, T* out, int B) {
+  if (!p->opt.use_graphs || p->opt.precond == LS_PREC_NONE)
+    return inner_prec_eager<T>(p, in, out, B);
+  for (auto& g : p->graphs)
+    if (g.in == (const void*)in && g.out == (void*)out && g.B == B && g.elem == (int)sizeof(T)) {
+      LS_HIP(hipGraphLaunch(g.exec, p->stream));
+      return LS_OK;
+    }
+  LS_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed));
+  ls_status st = inner_prec_eager<T>(p, in, out, B);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(p->stream, &graph);
+  if (st != LS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) {
+    ls_set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+    return LS_EDEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    ls_set_error(std::string("graph instantiate failed: ") + hipGetErrorString(e));
+    return LS_EDEVICE;
+  }
+  if (p->graphs.size() >= 64) {
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    p->graphs.erase(p->graphs.begin());
+  }
+  p->graphs.push_back(GraphEntry{(const void*)in, (void*)out, B, (int)sizeof(T), exec});
+  LS_HIP(hipGraphLaunch(exec, p->stream));
+  return LS_OK;
 }
 
 template <typename T>
@@ -242,6 +284,7 @@ ls_status f32_scratch(ls_plan* p, F32Scratch& s) {
 }
 
 bool valid_opts(const ls_options& o) {
+  if (o.use_graphs < 0 || o.use_graphs > 1 || o.autotune < 0 || o.autotune > 1) return false;
   return o.ext >= 0 && o.inner_tol > 0 && o.max_outer >= 1 && o.max_inner >= 1 &&
          (o.precision == LS_FP64 || o.precision == LS_FP32_REFINE) && o.precond >= LS_PREC_BD &&
          o.precond <= LS_PREC_NONE && o.inner_fixed_iters >= 0 && o.max_batch >= 1 &&
@@ -331,6 +374,8 @@ void ls_options_default(ls_options* o) {
   o->max_batch = 1;
   o->lowp_tol = 1e-5;
   o->max_refine = 10;
+  o->use_graphs = 1;
+  o->autotune = 1;
 }
 
 const char* ls_status_str(ls_status s) {
@@ -352,7 +397,9 @@ ls_status ls_plan_destroy(ls_plan* p) {
   if (!p) return LS_OK;
   DeviceGuard dg(p->device);
   (void)hipStreamSynchronize(p->stream);
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   for (void* a : p->allocs) (void)hipFree(a);
+  if (p->own_stream) (void)hipStreamDestroy(p->stream);
   delete p;
   return LS_OK;
 }
@@ -389,6 +436,7 @@ static ls_status create_impl(ls_plan* p, const double* m) {
   LS_TRY(plan_alloc(p, (void**)&p->fft_work, sizeof(cplx) * (size_t)p->opt.max_batch * n * p->P));
   LS_TRY(plan_alloc(p, (void**)&p->vtmp, sizeof(cplx) * (size_t)3 * n * n * p->opt.max_batch));
   if (p->opt.precond != LS_PREC_NONE) LS_TRY(slabs_build(p));
+  if (p->opt.autotune) LS_TRY(fft_autotune(p));
   LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
@@ -435,6 +483,16 @@ ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const dou
     ls_set_error("ls_plan_create: no HIP device");
     delete p;
     return LS_EDEVICE;
+  }
+  if (p->stream == nullptr) {
+    // a private blocking stream: ordered with the null stream like it, but
+    // capturable into graphs
+    if (hipStreamCreate(&p->stream) != hipSuccess) {
+      ls_set_error("ls_plan_create: stream creation failed");
+      delete p;
+      return LS_EDEVICE;
+    }
+    p->own_stream = true;
   }
   ls_status s = create_impl(p, m);
   if (s != LS_OK) {
@@ -559,8 +617,12 @@ ls_status ls_bidirectional(ls_plan* p, const double* g, double* v) {
   }
   DeviceGuard dg(p->device);
   if (p->fp32)
-    return via_f32(p, g, v, 1, [&](const fcplx* a, fcplx* b) { return bidirectional_apply(p, a, b, 1); });
-  return bidirectional_apply(p, reinterpret_cast<const cplx*>(g), reinterpret_cast<cplx*>(v), 1);
+    return via_f32(p, g, v, 1, [&](const fcplx* a, fcplx* b) {
+      return p->opt.precond == LS_PREC_BD ? inner_prec<fcplx>(p, a, b, 1) : bidirectional_apply(p, a, b, 1);
+    });
+  const cplx* gi = reinterpret_cast<const cplx*>(g);
+  cplx* vo = reinterpret_cast<cplx*>(v);
+  return p->opt.precond == LS_PREC_BD ? inner_prec<cplx>(p, gi, vo, 1) : bidirectional_apply(p, gi, vo, 1);
 }
 
 ls_status ls_apply_c64(ls_plan* p, const float* v, float* Hv, int batch) {
@@ -685,6 +747,38 @@ ls_status ls_solve(ls_plan* p, const double* f, double* u, int batch, double tol
     return LS_ENOCONV;
   }
   return LS_OK;
+}
+
+ls_status ls_solve_multi(ls_plan* const* plans, int count, const double* const* f,
+                         double* const* u, const int* batch, double tol,
+                         ls_solve_info* const* info) {
+  if (!plans || count < 1 || !f || !u || !batch) {
+    ls_set_error("ls_solve_multi: bad arguments");
+    return LS_EINVAL;
+  }
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i; ++j)
+      if (plans[i] == plans[j] || (plans[i] && plans[j] && plans[i]->stream == plans[j]->stream)) {
+        ls_set_error("ls_solve_multi: plans must be distinct and use distinct streams");
+        return LS_EINVAL;
+      }
+  std::vector<ls_status> st(count, LS_OK);
+  std::vector<std::string> msg(count);
+  std::vector<std::thread> th;
+  for (int i = 0; i < count; ++i)
+    th.emplace_back([&, i]() {
+      if (plans[i]) (void)hipSetDevice(plans[i]->device);
+      st[i] = ls_solve(plans[i], f[i], u[i], batch[i], tol, info ? info[i] : nullptr);
+      msg[i] = g_last_error;
+    });
+  for (auto& t : th) t.join();
+  ls_status worst = LS_OK;
+  for (int i = 0; i < count; ++i)
+    if (st[i] != LS_OK && (worst == LS_OK || worst == LS_ENOCONV)) {
+      worst = st[i];
+      g_last_error = "plan " + std::to_string(i) + ": " + msg[i];
+    }
+  return worst;
 }
 
 }  // extern "C"

@@ -129,15 +129,18 @@ struct RowCfg {
 };
 
 // Column pass: CPW adjacent columns per workgroup (<= 128 KB of LDS).
-template <typename T, int LOGN>
+// Variant V halves CPW V times (the autotuner picks V per plan).
+template <typename T, int LOGN, int V = 0>
 struct ColCfg {
   static constexpr int N = 1 << LOGN;
   static constexpr int LIM = (131072 / (int)sizeof(T)) / N;
-  static constexpr int CPW = (LIM < Tile<T>::W) ? LIM : Tile<T>::W;
+  static constexpr int CPW0 = (LIM < Tile<T>::W) ? LIM : Tile<T>::W;
+  static constexpr int CPW = (CPW0 >> V) > 0 ? (CPW0 >> V) : 1;
   static constexpr int NT0 = CPW * N / 4;
   static constexpr int NT = NT0 > 1024 ? 1024 : (NT0 < 64 ? 64 : NT0);
   static constexpr int STRIDE = N + 1;  // pad: adjacent columns in different banks
 };
+constexpr int kColVariants = 3;
 
 template <typename T>
 __device__ __forceinline__ size_t tiled(int b, int n, int N, int j, int kx) {
@@ -190,13 +193,13 @@ __device__ __forceinline__ int xcd_remap(int id, int total) {
 }
 
 // K2: per column c of X: FFT, multiply by the spectrum, IFFT, keep n.
-template <typename T, int LOGN>
-__global__ __launch_bounds__((ColCfg<T, LOGN>::NT)) void k_cols_conv(T* __restrict__ X,
-                                                                 const T* __restrict__ spec,
-                                                                 const T* __restrict__ tw, int n,
-                                                                 int ss, int groups_per_rhs,
-                                                                 int total_groups) {
-  using C = ColCfg<T, LOGN>;
+template <typename T, int LOGN, int V>
+__global__ __launch_bounds__((ColCfg<T, LOGN, V>::NT)) void k_cols_conv(T* __restrict__ X,
+                                                                    const T* __restrict__ spec,
+                                                                    const T* __restrict__ tw, int n,
+                                                                    int ss, int groups_per_rhs,
+                                                                    int total_groups) {
+  using C = ColCfg<T, LOGN, V>;
   constexpr int N = C::N, CPW = C::CPW, S = C::STRIDE, W = Tile<T>::W;
   extern __shared__ unsigned char lds_raw[];
   T* buf = reinterpret_cast<T*>(lds_raw);
@@ -289,9 +292,9 @@ __global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_full_rows(cplx* __restrict
 
 // Setup: forward FFT of every column, in place.
 template <int LOGN>
-__global__ __launch_bounds__((ColCfg<cplx, LOGN>::NT)) void k_full_cols(cplx* __restrict__ c,
-                                                                    const cplx* __restrict__ tw) {
-  using C = ColCfg<cplx, LOGN>;
+__global__ __launch_bounds__((ColCfg<cplx, LOGN, 0>::NT)) void k_full_cols(cplx* __restrict__ c,
+                                                                       const cplx* __restrict__ tw) {
+  using C = ColCfg<cplx, LOGN, 0>;
   constexpr int N = C::N, CPW = C::CPW, S = C::STRIDE;
   extern __shared__ unsigned char lds_raw[];
   cplx* buf = reinterpret_cast<cplx*>(lds_raw);
@@ -327,30 +330,45 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <typename T, int LOGN, int V>
+ls_status run_cols(const ApplyView<T, typename CT<T>::R>& av, int batch) {
+  using CC = ColCfg<T, LOGN, V>;
+  constexpr int N = 1 << LOGN;
+  const size_t lds_c = (size_t)CC::CPW * CC::STRIDE * sizeof(T);
+  static bool attr_done = false;
+  if (!attr_done) {
+    LS_HIP(set_lds(k_cols_conv<T, LOGN, V>, lds_c));
+    attr_done = true;
+  }
+  const int gpr = N / CC::CPW;
+  const int groups = gpr * batch;
+  k_cols_conv<T, LOGN, V><<<groups, CC::NT, lds_c, av.stream>>>(av.work, av.spec, av.tw, av.n,
+                                                               av.ss, gpr, groups);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
 template <typename T, typename R, int LOGN>
 ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, double a, double b) {
   using RC = RowCfg<LOGN>;
-  using CC = ColCfg<T, LOGN>;
   constexpr int N = 1 << LOGN;
   const int n = av.n;
   const int rows = batch * n;
   const size_t lds_r = (size_t)RC::COUNT * N * sizeof(T);
-  const size_t lds_c = (size_t)CC::CPW * CC::STRIDE * sizeof(T);
   static bool attr_done = false;
   if (!attr_done) {
     LS_HIP(set_lds(k_rows_fwd<T, R, LOGN>, lds_r));
     LS_HIP(set_lds(k_rows_inv<T, LOGN>, lds_r));
-    LS_HIP(set_lds(k_cols_conv<T, LOGN>, lds_c));
     attr_done = true;
   }
   k_rows_fwd<T, R, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
       v, av.m, av.work, av.tw, n, rows);
   LS_HIP(hipGetLastError());
-  const int gpr = N / CC::CPW;
-  const int groups = gpr * batch;
-  k_cols_conv<T, LOGN><<<groups, CC::NT, lds_c, av.stream>>>(av.work, av.spec, av.tw, n, av.ss,
-                                                            gpr, groups);
-  LS_HIP(hipGetLastError());
+  switch (av.col_variant) {
+    case 1: LS_TRY((run_cols<T, LOGN, 1>(av, batch))); break;
+    case 2: LS_TRY((run_cols<T, LOGN, 2>(av, batch))); break;
+    default: LS_TRY((run_cols<T, LOGN, 0>(av, batch))); break;
+  }
   k_rows_inv<T, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
       av.work, v, y, av.tw, n, rows, a, b);
   LS_HIP(hipGetLastError());
@@ -360,7 +378,7 @@ ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, doub
 template <int LOGN>
 ls_status run_full_forward(ls_plan* p, cplx* c) {
   using RC = RowCfg<LOGN>;
-  using CC = ColCfg<cplx, LOGN>;
+  using CC = ColCfg<cplx, LOGN, 0>;
   constexpr int N = 1 << LOGN;
   const size_t lds_r = (size_t)RC::COUNT * N * sizeof(cplx);
   const size_t lds_c = (size_t)CC::CPW * CC::STRIDE * sizeof(cplx);
@@ -444,4 +462,48 @@ ls_status apply_H(ls_plan* p, const cplx* v, cplx* y, int batch, double a, doubl
 
 ls_status apply_H32(ls_plan* p, const fcplx* v, fcplx* y, int batch, double a, double b) {
   return apply_H_t<fcplx, float>(view32(p), p->logP, v, y, batch, a, b);
+}
+
+// FFT autotuner: times every column-pass variant (tile width CPW, CPW/2,
+// CPW/4) on `batch` vectors of this plan with HIP events on the plan's
+// stream and keeps the fastest, for the FP64 and (FP32 plans) FP32 operator.
+template <typename T, typename R>
+static ls_status tune_one(ls_plan* p, ApplyView<T, R> av, T* in, T* out, int batch, int* choice,
+                          float* ms_out) {
+  hipEvent_t e0, e1;
+  LS_HIP(hipEventCreate(&e0));
+  LS_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int arg = 0;
+  for (int v = 0; v < kColVariants; ++v) {
+    av.col_variant = v;
+    LS_TRY((apply_H_t<T, R>(av, p->logP, in, out, batch, 1.0, 1.0)));
+    LS_HIP(hipEventRecord(e0, p->stream));
+    for (int r = 0; r < 3; ++r) LS_TRY((apply_H_t<T, R>(av, p->logP, in, out, batch, 1.0, 1.0)));
+    LS_HIP(hipEventRecord(e1, p->stream));
+    LS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms_out[v] = ms / 3.f;
+    if (ms < best) { best = ms; arg = v; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *choice = arg;
+  return LS_OK;
+}
+
+ls_status fft_autotune(ls_plan* p) {
+  const int batch = p->opt.max_batch;
+  const size_t N = (size_t)p->n * p->n;
+  // inputs: the plan's grid scratch (contents irrelevant for timing)
+  LS_TRY(vec_zero(p, p->vtmp, N * batch));
+  LS_TRY((tune_one<cplx, double>(p, view64(p), p->vtmp, p->vtmp + N * batch, batch,
+                                  &p->col_variant64, p->tune_ms64)));
+  if (p->fp32) {
+    LS_TRY(vec_zero(p, p->vtmp32, N * batch));
+    LS_TRY((tune_one<fcplx, float>(p, view32(p), p->vtmp32, p->vtmp32 + N * batch, batch,
+                                   &p->col_variant32, p->tune_ms32)));
+  }
+  return LS_OK;
 }

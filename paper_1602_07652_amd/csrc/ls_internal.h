@@ -129,6 +129,14 @@ struct Fp32State {
   fcplx* stencil = nullptr;   // alpha, beta, alphaT, betaT as float2
 };
 
+// Real type of a complex type.
+template <typename T>
+struct CT;
+template <>
+struct CT<cplx> { typedef double R; };
+template <>
+struct CT<fcplx> { typedef float R; };
+
 // Everything the FFT convolution needs, for one precision.
 template <typename T, typename R>
 struct ApplyView {
@@ -138,6 +146,16 @@ struct ApplyView {
   T* work;
   int n, ss;
   hipStream_t stream;
+  int col_variant;  // column-pass tile variant chosen by the autotuner
+};
+
+// A captured inner-preconditioner application.
+struct GraphEntry {
+  const void* in;
+  void* out;
+  int B;
+  int elem;  // sizeof the complex type
+  hipGraphExec_t exec;
 };
 
 // ---------------------------------------------------------------- plan
@@ -175,14 +193,20 @@ struct ls_plan {
 
   bool fp32 = false;             // FP32 operator + FP64 refinement
   Fp32State f32;
+
+  bool own_stream = false;       // created by the plan (caller passed NULL)
+  std::vector<GraphEntry> graphs;
+  int col_variant64 = 0, col_variant32 = 0;  // autotuned FFT column-pass variants
+  float tune_ms64[3] = {0, 0, 0}, tune_ms32[3] = {0, 0, 0};
 };
 
 inline ApplyView<cplx, double> view64(ls_plan* p) {
-  return ApplyView<cplx, double>{p->m, p->spec, p->tw, p->fft_work, p->n, p->spec_side, p->stream};
+  return ApplyView<cplx, double>{p->m,    p->spec,       p->tw,     p->fft_work,
+                                 p->n,    p->spec_side,  p->stream, p->col_variant64};
 }
 inline ApplyView<fcplx, float> view32(ls_plan* p) {
-  return ApplyView<fcplx, float>{p->f32.m, p->f32.spec, p->f32.tw, p->f32.fft_work, p->n,
-                                 p->spec_side, p->stream};
+  return ApplyView<fcplx, float>{p->f32.m, p->f32.spec,   p->f32.tw, p->f32.fft_work,
+                                 p->n,     p->spec_side,  p->stream, p->col_variant32};
 }
 
 // device memory helpers (record in plan->allocs)
@@ -198,6 +222,7 @@ ls_status fft2_full_forward(ls_plan* p, cplx* c);                // in place, P 
 ls_status spectrum_extract(ls_plan* p, const cplx* c);           // -> p->spec
 ls_status apply_H(ls_plan* p, const cplx* v, cplx* y, int batch, double sign_identity, double scale_conv);
 ls_status apply_H32(ls_plan* p, const fcplx* v, fcplx* y, int batch, double sign_identity, double scale_conv);
+ls_status fft_autotune(ls_plan* p);
 // stencil.hip
 ls_status stencils_build(ls_plan* p, const cplx* circ);
 ls_status stencil_apply_A(ls_plan* p, const cplx* r, cplx* y, int batch);
