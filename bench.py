@@ -179,6 +179,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--slab-reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 variant")
+    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched"],
+                    help="profiling sub-runs: slab = only slab solves of the bench workload's "
+                         "interior layer; copy = 1 GiB device copies (counter calibration); "
+                         "batched = only the multi-grid variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on a "
@@ -191,6 +195,17 @@ def main():
     from paper_1602_07652_amd import Plan
 
     dev = torch.device("cuda:0")
+    if args.mode == "copy":
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(args.slab_reps):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_per_copy": 1 << 30, "reps": args.slab_reps}))
+        return
+    if args.mode == "batched":
+        print(json.dumps({"mode": "batched", "batched": batched_variant(args.tol, log)}))
+        return
     cfg = li.config_inputs("c2_1024_bumps")
     n, omega, L, ext = cfg["n"], cfg["omega"], cfg["slabs"], 10
     log(f"workload n={n} omega={omega:.3f} L={L} theta={cfg['theta']:.4f}")
@@ -201,6 +216,21 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"plan created in {setup_s:.2f} s")
+    if args.mode == "slab":
+        lims = plan.slab_info(0, 1)
+        q = lims[3] - lims[2] + 1
+        bs = torch.randn(n * q, dtype=torch.complex128, device=dev)
+        xs = torch.empty_like(bs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.slab_reps):
+            plan.slab_solve(0, 1, bs, out=xs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.slab_reps
+        print(json.dumps({"mode": "slab", "q": q, "reps": args.slab_reps, "ms": dt * 1e3,
+                          "alg_bytes": slab_solve_bytes(n, q)}))
+        plan.close()
+        return
     uI = torch.from_numpy(cfg["uI"]).to(dev)
     f = plan.rhs_from_incident(uI)
     u = torch.empty_like(f)

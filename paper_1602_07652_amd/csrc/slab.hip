@@ -355,115 +355,148 @@ __global__ __launch_bounds__(NT) void k_step(C* __restrict__ x, const C* __restr
 
 // ---------------------------------------------------------------- batched
 // The same level steps for B right-hand sides x[b][n][q] (stride xs_b):
-// a workgroup takes one block (or one slice of its virtual columns, S per
-// block) and a tile of up to BT right-hand sides, stages the tile's input
-// vectors in LDS, and streams each matrix column once for the whole tile
-// (y(r, b) += M(r, c) x(c, b)): the factors are read once per tile instead
-// of once per right-hand side.  Threads: row r = tid % 128, right-hand sides
-// b = tid / 128, tid / 128 + 2, ...
+// y = sum_t M_t X_t with q x q factor blocks M_t and q x BT right-hand-side
+// panels X_t.  A workgroup of NT threads takes one block and a tile of BT
+// right-hand sides.  It stages the panels in LDS (coalesced along the
+// block's rows), then thread (r, g) = (tid % q, tid / q) multiplies row r of
+// the columns c = g, g + G, ... (G = NT / q groups) into BT accumulators:
+// every factor element is loaded once per tile, straight from memory into a
+// register (U loads in flight per thread), and the G partial sums are added
+// through LDS.  Three tile shapes trade factor re-reads (B / BT per block)
+// against parallelism on the upper levels, where there are few blocks.
 enum { BSTEP_FWD = 0, BSTEP_BWD = 1, BSTEP_LAST = 2, BSTEP_ODD0 = 3, BSTEP_BWD0 = 4 };
-// right-hand sides per tile: 8 (FP64) or 16 (FP32), i.e. 128 bytes per row
-template <typename C>
-struct BTile {
-  static constexpr int V = 128 / (int)sizeof(C);
+template <typename C, int BT, int NT>
+struct BShape {
+  static constexpr int XS = BT + 16 / (int)sizeof(C);  // padded panel row (complex entries)
+  static constexpr int U = 8;                           // factor loads in flight per thread
+  static constexpr int ROWS = (3 * kMaxQ > NT) ? 3 * kMaxQ : NT;
+  static constexpr size_t lds() { return (size_t)ROWS * XS * sizeof(C); }
+};
+// tile variants: index 0 widest (most right-hand sides per workgroup)
+template <typename C> struct BVariants;
+template <> struct BVariants<fcplx> {
+  static constexpr int BT[3] = {16, 8, 4};
+  static constexpr int NT[3] = {256, 512, 1024};
+};
+template <> struct BVariants<cplx> {
+  static constexpr int BT[3] = {8, 4, 2};
+  static constexpr int NT[3] = {256, 512, 1024};
 };
 
-template <typename C, int MODE>
-__global__ __launch_bounds__(256) void k_bstep(C* __restrict__ x, size_t xs_b, int B,
-                                               const C* __restrict__ m0, const C* __restrict__ m1,
-                                               const C* __restrict__ m2,
-                                               const C* __restrict__ coef, int n, int q, int nl,
-                                               int shift) {
-  constexpr int kBT = BTile<C>::V;
-  __shared__ C xs[3][kMaxQ][kBT];
-  const int blk = blockIdx.x;
-  const int b0 = blockIdx.y * kBT;
-  const int nbt = min(kBT, B - b0);
+// consecutive logical workgroups (the tiles of one block) on one XCD
+__device__ __forceinline__ int bstep_remap(int id, int total) {
+  const int per = total / 8;
+  if (per == 0 || id >= per * 8) return id;
+  return (id % 8) * per + id / 8;
+}
+
+template <typename C, int MODE, int BT, int NT>
+__global__ __launch_bounds__(NT) void k_bstep(C* __restrict__ x, size_t xs_b, int B,
+                                              const C* __restrict__ m0, const C* __restrict__ m1,
+                                              const C* __restrict__ m2,
+                                              const C* __restrict__ coef, int n, int q, int nl,
+                                              int shift, int tiles, int total) {
+  using S = BShape<C, BT, NT>;
+  constexpr int XS = S::XS, U = S::U;
+  extern __shared__ unsigned char lds_raw[];
+  C* xs = reinterpret_cast<C*>(lds_raw);  // panels [t][c][XS], later partial sums [g][r][XS]
+  const int lid = bstep_remap(blockIdx.x, total);
+  const int blk = lid / tiles;
+  const int b0 = (lid % tiles) * BT;
+  const int nbt = min(BT, B - b0);
   const size_t qq = (size_t)q * q;
   const int tid = threadIdx.x;
-  int k = 0, T = 0;
-  const C* M[3];
-  // stage inputs
-  for (int e = tid; e < q * nbt; e += 256) {
-    const int r = e % q, bb = e / q;
-    C* xb = x + (size_t)(b0 + bb) * xs_b;
-    if (MODE == BSTEP_FWD) {
-      const int kk = 2 * blk;
-      int t = 0;
-      if (kk >= 1) xs[t++][r][bb] = xb[((size_t)(kk - 1) << shift) * q + r];
-      if (kk + 1 < nl) xs[t][r][bb] = xb[((size_t)(kk + 1) << shift) * q + r];
-    } else if (MODE == BSTEP_BWD) {
-      const int kk = 2 * blk + 1;
-      xs[0][r][bb] = xb[((size_t)kk << shift) * q + r];
-      xs[1][r][bb] = tneg(xb[((size_t)(kk - 1) << shift) * q + r]);
-      if (kk + 1 < nl) xs[2][r][bb] = tneg(xb[((size_t)(kk + 1) << shift) * q + r]);
-    } else if (MODE == BSTEP_LAST) {
-      xs[0][r][bb] = xb[r];
-    } else if (MODE == BSTEP_ODD0) {
-      xs[0][r][bb] = xb[(size_t)(2 * blk + 1) * q + r];
-    } else {  // BWD0: t = L_k x_{k-1} + U_k x_{k+1}
-      const int kk = 2 * blk + 1;
-      const C* cf = coef + ((size_t)kk * q + r) * 9;
-      C acc = tmk<C>(0, 0);
-      for (int dZ = -1; dZ <= 1; ++dZ) {
-        const int rr = r + dZ;
-        if (rr < 0 || rr >= q) continue;
-        acc = tfma(cf[(dZ + 1) * 3 + 0], xb[(size_t)(kk - 1) * q + rr], acc);
-        if (kk + 1 < n) acc = tfma(cf[(dZ + 1) * 3 + 2], xb[(size_t)(kk + 1) * q + rr], acc);
-      }
-      xs[0][r][bb] = acc;
-    }
-  }
+  // panel rows (global row index, sign) and factor blocks per mode
+  int T = 0, k = 0;
+  int row[3] = {0, 0, 0};
+  bool neg[3] = {false, false, false};
+  const C* M[3] = {nullptr, nullptr, nullptr};
   if (MODE == BSTEP_FWD) {
     k = 2 * blk;
-    if (k >= 1) M[T++] = m0 + blk * qq;
-    if (k + 1 < nl) M[T++] = m1 + blk * qq;
+    if (k >= 1) { row[T] = (k - 1) << shift; M[T++] = m0 + blk * qq; }
+    if (k + 1 < nl) { row[T] = (k + 1) << shift; M[T++] = m1 + blk * qq; }
   } else if (MODE == BSTEP_BWD) {
     k = 2 * blk + 1;
-    M[0] = m0 + blk * qq;
-    M[1] = m1 + blk * qq;
-    M[2] = m2 + blk * qq;
-    T = (k + 1 < nl) ? 3 : 2;
+    row[0] = k << shift; M[0] = m0 + blk * qq;
+    row[1] = (k - 1) << shift; neg[1] = true; M[1] = m1 + blk * qq;
+    T = 2;
+    if (k + 1 < nl) { row[2] = (k + 1) << shift; neg[2] = true; M[2] = m2 + blk * qq; T = 3; }
   } else if (MODE == BSTEP_LAST) {
-    k = 0;
-    M[0] = m0;
-    T = 1;
-  } else {
-    k = 2 * blk + 1;
-    M[0] = m0 + blk * qq;
-    T = 1;
+    k = 0; row[0] = 0; M[0] = m0; T = 1;
+  } else {  // ODD0, BWD0 (level 0)
+    k = 2 * blk + 1; row[0] = k; M[0] = m0 + blk * qq; T = 1;
+  }
+  // stage panels: element e -> (t, bb, c), c fastest (coalesced)
+  const int per_t = q * nbt;
+  for (int e = tid; e < T * per_t; e += NT) {
+    const int t = e / per_t, rem = e - t * per_t;
+    const int bb = rem / q, c = rem - bb * q;
+    const C* xb = x + (size_t)(b0 + bb) * xs_b;
+    C v;
+    if (MODE == BSTEP_BWD0) {  // L_k x_{k-1} + U_k x_{k+1} from the stencil coefficients
+      const C* cf = coef + ((size_t)k * q + c) * 9;
+      v = tmk<C>(0, 0);
+      for (int dZ = -1; dZ <= 1; ++dZ) {
+        const int rr = c + dZ;
+        if (rr < 0 || rr >= q) continue;
+        v = tfma(cf[(dZ + 1) * 3 + 0], xb[(size_t)(k - 1) * q + rr], v);
+        if (k + 1 < n) v = tfma(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr], v);
+      }
+    } else {
+      v = xb[(size_t)row[t] * q + c];
+      if (neg[t]) v = tneg(v);
+    }
+    xs[((size_t)t * kMaxQ + c) * XS + bb] = v;
+  }
+  for (int e = tid; e < T * q * (BT - nbt); e += NT) {  // unused right-hand-side slots
+    const int tc = e / (BT - nbt);
+    xs[(size_t)((tc / q) * kMaxQ + tc % q) * XS + nbt + e % (BT - nbt)] = tmk<C>(0, 0);
   }
   __syncthreads();
-  const int v0 = 0, v1 = T * q;
-  const int r = tid & 127, bh = tid >> 7;
-  C acc[kBT / 2];
+  const int G = NT / q;
+  const int r = tid % q, g = tid / q;
+  const bool act = g < G;
+  C acc[BT];
 #pragma unroll
-  for (int j = 0; j < kBT / 2; ++j) acc[j] = tmk<C>(0, 0);
-  if (r < q) {
-    int t = v0 / q, c = v0 % q;
-#pragma unroll 4
-    for (int vc = v0; vc < v1; ++vc) {
-      const C mv = M[t][(size_t)c * q + r];
+  for (int j = 0; j < BT; ++j) acc[j] = tmk<C>(0, 0);
+  if (act) {
+    for (int t = 0; t < T; ++t) {
+      const C* Mt = M[t] + r;
+      const C* Xt = xs + (size_t)t * kMaxQ * XS;
+      for (int c0 = g; c0 < q; c0 += U * G) {
+        C mv[U];
 #pragma unroll
-      for (int j = 0; j < kBT / 2; ++j) {
-        const int bb = bh + 2 * j;
-        if (bb < nbt) acc[j] = tfma(mv, xs[t][c][bb], acc[j]);
+        for (int u = 0; u < U; ++u) {
+          const int c = c0 + u * G;
+          mv[u] = c < q ? Mt[(size_t)c * q] : tmk<C>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int c = min(c0 + u * G, q - 1);  // mv is zero past the end
+          const C* xr = Xt + (size_t)c * XS;
+#pragma unroll
+          for (int j = 0; j < BT; ++j) acc[j] = tfma(mv[u], xr[j], acc[j]);
+        }
       }
-      if (++c == q) { c = 0; ++t; }
     }
   }
-  const size_t okq = ((MODE == BSTEP_FWD || MODE == BSTEP_BWD) ? ((size_t)k << shift) : (size_t)k) * q;
-  if (r < q)
+  __syncthreads();  // panels consumed; reuse LDS for the partial sums
+  if (act) {
 #pragma unroll
-    for (int j = 0; j < kBT / 2; ++j) {
-      const int bb = bh + 2 * j;
-      if (bb >= nbt) continue;
-      C* o = x + (size_t)(b0 + bb) * xs_b + okq + r;
-      if (MODE == BSTEP_FWD || MODE == BSTEP_BWD0)
-        *o = tsub(*o, acc[j]);
-      else
-        *o = acc[j];
-    }
+    for (int j = 0; j < BT; ++j) xs[(size_t)tid * XS + j] = acc[j];
+  }
+  __syncthreads();
+  const size_t okq = (size_t)(MODE == BSTEP_FWD || MODE == BSTEP_BWD ? (k << shift) : k) * q;
+  for (int e = tid; e < per_t; e += NT) {
+    const int bb = e / q, rr = e - bb * q;
+    C sum = tmk<C>(0, 0);
+    for (int gg = 0; gg < G; ++gg) sum = tadd(sum, xs[(size_t)(gg * q + rr) * XS + bb]);
+    C* o = x + (size_t)(b0 + bb) * xs_b + okq + rr;
+    if (MODE == BSTEP_FWD || MODE == BSTEP_BWD0)
+      *o = tsub(*o, sum);
+    else
+      *o = sum;
+  }
 }
 
 template <typename C>
@@ -628,6 +661,36 @@ hipError_t set_lds(K kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Launch of one batched level step: the widest tile shape that still gives
+// at least two workgroups per CU, never wider than the batch needs.
+template <typename C, int MODE, int V>
+static void bstep_go(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C* a1, const C* a2,
+                     const C* coef, int q, int nl, int shift, int nb) {
+  constexpr int BT = BVariants<C>::BT[V], NT = BVariants<C>::NT[V];
+  const int tiles = (B + BT - 1) / BT;
+  const int total = nb * tiles;
+  k_bstep<C, MODE, BT, NT><<<total, NT, BShape<C, BT, NT>::lds(), p->stream>>>(
+      x, xs_b, B, a0, a1, a2, coef, p->n, q, nl, shift, tiles, total);
+}
+
+template <typename C, int MODE>
+static void bstep(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C* a1, const C* a2,
+                  const C* coef, int q, int nl, int shift, int nb) {
+  using V = BVariants<C>;
+  int v = 2;
+  for (int i = 0; i < 2; ++i) {
+    if (V::BT[i + 1] >= B) continue;  // a narrower tile already holds the batch
+    if ((long)nb * ((B + V::BT[i] - 1) / V::BT[i]) >= 512) { v = i; break; }
+    v = i + 1;
+  }
+  if (v == 0)
+    bstep_go<C, MODE, 0>(p, x, xs_b, B, a0, a1, a2, coef, q, nl, shift, nb);
+  else if (v == 1)
+    bstep_go<C, MODE, 1>(p, x, xs_b, B, a0, a1, a2, coef, q, nl, shift, nb);
+  else
+    bstep_go<C, MODE, 2>(p, x, xs_b, B, a0, a1, a2, coef, q, nl, shift, nb);
 }
 
 struct PtrBatch {
@@ -979,30 +1042,30 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
                                 size_t xs_b, int B) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
-  constexpr int kBT = BTile<C>::V;
-  const int tiles = (B + kBT - 1) / kBT;
-  auto launch = [&](auto kern, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
-    kern<<<dim3(nb, tiles), 256, 0, p->stream>>>(x, xs_b, B, a0, a1, a2, coef, n, q, nl, shift);
-  };
   if (nlev == 1) {
-    launch(k_bstep<C, BSTEP_LAST>, 1, fac + s.levels[0].off_dinv, nullptr, nullptr, 1, 0);
+    bstep<C, BSTEP_LAST>(p, x, xs_b, B, fac + s.levels[0].off_dinv, nullptr, nullptr, coef, q, 1,
+                         0, 1);
     LS_HIP(hipGetLastError());
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
-  launch(k_bstep<C, BSTEP_ODD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  bstep<C, BSTEP_ODD0>(p, x, xs_b, B, fac + L0.off_dinv, nullptr, nullptr, coef, q, L0.nl, 0,
+                       L0.nl / 2);
   k_fwd0_even_b<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, B), 128, 0, p->stream>>>(x, xs_b, coef, n, q);
   for (int l = 1; l < nlev - 1; ++l) {
     const SlabLevel& L = s.levels[l];
-    launch(k_bstep<C, BSTEP_FWD>, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
+    bstep<C, BSTEP_FWD>(p, x, xs_b, B, fac + L.off_pm, fac + L.off_pp, nullptr, coef, q, L.nl, l,
+                        (L.nl + 1) / 2);
   }
-  launch(k_bstep<C, BSTEP_LAST>, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
+  bstep<C, BSTEP_LAST>(p, x, xs_b, B, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, coef,
+                       q, 1, 0, 1);
   for (int l = nlev - 2; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
-    launch(k_bstep<C, BSTEP_BWD>, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu,
-           L.nl, l);
+    bstep<C, BSTEP_BWD>(p, x, xs_b, B, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu,
+                        coef, q, L.nl, l, L.nl / 2);
   }
-  launch(k_bstep<C, BSTEP_BWD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  bstep<C, BSTEP_BWD0>(p, x, xs_b, B, fac + L0.off_dinv, nullptr, nullptr, coef, q, L0.nl, 0,
+                       L0.nl / 2);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
