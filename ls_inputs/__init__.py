@@ -28,6 +28,9 @@ __all__ = [
     "random_complex",
     "CONFIGS",
     "config_inputs",
+    "fno_param_sizes",
+    "fno_initial_parameters",
+    "fno_sample_recipe",
 ]
 
 
@@ -139,3 +142,46 @@ def config_inputs(name: str):
         raise KeyError(name)
     cfg.update(h=1.0 / n, m=m, theta=theta, uI=plane_wave(n, cfg["omega"], theta))
     return cfg
+
+
+# ---------------------------------------------------------------- learned part
+# Flat parameter vector of the Fourier-neural-operator preconditioner, in
+# order: lift weight [W][5], lift bias [W]; per Fourier layer l: spectral
+# weights real part [2M][M][W][W], imaginary part [2M][M][W][W], pointwise
+# weight [W][W], bias [W]; projection 1 weight [Hd][W], bias [Hd];
+# projection 2 weight [2][Hd], bias [2].
+def fno_param_sizes(width=32, modes=16, layers=4, hidden=128):
+    """(kind, fan_in, size) of each block of the flat vector, in order."""
+    sizes = [("affine", 5, width * 5), ("bias", 5, width)]
+    for _ in range(layers):
+        sizes += [("spectral", width, 2 * modes * modes * width * width),
+                  ("spectral", width, 2 * modes * modes * width * width),
+                  ("affine", width, width * width), ("bias", width, width)]
+    sizes += [("affine", width, hidden * width), ("bias", width, hidden),
+              ("last", hidden, 2 * hidden), ("lastbias", hidden, 2)]
+    return sizes
+
+
+def fno_initial_parameters(seed: int, width=32, modes=16, layers=4, hidden=128):
+    """Seeded initial weights, float64: affine maps and biases uniform in
+    +-1/sqrt(fan_in), spectral weights uniform in [0, 1) / width^2, and the
+    last projection scaled by 1e-2 (the network starts close to z = r)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for kind, fan_in, size in fno_param_sizes(width, modes, layers, hidden):
+        if kind == "spectral":
+            parts.append(rng.random(size) / width**2)
+        else:
+            a = 1.0 / np.sqrt(fan_in)
+            scale = 1e-2 if kind.startswith("last") else 1.0
+            parts.append(scale * rng.uniform(-a, a, size))
+    return np.concatenate(parts)
+
+
+def fno_sample_recipe(seed: int, n: int = 256):
+    """One training / test sample of the learned preconditioner: a Gaussian
+    random field medium (seed) and an incident angle theta ~ U[0, 2 pi) drawn
+    from the same seed.  Returns (m, theta)."""
+    m = gaussian_random_field_medium(n, seed=seed)
+    theta = float(np.random.default_rng(10_000_000 + seed).uniform(0.0, 2 * np.pi))
+    return m, theta

@@ -23,8 +23,10 @@ krylov    right-preconditioned GMRES and flexible GMRES.
 solver    Alg. 3 (the Lippmann-Schwinger preconditioner) and the outer
           solve; dense reference solve.
 disk      closed-form Bessel series for a homogeneous disk.
+fno       the Fourier-neural-operator preconditioner / warm start: forward,
+          analytic adjoint, relative loss, Adam.
 
 Parity status: every function is pinned by a CPU test against something other
 than itself (closed forms, brute force, invariants); see tests/test_oracle_*.py.
 """
-from . import kernel, sparsify, slabs, krylov, solver, disk  # noqa: F401
+from . import kernel, sparsify, slabs, krylov, solver, disk, fno  # noqa: F401
