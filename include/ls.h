@@ -91,6 +91,7 @@ typedef struct {
   double relres_true;     /* ||f - H u|| / ||f|| recomputed in FP64 at exit */
   int converged;          /* 1 if relres_est <= tol */
   double t_ms;            /* wall time of this right-hand side */
+  int fno_flags;          /* ls_solve_fno only: LS_FNO_* bits of ls_fno.h, else 0 */
 } ls_solve_info;
 
 /* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,

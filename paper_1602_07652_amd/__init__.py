@@ -51,6 +51,7 @@ class SolveInfo(ctypes.Structure):
         ("outer_its", ctypes.c_int), ("inner_its_total", ctypes.c_int),
         ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double),
         ("converged", ctypes.c_int), ("t_ms", ctypes.c_double),
+        ("fno_flags", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -95,6 +96,22 @@ def lib():
         "ls_bidirectional": (_i, [_vp, _vp, _vp]),
         "ls_solve_multi": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                 ctypes.POINTER(_i), _d, ctypes.POINTER(ctypes.POINTER(SolveInfo))]),
+        "ls_fno_param_count": (ctypes.c_size_t, []),
+        "ls_fno_create": (_i, [ctypes.POINTER(_vp), _i, _i, _vp]),
+        "ls_fno_destroy": (_i, [_vp]),
+        "ls_fno_set_params": (_i, [_vp, _vp]),
+        "ls_fno_get_params": (_i, [_vp, _vp]),
+        "ls_fno_make_inputs": (_i, [_vp, _i, _i, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp]),
+        "ls_fno_forward": (_i, [_vp, _i, _i, _vp, _vp, _i]),
+        "ls_fno_loss": (_i, [_vp, _i, _i, _vp, _vp, _vp, ctypes.POINTER(_d)]),
+        "ls_fno_backward": (_i, [_vp, _i, _i, _vp, _vp]),
+        "ls_fno_adam": (_i, [_vp, _vp, _d, _d, _d, _d, _i]),
+        "ls_fno_apply": (_i, [_vp, _i, _i, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+        "ls_bf16_gemm": (_i, [_i, _i, _i, _i, _vp, ctypes.c_longlong, ctypes.c_longlong,
+                              ctypes.c_longlong, _vp, ctypes.c_longlong, ctypes.c_longlong,
+                              ctypes.c_longlong, _vp, ctypes.c_longlong, ctypes.c_longlong,
+                              ctypes.c_longlong, ctypes.c_float, ctypes.c_float, _vp]),
+        "ls_solve_fno": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(SolveInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -273,6 +290,126 @@ class Plan:
         N = self.n * self.n
         _check("ls_bidirectional", lib().ls_bidirectional(self.handle, _ptr(g, N, "g"), _ptr(out, N, "v")))
         return out
+
+    def solve_fno(self, fno, uI, f, tol=1e-8, mode=3, out=None, allow_noconv=False):
+        """ls_solve_fno: solve with the network as warm start (mode bit 1)
+        and / or flexible-GMRES preconditioner (bit 2), plain BD fallback."""
+        b = self._batch(f)
+        out = torch.empty_like(f) if out is None else out
+        N = self.n * self.n * b
+        infos = (SolveInfo * b)()
+        code = lib().ls_solve_fno(self.handle, fno.handle, _ptr(uI, N, "uI"), _ptr(f, N, "f"),
+                                  _ptr(out, N, "u"), b, float(tol), int(mode), infos)
+        if not (allow_noconv and code == 4):
+            _check("ls_solve_fno", code)
+        return out, [i.as_dict() for i in infos]
+
+
+LS_FNO_WARM, LS_FNO_PREC = 1, 2
+LS_FNO_WARM_USED, LS_FNO_WARM_REJECTED, LS_FNO_PREC_USED, LS_FNO_PREC_FALLBACK = 1, 2, 4, 8
+
+
+def fno_param_count() -> int:
+    return int(lib().ls_fno_param_count())
+
+
+class Fno:
+    """The learned preconditioner: ls_fno_create ... ls_fno_destroy.
+
+    Parameters and activations live on the device; every method enqueues the
+    library's kernels on the handle's stream (the current torch stream of
+    `device` at creation)."""
+
+    def __init__(self, max_batch: int, max_n: int, device="cuda:0"):
+        self.device = torch.device(device)
+        self.max_batch, self.max_n = int(max_batch), int(max_n)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check("ls_fno_create", lib().ls_fno_create(ctypes.byref(h), self.max_batch, self.max_n,
+                                                    ctypes.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+        self.nparams = fno_param_count()
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().ls_fno_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: torch.Tensor):
+        _check("ls_fno_set_params", lib().ls_fno_set_params(
+            self.handle, _ptr(params, self.nparams, "params", torch.float32)))
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check("ls_fno_get_params", lib().ls_fno_get_params(self.handle, _ptr(out, self.nparams, "params",
+                                                                               torch.float32)))
+        return out
+
+    def make_inputs(self, m, uI, r, shared_medium=True):
+        S, n = r.shape[0], r.shape[-1]
+        P = n * n
+        x = torch.empty((S, 5, n, n), dtype=torch.float32, device=self.device)
+        s = torch.empty(S, dtype=torch.float64, device=self.device)
+        _check("ls_fno_make_inputs", lib().ls_fno_make_inputs(
+            self.handle, n, S, _ptr(m, P if shared_medium else S * P, "m", torch.float64),
+            0 if shared_medium else P, _ptr(uI, S * P, "uI"), _ptr(r, S * P, "r"),
+            _ptr(x, S * 5 * P, "x", torch.float32), _ptr(s, S, "s", torch.float64)))
+        return x, s
+
+    def forward(self, x, keep=False, out=None):
+        S, n = x.shape[0], x.shape[-1]
+        y = torch.empty((S, 2, n, n), dtype=torch.float32, device=self.device) if out is None else out
+        _check("ls_fno_forward", lib().ls_fno_forward(
+            self.handle, n, S, _ptr(x, S * 5 * n * n, "x", torch.float32),
+            _ptr(y, S * 2 * n * n, "y", torch.float32), int(bool(keep))))
+        return y
+
+    def loss(self, y, target, dy=None):
+        S, n = y.shape[0], y.shape[-1]
+        dy = torch.empty_like(y) if dy is None else dy
+        L = _d()
+        Q = S * 2 * n * n
+        _check("ls_fno_loss", lib().ls_fno_loss(
+            self.handle, n, S, _ptr(y, Q, "y", torch.float32), _ptr(target, Q, "target", torch.float32),
+            _ptr(dy, Q, "dy", torch.float32), ctypes.byref(L)))
+        return L.value, dy
+
+    def backward(self, dy, grad=None):
+        S, n = dy.shape[0], dy.shape[-1]
+        grad = torch.empty(self.nparams, dtype=torch.float32, device=self.device) if grad is None else grad
+        _check("ls_fno_backward", lib().ls_fno_backward(
+            self.handle, n, S, _ptr(dy, S * 2 * n * n, "dy", torch.float32),
+            _ptr(grad, self.nparams, "grad", torch.float32)))
+        return grad
+
+    def adam(self, grad, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check("ls_fno_adam", lib().ls_fno_adam(self.handle, _ptr(grad, self.nparams, "grad", torch.float32),
+                                                float(lr), float(beta1), float(beta2), float(eps), int(t)))
+
+    def apply(self, m, uI, r, out=None):
+        S = Plan._batch(r)
+        n = r.shape[-1]
+        out = torch.empty_like(r) if out is None else out
+        P = n * n
+        _check("ls_fno_apply", lib().ls_fno_apply(
+            self.handle, n, S, _ptr(m, P, "m", torch.float64), 0, _ptr(uI, S * P, "uI"),
+            _ptr(r, S * P, "r"), _ptr(out, S * P, "z")))
+        return out
+
+
+def bf16_gemm(A, B, C, M, N, K, batch, sa, sb, sc, alpha=1.0, beta=0.0, stream=None):
+    """ls_bf16_gemm on float32 device tensors; sa = (sam, sak, sab) etc."""
+    st = torch.cuda.current_stream(A.device) if stream is None else stream
+    _check("ls_bf16_gemm", lib().ls_bf16_gemm(
+        M, N, K, batch, ctypes.c_void_p(A.data_ptr()), *sa, ctypes.c_void_p(B.data_ptr()), *sb,
+        ctypes.c_void_p(C.data_ptr()), *sc, float(alpha), float(beta), ctypes.c_void_p(st.cuda_stream)))
+    return C
 
 
 def solve_multi(plans, fs, tol=1e-8, outs=None):

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 OBJDIR = os.path.join(HERE, "_build")
 LIBNAME = "libls_mi355x.so"
-SOURCES = ["hankel.hip", "fft.hip", "stencil.hip", "slab.hip", "blas.hip", "api.cpp"]
+SOURCES = ["hankel.hip", "fft.hip", "stencil.hip", "slab.hip", "blas.hip", "fno.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

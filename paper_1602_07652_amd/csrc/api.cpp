@@ -88,7 +88,10 @@ ls_status fgmres(ls_plan* p, Op op, Prec prec, const T* b, T* x, int B, double t
   for (int i = 0; i < B; ++i) {
     active[i] = beta[i] > 0.0;
     nactive += active[i];
-    if (!active[i]) res[i].converged = true;
+    if (!active[i]) {  // zero right-hand side: x = 0 is exact; NaN: not converged
+      res[i].converged = beta[i] == 0.0;
+      res[i].relres = beta[i] == 0.0 ? 0.0 : beta[i];
+    }
     sc[i] = active[i] ? 1.0 / beta[i] : 0.0;
   }
   if (nactive == 0) return vec_zero(p, x, (size_t)B * N);
@@ -153,7 +156,9 @@ ls_status fgmres(ls_plan* p, Op op, Prec prec, const T* b, T* x, int B, double t
       res[i].iters = j + 1;
       res[i].relres = rel;
       res[i].converged = rel <= tol;
-      if ((fixed == 0 && rel <= tol) || rel <= 1e-15 || hn[i] == 0.0) {
+      // stop: converged, Krylov space exhausted, or a non-finite value
+      // (the right-hand side stays unconverged)
+      if ((fixed == 0 && rel <= tol) || rel <= 1e-15 || hn[i] == 0.0 || !std::isfinite(rel)) {
         active[i] = 0;
         --nactive;
       }
@@ -356,6 +361,94 @@ static ls_status true_residual(ls_plan* p, const cplx* f, const cplx* u, cplx* r
   for (int i = 0; i < B; ++i) rel[i] = nf[i] > 0 ? nr[i] / nf[i] : 0.0;
   return LS_OK;
 }
+
+
+// ------------------------------------------------------- correction solves
+// X = u + back_i d_i with d_i ~ H^{-1} (scale_i r_i): flexible GMRES in the
+// plan's precision (at most maxit iterations, relative tolerance tgt) with
+// the preconditioner pr64 (FP64 plans) or pr32 (FP32 plans).  A right-hand
+// side with scale 0 gets d = 0.  X must not alias u or r.
+template <class Pr64, class Pr32>
+static ls_status correction(ls_plan* p, const cplx* r, const cplx* u, cplx* X, int B,
+                            const std::vector<double>& scale, const std::vector<double>& back,
+                            double tgt, int maxit, Pr64 pr64, Pr32 pr32,
+                            std::vector<GmresResult>& res) {
+  const size_t N = (size_t)p->n * p->n;
+  if (p->fp32) {
+    F32Scratch sc;
+    LS_TRY(f32_scratch(p, sc));
+    LS_TRY(vec_to_f32_b(p, sc.a, r, scale.data(), N, B));
+    auto op = [&](const fcplx* in, fcplx* out, int nb) { return apply_H32(p, in, out, nb, 1.0, 1.0); };
+    LS_TRY(fgmres<fcplx>(p, op, pr32, sc.a, sc.b, B, tgt, maxit, 0, p->outerV32, p->outerZ32, res));
+    return vec_from_f32_b(p, X, u, sc.b, back.data(), N, B);
+  }
+  // vtmp slot 2 is free outside ls_solve's own loop (slot 0 is Alg. 2's
+  // residual, slot 1 the solve's residual)
+  cplx* rs = p->vtmp + 2 * (size_t)p->opt.max_batch * N;
+  LS_TRY(vec_scale_b(p, rs, r, scale.data(), N, B));
+  auto op = [&](const cplx* in, cplx* out, int nb) { return apply_H(p, in, out, nb, 1.0, 1.0); };
+  LS_TRY(fgmres<cplx>(p, op, pr64, rs, X, B, tgt, maxit, 0, p->outerV, p->outerZ, res));
+  LS_TRY(vec_scale_b(p, X, X, back.data(), N, B));
+  return vec_axpy(p, X, u, cmk(1.0, 0.0), N * B);
+}
+
+// Scales of one refinement step: active right-hand sides (rel > tol) get
+// their residual normalised and a target max(floor, 0.5 tol / rel); the
+// lockstep loop runs to the smallest target.
+static double refine_scales(const std::vector<double>& rel, const std::vector<double>& nf, double tol,
+                            double floor, std::vector<double>& scale, std::vector<double>& back) {
+  const int B = (int)rel.size();
+  scale.assign(B, 0.0);
+  back.assign(B, 0.0);
+  double tmin = 1.0;
+  for (int i = 0; i < B; ++i) {
+    if (!(rel[i] > tol)) continue;
+    const double nr = rel[i] * nf[i];
+    scale[i] = 1.0 / nr;
+    back[i] = nr;
+    tmin = std::min(tmin, std::max(floor, 0.5 * tol / rel[i]));
+  }
+  return tmin;
+}
+
+// Iterative refinement with the plan's two-level preconditioner from the
+// state (u, r = f - H u, rel = ||r|| / ||f||) until rel <= tol for every
+// right-hand side or max_refine steps; X is scratch for the candidate u.
+static ls_status refine_bd(ls_plan* p, const cplx* fb, cplx* ub, cplx* rbuf, cplx* X, int B, double tol,
+                           const std::vector<double>& nf, std::vector<double>& rel,
+                           std::vector<int>& outer_total, std::vector<int>& inner_total) {
+  const size_t N = (size_t)p->n * p->n;
+  auto bd = [&](auto tag) {
+    using T = decltype(tag);
+    return [&, p](const T* in, T* out, int nb) -> ls_status {
+      std::vector<GmresResult> r;
+      ls_status st = precond_batch<T>(p, in, out, nb, r);
+      for (int i = 0; i < nb; ++i) inner_total[i] += r[i].iters;
+      return st;
+    };
+  };
+  for (int it = 0; it < p->opt.max_refine; ++it) {
+    std::vector<double> scale, back;
+    const double tgt = refine_scales(rel, nf, tol, p->fp32 ? p->opt.lowp_tol : 0.0, scale, back);
+    bool done = true;
+    for (int i = 0; i < B; ++i) done = done && !(rel[i] > tol);
+    if (done) break;
+    std::vector<GmresResult> res;
+    LS_TRY(correction(p, rbuf, ub, X, B, scale, back, tgt, p->opt.max_outer, bd(cplx{}), bd(fcplx{}), res));
+    for (int i = 0; i < B; ++i) outer_total[i] += scale[i] > 0 ? res[i].iters : 0;
+    LS_TRY(vec_copy(p, ub, X, N * B));
+    LS_TRY(true_residual(p, fb, ub, rbuf, B, nf, rel));
+  }
+  return LS_OK;
+}
+
+// Sets the stream of a network handle for the lifetime of a solve.
+struct FnoStreamGuard {
+  ls_fno* f;
+  hipStream_t old;
+  FnoStreamGuard(ls_fno* f_, hipStream_t s) : f(f_), old(fno_swap_stream(f_, s)) {}
+  ~FnoStreamGuard() { fno_swap_stream(f, old); }
+};
 
 extern "C" {
 
@@ -738,6 +831,7 @@ ls_status ls_solve(ls_plan* p, const double* f, double* u, int batch, double tol
         I.relres_true = rel[i];
         I.converged = conv[i] ? 1 : 0;
         I.t_ms = ms / B;
+        I.fno_flags = 0;
       }
     }
   }
@@ -779,6 +873,111 @@ ls_status ls_solve_multi(ls_plan* const* plans, int count, const double* const* 
       g_last_error = "plan " + std::to_string(i) + ": " + msg[i];
     }
   return worst;
+}
+
+ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f, double* u, int batch,
+                       double tol, int mode, ls_solve_info* info) {
+  if (!p || !fn || !uI || !f || !u || batch < 1 || f == u || !(tol > 0) || mode < 0 ||
+      mode > (LS_FNO_WARM | LS_FNO_PREC)) {
+    ls_set_error("ls_solve_fno: bad arguments");
+    return LS_EINVAL;
+  }
+  if (p->n < 32 || p->n > fno_max_n(fn)) {
+    ls_set_error("ls_solve_fno: grid side outside the network's range [32, max_n]");
+    return LS_EINVAL;
+  }
+  DeviceGuard dg(p->device);
+  FnoStreamGuard sg(fn, p->stream);
+  const int n = p->n;
+  const size_t N = (size_t)n * n;
+  const size_t BN = (size_t)p->opt.max_batch * N;
+  // candidate solution X and its residual R2: FP32 plans have vtmp slots
+  // 0 and 2 free (their Alg. 2 runs in vtmp32); FP64 plans get two more
+  if (!p->fp32 && !p->solve_buf) LS_TRY(plan_alloc(p, (void**)&p->solve_buf, sizeof(cplx) * 2 * BN));
+  cplx* X = p->fp32 ? p->vtmp + 2 * BN : p->solve_buf;
+  cplx* R2 = p->fp32 ? p->vtmp : p->solve_buf + BN;
+  cplx* rbuf = p->vtmp + BN;
+  const int chunk = std::min(p->opt.max_batch, fno_max_batch(fn));
+  bool all = true;
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int B = std::min(chunk, batch - b0);
+    const auto t0 = std::chrono::steady_clock::now();
+    const cplx* fb = reinterpret_cast<const cplx*>(f) + b0 * N;
+    const double* uIb = uI + 2 * b0 * N;
+    cplx* ub = reinterpret_cast<cplx*>(u) + b0 * N;
+    std::vector<int> inner_total(B, 0), outer_total(B, 0), flags(B, 0);
+    std::vector<double> nf(B), rel(B, 0.0);
+    LS_TRY(vec_norms(p, fb, N, B, nf.data()));
+    if (mode & LS_FNO_WARM) {
+      LS_TRY(fno_residual_map<cplx>(fn, n, B, p->m, 0, uIb, fb, ub));  // u0 = f + s y
+      LS_TRY(true_residual(p, fb, ub, rbuf, B, nf, rel));
+      for (int i = 0; i < B; ++i) {
+        if (nf[i] > 0 && rel[i] < 1.0) {
+          flags[i] |= LS_FNO_WARM_USED;
+          continue;
+        }
+        flags[i] |= nf[i] > 0 ? LS_FNO_WARM_REJECTED : 0;
+        LS_TRY(vec_zero(p, ub + i * N, N));
+        LS_TRY(vec_copy(p, rbuf + i * N, fb + i * N, N));
+        rel[i] = nf[i] > 0 ? 1.0 : 0.0;
+      }
+    } else {
+      LS_TRY(vec_zero(p, ub, N * B));
+      LS_TRY(vec_copy(p, rbuf, fb, N * B));
+      for (int i = 0; i < B; ++i) rel[i] = nf[i] > 0 ? 1.0 : 0.0;
+    }
+    if (mode & LS_FNO_PREC) {
+      // one flexible-GMRES pass preconditioned by the network; kept per
+      // right-hand side only if it at least halves the residual
+      std::vector<double> scale, back;
+      const double tgt = refine_scales(rel, nf, tol, p->fp32 ? p->opt.lowp_tol : 0.0, scale, back);
+      const int maxit = std::max(2, p->opt.max_outer / 4);
+      auto net = [&](auto tag) {
+        using T = decltype(tag);
+        return [&, p](const T* in, T* out, int nb) -> ls_status {
+          return fno_residual_map<T>(fn, n, nb, p->m, 0, uIb, in, out);
+        };
+      };
+      std::vector<GmresResult> res;
+      LS_TRY(correction(p, rbuf, ub, X, B, scale, back, tgt, maxit, net(cplx{}), net(fcplx{}), res));
+      std::vector<double> rel2;
+      LS_TRY(true_residual(p, fb, X, R2, B, nf, rel2));
+      for (int i = 0; i < B; ++i) {
+        if (!(scale[i] > 0)) continue;
+        outer_total[i] += res[i].iters;
+        if (rel2[i] <= 0.5 * rel[i]) {
+          flags[i] |= LS_FNO_PREC_USED;
+          LS_TRY(vec_copy(p, ub + i * N, X + i * N, N));
+          LS_TRY(vec_copy(p, rbuf + i * N, R2 + i * N, N));
+          rel[i] = rel2[i];
+        } else {
+          flags[i] |= LS_FNO_PREC_FALLBACK;
+        }
+      }
+    }
+    LS_TRY(refine_bd(p, fb, ub, rbuf, X, B, tol, nf, rel, outer_total, inner_total));
+    LS_HIP(hipStreamSynchronize(p->stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < B; ++i) {
+      const bool conv = rel[i] <= tol;
+      all = all && conv;
+      if (info) {
+        ls_solve_info& I = info[b0 + i];
+        I.outer_its = outer_total[i];
+        I.inner_its_total = inner_total[i];
+        I.relres_est = rel[i];
+        I.relres_true = rel[i];
+        I.converged = conv ? 1 : 0;
+        I.t_ms = ms / B;
+        I.fno_flags = flags[i];
+      }
+    }
+  }
+  if (!all) {
+    ls_set_error("ls_solve_fno: hit max_refine before tol");
+    return LS_ENOCONV;
+  }
+  return LS_OK;
 }
 
 }  // extern "C"

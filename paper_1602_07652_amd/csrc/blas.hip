@@ -222,7 +222,8 @@ ls_status scale_b_t(ls_plan* p, T* y, const T* x, const double* s_host, size_t N
   ls_status vec_norms(ls_plan* p, const T* w, size_t N, int B, double* out_host) {                \
     std::vector<cplx> d(B);                                                                        \
     LS_TRY(multidot_t<T>(p, w, 1, 0, w, N, B, d.data()));                                          \
-    for (int b = 0; b < B; ++b) out_host[b] = sqrt(fmax(d[b].x, 0.0));                             \
+    for (int b = 0; b < B; ++b) /* NaN stays NaN: a poisoned vector must not look converged */     \
+      out_host[b] = std::isnan(d[b].x) ? d[b].x : sqrt(fmax(d[b].x, 0.0));                         \
     return LS_OK;                                                                                  \
   }                                                                                                \
   ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host) {                        \

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/ls.h"
+#include "../../include/ls_fno.h"
 
 typedef double2 cplx;
 typedef float2 fcplx;
@@ -196,6 +197,7 @@ struct ls_plan {
 
   bool own_stream = false;       // created by the plan (caller passed NULL)
   std::vector<GraphEntry> graphs;
+  cplx* solve_buf = nullptr;     // FP64 plans, learned solves: two grid-vector batches
   int col_variant64 = 0, col_variant32 = 0;  // autotuned FFT column-pass variants
   float tune_ms64[3] = {0, 0, 0}, tune_ms32[3] = {0, 0, 0};
 };
@@ -208,6 +210,15 @@ inline ApplyView<fcplx, float> view32(ls_plan* p) {
   return ApplyView<fcplx, float>{p->f32.m, p->f32.spec,   p->f32.tw, p->f32.fft_work,
                                  p->n,     p->spec_side,  p->stream, p->col_variant32};
 }
+
+// fno.hip: the network as a residual map z = r + s y(m, u_I, r / s) on the
+// handle's stream; the stream can be swapped for the duration of a solve.
+template <typename T>
+ls_status fno_residual_map(ls_fno* f, int n, int S, const double* m, size_t mstr, const double* uI,
+                           const T* r, T* z);
+hipStream_t fno_swap_stream(ls_fno* f, hipStream_t s);
+int fno_max_batch(const ls_fno* f);
+int fno_max_n(const ls_fno* f);
 
 // device memory helpers (record in plan->allocs)
 ls_status plan_alloc(ls_plan* p, void** ptr, size_t bytes);
