@@ -170,6 +170,73 @@ def batched_variant(tol, log_fn):
     return summary
 
 
+def learned_variant(tol, log_fn, weights):
+    """The learned form next to the plain batched form on the same job:
+    64 incident plane waves (theta_k = 2 pi k / 64) per medium on three
+    Gaussian-random-field media never seen in training (seeds 5000-5002) at
+    256^2, 512^2, 1024^2 (omega = 2 pi n / 10, 64 lines per layer), FP32
+    operator and slab solves with FP64 refinement, all grids at once.  Arm A:
+    ls_solve_multi (plain two-level preconditioner).  Arm B:
+    ls_solve_fno_multi with the trained network as warm start (mode 1).
+    Returns a summary of both arms."""
+    import numpy as np
+    import torch
+    import ls_inputs as li
+    from paper_1602_07652_amd import (Plan, Fno, LS_FP32_REFINE, LS_FNO_WARM, solve_multi,
+                                      solve_fno_multi)
+    from paper_1602_07652_amd.fno_train import load_weights
+    dev = torch.device("cuda:0")
+    params, meta = load_weights(weights)
+    sizes, seeds, B = [256, 512, 1024], [5000, 5001, 5002], 64
+    plans, nets, uIs, fs, us = [], [], [], [], []
+    for n, seed in zip(sizes, seeds):
+        st = torch.cuda.Stream()
+        omega = 2 * np.pi * n / 10
+        m = li.gaussian_random_field_medium(n, seed=seed)
+        with torch.cuda.stream(st):
+            p = Plan(n, 1.0 / n, omega, torch.from_numpy(m).to(dev), slabs=max(1, n // 64), ext=10,
+                     max_batch=B, precision=LS_FP32_REFINE)
+            net = Fno(max_batch=8, max_n=n)
+            net.set_params(params)
+            uI = torch.from_numpy(np.stack([li.plane_wave(n, omega, 2 * np.pi * k / B)
+                                            for k in range(B)])).to(dev)
+            fs.append(p.rhs_from_incident(uI))
+            uIs.append(uI)
+            us.append(torch.empty_like(fs[-1]))
+        plans.append(p)
+        nets.append(net)
+    torch.cuda.synchronize()
+    total = len(sizes) * B
+    arms = {}
+    for arm in ("plain", "learned"):
+        run = (lambda: solve_multi(plans, fs, tol=tol, outs=us)) if arm == "plain" else \
+              (lambda: solve_fno_multi(plans, nets, uIs, fs, tol=tol, mode=LS_FNO_WARM, outs=us))
+        run()                                   # warm-up: graphs, Krylov spaces
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infos = run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        arms[arm] = {
+            "wall_s": wall, "solves_per_s": total / wall,
+            "per_grid": [{"n": p.n,
+                          "outer_its_mean": float(np.mean([i["outer_its"] for i in inf])),
+                          "relres_true_max": max(i["relres_true"] for i in inf),
+                          "converged": all(i["converged"] for i in inf),
+                          "warm_kept": int(sum(1 for i in inf if i.get("fno_flags", 0) & 1))}
+                         for p, inf in zip(plans, infos)],
+        }
+        log_fn(f"learned-form job, {arm}: {total} solves in {wall:.3f} s = {total / wall:.1f} solves/s; "
+               f"{arms[arm]['per_grid']}")
+    for x in plans + nets:
+        x.close()
+    return {"workload": "64 plane waves x {256^2, 512^2, 1024^2} GRF media (held-out seeds 5000-5002), "
+                        "FP32+FP64 refinement, one stream per grid",
+            "solves": total, "weights_val_loss": meta["history"][-1]["val"],
+            "plain": arms["plain"], "learned": arms["learned"],
+            "speedup": arms["plain"]["wall_s"] / arms["learned"]["wall_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,7 +246,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--slab-reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 variant")
-    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched"],
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
+    ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
+    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned"],
                     help="profiling sub-runs: slab = only slab solves of the bench workload's "
                          "interior layer; copy = 1 GiB device copies (counter calibration); "
                          "batched = only the multi-grid variant")
@@ -205,6 +274,11 @@ def main():
         return
     if args.mode == "batched":
         print(json.dumps({"mode": "batched", "batched": batched_variant(args.tol, log)}))
+        return
+    from paper_1602_07652_amd.fno_train import DEFAULT_WEIGHTS
+    weights = args.weights or DEFAULT_WEIGHTS
+    if args.mode == "learned":
+        print(json.dumps({"mode": "learned", "learned": learned_variant(args.tol, log, weights)}))
         return
     cfg = li.config_inputs("c2_1024_bumps")
     n, omega, L, ext = cfg["n"], cfg["omega"], cfg["slabs"], 10
@@ -285,9 +359,11 @@ def main():
     log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic")
 
     plan.close()
-    batched = None
+    batched = learned = None
     if not args.no_batched:
         batched = batched_variant(args.tol, log)
+    if not args.no_learned and os.path.exists(weights):
+        learned = learned_variant(args.tol, log, weights)
 
     outer = float(np.mean([i["outer_its"] for i in infos]))
     inner = float(np.mean([i["inner_its_total"] for i in infos]))
@@ -331,7 +407,7 @@ def main():
             "ms_per_launch": slab_ms,
         },
         "cpu_baseline": cpu,
-        "variants": {"batched_fp32_multigrid": batched},
+        "variants": {"batched_fp32_multigrid": batched, "learned_fp32_multigrid": learned},
     }
     print(json.dumps(rec), flush=True)
 

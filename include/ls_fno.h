@@ -110,7 +110,8 @@ ls_status ls_fno_adam(ls_fno* f, const float* grad, double lr, double beta1, dou
 
 /* z = r + s (y_0 + i y_1) with y = network(make_inputs(m, uI, r)): the
  * network as a map from residuals to approximations of H^{-1} r.  z and r
- * complex FP64 [batch][n][n]; z may not alias r. */
+ * complex FP64 [batch][n][n]; z may not alias r.  Any batch >= 1: the
+ * network runs on max_batch vectors at a time. */
 ls_status ls_fno_apply(ls_fno* f, int n, int batch, const double* m, size_t m_stride,
                        const double* uI, const double* r, double* z);
 
@@ -130,9 +131,19 @@ ls_status ls_bf16_gemm(int M, int N, int K, int batch, const float* A, long long
  * residual is not below ||f|| is dropped; an FNO-preconditioned pass that
  * does not halve the residual within max_outer / 4 iterations is dropped
  * and the solve continues with BD.  info[b].fno_flags reports what
- * happened.  The plan's max_batch and n must fit the network's. */
+ * happened.  n must be in the network's range; the network is evaluated
+ * max_batch (its own) vectors at a time. */
 ls_status ls_solve_fno(ls_plan* p, ls_fno* f, const double* uI, const double* fvec, double* u,
                        int batch, double tol, int mode, ls_solve_info* info);
+
+/* Several media at once, as ls_solve_multi: one host thread per plan runs
+ * ls_solve_fno(plans[i], fnos[i], ...) on that plan's stream.  Plans,
+ * networks and streams must be distinct (a network handle is not
+ * re-entrant); uI[i], f[i], u[i] device arrays of batch[i] grid vectors,
+ * info[i] host arrays or info == NULL.  Returns the first failure. */
+ls_status ls_solve_fno_multi(ls_plan* const* plans, ls_fno* const* fnos, int count,
+                             const double* const* uI, const double* const* f, double* const* u,
+                             const int* batch, double tol, int mode, ls_solve_info* const* info);
 
 #ifdef __cplusplus
 }

@@ -112,6 +112,9 @@ def lib():
                               ctypes.c_longlong, _vp, ctypes.c_longlong, ctypes.c_longlong,
                               ctypes.c_longlong, ctypes.c_float, ctypes.c_float, _vp]),
         "ls_solve_fno": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(SolveInfo)]),
+        "ls_solve_fno_multi": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d, _i,
+                                    ctypes.POINTER(ctypes.POINTER(SolveInfo))]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -431,4 +434,25 @@ def solve_multi(plans, fs, tol=1e-8, outs=None):
     I = (ctypes.POINTER(SolveInfo) * k)(*[ctypes.cast(x, ctypes.POINTER(SolveInfo)) for x in infos])
     code = lib().ls_solve_multi(P, k, F, U, B, float(tol), I)
     _check("ls_solve_multi", code)
+    return outs, [[i.as_dict() for i in x] for x in infos]
+
+
+def solve_fno_multi(plans, fnos, uIs, fs, tol=1e-8, mode=LS_FNO_WARM, outs=None):
+    """ls_solve_fno_multi: ls_solve_fno on several plans concurrently, one
+    network handle per plan.  Returns (us, infos)."""
+    k = len(plans)
+    outs = [torch.empty_like(f) for f in fs] if outs is None else outs
+    bs = [Plan._batch(f) for f in fs]
+    for p, uI, f, u, b in zip(plans, uIs, fs, outs, bs):
+        for t, what in ((uI, "uI"), (f, "f"), (u, "u")):
+            _ptr(t, p.n * p.n * b, what)
+    P = (_vp * k)(*[p.handle.value for p in plans])
+    Fh = (_vp * k)(*[x.handle.value for x in fnos])
+    UI = (_vp * k)(*[t.data_ptr() for t in uIs])
+    F = (_vp * k)(*[t.data_ptr() for t in fs])
+    U = (_vp * k)(*[t.data_ptr() for t in outs])
+    B = (_i * k)(*bs)
+    infos = [(SolveInfo * b)() for b in bs]
+    I = (ctypes.POINTER(SolveInfo) * k)(*[ctypes.cast(x, ctypes.POINTER(SolveInfo)) for x in infos])
+    _check("ls_solve_fno_multi", lib().ls_solve_fno_multi(P, Fh, k, UI, F, U, B, float(tol), int(mode), I))
     return outs, [[i.as_dict() for i in x] for x in infos]

@@ -897,7 +897,7 @@ ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f
   cplx* X = p->fp32 ? p->vtmp + 2 * BN : p->solve_buf;
   cplx* R2 = p->fp32 ? p->vtmp : p->solve_buf + BN;
   cplx* rbuf = p->vtmp + BN;
-  const int chunk = std::min(p->opt.max_batch, fno_max_batch(fn));
+  const int chunk = p->opt.max_batch;  // the network runs in its own sub-batches
   bool all = true;
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int B = std::min(chunk, batch - b0);
@@ -978,6 +978,39 @@ ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f
     return LS_ENOCONV;
   }
   return LS_OK;
+}
+
+ls_status ls_solve_fno_multi(ls_plan* const* plans, ls_fno* const* fnos, int count, const double* const* uI,
+                             const double* const* f, double* const* u, const int* batch, double tol, int mode,
+                             ls_solve_info* const* info) {
+  if (!plans || !fnos || count < 1 || !uI || !f || !u || !batch) {
+    ls_set_error("ls_solve_fno_multi: bad arguments");
+    return LS_EINVAL;
+  }
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i; ++j)
+      if (plans[i] == plans[j] || fnos[i] == fnos[j] ||
+          (plans[i] && plans[j] && plans[i]->stream == plans[j]->stream)) {
+        ls_set_error("ls_solve_fno_multi: plans and networks must be distinct, streams distinct");
+        return LS_EINVAL;
+      }
+  std::vector<ls_status> st(count, LS_OK);
+  std::vector<std::string> msg(count);
+  std::vector<std::thread> th;
+  for (int i = 0; i < count; ++i)
+    th.emplace_back([&, i]() {
+      if (plans[i]) (void)hipSetDevice(plans[i]->device);
+      st[i] = ls_solve_fno(plans[i], fnos[i], uI[i], f[i], u[i], batch[i], tol, mode, info ? info[i] : nullptr);
+      msg[i] = g_last_error;
+    });
+  for (auto& t : th) t.join();
+  ls_status worst = LS_OK;
+  for (int i = 0; i < count; ++i)
+    if (st[i] != LS_OK && (worst == LS_OK || worst == LS_ENOCONV)) {
+      worst = st[i];
+      g_last_error = "plan " + std::to_string(i) + ": " + msg[i];
+    }
+  return worst;
 }
 
 }  // extern "C"

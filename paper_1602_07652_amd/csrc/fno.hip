@@ -789,16 +789,22 @@ ls_status check_sizes(const ls_fno* f, int n, int S) {
 
 }  // namespace
 
-// Residual map for the solver (complex type T): z = r + s (y0 + i y1).
+// Residual map for the solver (complex type T): z = r + s (y0 + i y1), for
+// any number S of vectors (the network runs on max_batch at a time).
 template <typename T>
 ls_status fno_residual_map(ls_fno* f, int n, int S, const double* m, size_t mstr, const double* uI, const T* r,
                            T* z) {
-  LS_TRY(check_sizes(f, n, S));
-  LS_TRY(make_inputs_t<T>(f, n, S, m, mstr, uI, r, f->x, f->s));
-  LS_TRY(forward(f, n, S, f->x, f->y, false));
+  if (S < 1) return LS_EINVAL;
+  LS_TRY(check_sizes(f, n, 1));
   const size_t P = (size_t)n * n;
-  k_output<T><<<dim3(grid_for(P, 256, 1024), S), 256, 0, f->stream>>>(r, f->y, f->s, z, P);
-  LS_HIP(hipGetLastError());
+  for (int b0 = 0; b0 < S; b0 += f->max_batch) {
+    const int B = std::min(f->max_batch, S - b0);
+    const T* rb = r + b0 * P;
+    LS_TRY(make_inputs_t<T>(f, n, B, m + b0 * mstr, mstr, uI + 2 * b0 * P, rb, f->x, f->s));
+    LS_TRY(forward(f, n, B, f->x, f->y, false));
+    k_output<T><<<dim3(grid_for(P, 256, 1024), B), 256, 0, f->stream>>>(rb, f->y, f->s, z + b0 * P, P);
+    LS_HIP(hipGetLastError());
+  }
   return LS_OK;
 }
 template ls_status fno_residual_map<cplx>(ls_fno*, int, int, const double*, size_t, const double*, const cplx*, cplx*);
