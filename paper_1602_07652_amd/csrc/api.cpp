@@ -682,14 +682,20 @@ ls_status ls_slab_solve(ls_plan* p, int orient, int slab, const double* b, doubl
   const size_t cnt = (size_t)p->n * s.q;
   const cplx* bb = reinterpret_cast<const cplx*>(b);
   cplx* xx = reinterpret_cast<cplx*>(x);
+  const size_t BN = (size_t)p->n * p->n * p->opt.max_batch;  // n*q <= one slot
   if (p->fp32) {
-    fcplx* t = p->vtmp32;  // n*q <= n*n
-    LS_TRY(vec_to_f32(p, t, bb, 1.0, cnt));
-    LS_TRY(slab_solve_frame(p, s, t));
-    return vec_from_f32(p, xx, nullptr, t, 1.0, cnt);
+    fcplx* gi = p->vtmp32;
+    fcplx* yo = p->vtmp32 + BN;
+    LS_TRY(vec_to_f32(p, gi, bb, 1.0, cnt));
+    LS_TRY(slab_solve(p, s, gi, yo, 1));
+    return vec_from_f32(p, xx, nullptr, yo, 1.0, cnt);
   }
-  LS_TRY(vec_copy(p, xx, bb, cnt));
-  return slab_solve_frame(p, s, xx);
+  if (bb == xx) {  // in place: solve from a copy
+    cplx* gi = p->vtmp;
+    LS_TRY(vec_copy(p, gi, bb, cnt));
+    return slab_solve(p, s, gi, xx, 1);
+  }
+  return slab_solve(p, s, bb, xx, 1);
 }
 
 ls_status ls_sweep(ls_plan* p, int orient, const double* g, double* v) {

@@ -178,9 +178,11 @@ struct ls_plan {
   std::vector<Slab> slabs[2];
   cplx* slab_work = nullptr;     // [n][qmax] scratch for one slab solve
   cplx* slab_work2 = nullptr;    // second scratch
+  cplx* slab_elim = nullptr;     // [n][qmax] eliminated right-hand sides of one solve
   cplx* vtmp = nullptr;          // grid vectors for Alg. 2 [3][n*n]
   fcplx* slab_work32 = nullptr;  // FP32 plans: the two slab scratch vectors
   fcplx* slab_work32b = nullptr;
+  fcplx* slab_elim32 = nullptr;
   fcplx* vtmp32 = nullptr;       // FP32 plans: grid vectors [3][n*n]
 
   // Krylov workspace (grid vectors), grown on demand
@@ -245,10 +247,10 @@ ls_status stencil_residual_C(ls_plan* p, const fcplx* g, const fcplx* u, fcplx* 
 ls_status stencils_to_f32(ls_plan* p);
 // slab.hip
 ls_status slabs_build(ls_plan* p);
-ls_status slab_solve_frame(ls_plan* p, Slab& s, cplx* x);        // in place on x [n][q]
-ls_status slab_solve_frame(ls_plan* p, Slab& s, fcplx* x);
-ls_status slab_solve_batch(ls_plan* p, Slab& s, cplx* x, int B);  // x [B][n][q]
-ls_status slab_solve_batch(ls_plan* p, Slab& s, fcplx* x, int B);
+// y = C_slab^{-1} g for B right-hand sides [B][n][q] in the slab frame;
+// g is not modified and must not alias y
+ls_status slab_solve(ls_plan* p, Slab& s, const cplx* g, cplx* y, int B);
+ls_status slab_solve(ls_plan* p, Slab& s, const fcplx* g, fcplx* y, int B);
 // B right-hand sides [B][n][n] at once
 ls_status sweep_apply(ls_plan* p, int orient, const cplx* g, cplx* v, bool accumulate, int B = 1);
 ls_status sweep_apply(ls_plan* p, int orient, const fcplx* g, fcplx* v, bool accumulate, int B = 1);

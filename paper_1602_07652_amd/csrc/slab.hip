@@ -237,120 +237,148 @@ __global__ __launch_bounds__(256) void k_gemm(const cplx* const* __restrict__ Ap
 }
 
 // ------------------------------------------------------------ solve kernels
-// Every level step is y = sum_t M_t x_t over up to three q x q column-major
-// matrices of one block (x_t staged in LDS).  The t*q "virtual columns" are
-// split evenly over the waves of the workgroup (rows over lanes), each lane
-// streams its slice of matrix columns with 8 independent loads in flight,
-// and the column splits are summed through LDS.  Levels with few blocks run
-// 1024-thread workgroups so that one block is read by 16 waves.
-template <typename C, int NT>
-struct GemvCtx {
-  int r, s, CS, v0, v1;
-  // virtual columns [base, base + len) of this workgroup
-  __device__ __forceinline__ GemvCtx(int q, int base, int len, int tid) {
-    const int RH = (q + 63) / 64;
-    CS = (NT / 64) / RH;
-    const int w = tid >> 6, lane = tid & 63;
-    r = (w % RH) * 64 + lane;
-    s = w / RH;
-    const int chunk = (len + CS - 1) / CS;
-    v0 = base + min(len, s * chunk);
-    v1 = base + min(len, s * chunk + chunk);
-  }
-  __device__ __forceinline__ GemvCtx(int q, int terms, int tid) : GemvCtx(q, 0, terms * q, tid) {}
-};
+// Single right-hand side.  The solve reads the right-hand side g, keeps the
+// eliminated right-hand sides of the even block rows in a scratch t, and
+// writes the solution to y (g, t, y: [n][q] slab frames), so no launch reads
+// a row it also writes: a block's output rows can then be split over
+// several workgroups.  Every level step is y_k = sum_t M_t x_t over up to
+// three q x q column-major matrices of block k.
+//
+// Workgroup (block, row tile): rows [r0, r0 + R) of the block, R = q / RS.
+// Thread (rl, grp) = (tid % R, tid / R) takes the virtual columns v = grp,
+// grp + G, ... (G = 256 / R) of the T*q columns and loads all its factor
+// elements (at most kRowCols) into registers before anything else, so a
+// level costs about one memory round trip however deep it is; the inputs
+// x_t are staged in LDS meanwhile and the G partial sums added in LDS.
+enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4 };
+constexpr int kRowCols = 24;
 
-template <typename C, int NT>
-__device__ __forceinline__ C gemv_terms(const GemvCtx<C, NT>& g, const C* const* M, const C* xs,
-                                        int q, C acc) {
-  if (g.r >= q || g.v0 >= g.v1) return acc;
-  int t = g.v0 / q, c = g.v0 % q;
-  int vc = g.v0;
-  for (; vc + 8 <= g.v1; vc += 8) {
-    C mv[8], xv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      mv[u] = M[t][(size_t)c * q + g.r];
-      xv[u] = xs[t * kMaxQ + c];
-      if (++c == q) { c = 0; ++t; }
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc = tfma(mv[u], xv[u], acc);
+// Row tiles per block for extended thickness q (the fewest with at most
+// kRowCols columns per thread when a step has three factor matrices).
+inline int row_splits(int q) {
+  for (int rs = 1; rs <= q; ++rs) {
+    const int R = (q + rs - 1) / rs, G = 256 / R;
+    if (G >= 1 && (3 * q + G - 1) / G <= kRowCols) return rs;
   }
-  for (; vc < g.v1; ++vc) {
-    acc = tfma(M[t][(size_t)c * q + g.r], xs[t * kMaxQ + c], acc);
-    if (++c == q) { c = 0; ++t; }
-  }
-  return acc;
+  return q;
 }
 
-// Sum of the column splits; the result is valid in threads tid < q.
-template <typename C, int NT>
-__device__ __forceinline__ C gemv_sum(const GemvCtx<C, NT>& g, C acc, C* part, int q) {
-  if (g.r < q) part[g.s * 128 + g.r] = acc;
-  __syncthreads();
-  C y = tmk<C>(0, 0);
-  if ((int)threadIdx.x < q)
-    for (int s = 0; s < g.CS; ++s) y = tadd(y, part[s * 128 + threadIdx.x]);
-  return y;
-}
-
-// One level step of blocks k (even: forward, odd: backward, or the single
-// last block): one workgroup per block; NT = 1024 for levels with few
-// blocks so that the block's matrices are streamed by 16 waves.  (Spreading
-// one block over several workgroups needs a device-scope fence per
-// workgroup to publish partial sums, which costs more than it saves here.)
-enum { STEP_FWD = 0, STEP_BWD = 1, STEP_LAST = 2 };
-
-template <typename C, int MODE, int NT>
-__global__ __launch_bounds__(NT) void k_step(C* __restrict__ x, const C* __restrict__ m0,
-                                             const C* __restrict__ m1, const C* __restrict__ m2,
-                                             int q, int nl, int shift) {
+// Modes (k: block row at this level, rows of level l are global rows k<<l):
+//   R_ODD0  level 0, k odd:  y_k = Dinv_k g_k
+//   R_FWD   level l, k even: t_k -= Pm_k t_{k-1} + Pp_k t_{k+1}
+//   R_LAST  top level:       y_0 = Dinv t_0
+//   R_BWD   level l, k odd:  y_k = Dinv_k t_k - (Dinv L)_k y_{k-1} - (Dinv U)_k y_{k+1}
+//   R_BWD0  level 0, k odd:  y_k -= Dinv_k (L_k y_{k-1} + U_k y_{k+1})  (L, U from coef)
+template <typename C, int MODE>
+__global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __restrict__ t, C* __restrict__ y,
+                                              const C* __restrict__ m0, const C* __restrict__ m1,
+                                              const C* __restrict__ m2, const C* __restrict__ coef, int n,
+                                              int q, int nl, int shift, int RS) {
   __shared__ C xs[3 * kMaxQ];
-  __shared__ C part[(NT / 64) * 128];
-  const int blk = blockIdx.x;
-  const size_t qq = (size_t)q * q;
+  __shared__ C part[256];
+  const int blk = blockIdx.x / RS, rs = blockIdx.x % RS;
+  const int R = (q + RS - 1) / RS, r0 = rs * R;
   const int tid = threadIdx.x;
-  int k, T = 0;
-  const C* M[3];
-  if (MODE == STEP_FWD) {
-    k = 2 * blk;
-    const bool hm = k >= 1, hp = k + 1 < nl;
-    if (tid < q) {
-      int t = 0;
-      if (hm) xs[(t++) * kMaxQ + tid] = x[((size_t)(k - 1) << shift) * q + tid];
-      if (hp) xs[t * kMaxQ + tid] = x[((size_t)(k + 1) << shift) * q + tid];
-    }
-    if (hm) M[T++] = m0 + blk * qq;
-    if (hp) M[T++] = m1 + blk * qq;
-  } else if (MODE == STEP_BWD) {
+  const int rl = tid % R, grp = tid / R, G = 256 / R;
+  const bool act = grp < G && r0 + rl < q;
+  const size_t qq = (size_t)q * q;
+  int k = 0, T = 1;
+  bool hm = false;
+  const C* M0 = nullptr;
+  const C* M1 = nullptr;
+  const C* M2 = nullptr;
+  if (MODE == R_ODD0 || MODE == R_BWD0) {
     k = 2 * blk + 1;
+    M0 = m0 + blk * qq;
+  } else if (MODE == R_FWD) {
+    k = 2 * blk;
+    hm = k >= 1;
     const bool hp = k + 1 < nl;
-    if (tid < q) {
-      xs[tid] = x[((size_t)k << shift) * q + tid];
-      xs[kMaxQ + tid] = tneg(x[((size_t)(k - 1) << shift) * q + tid]);
-      if (hp) xs[2 * kMaxQ + tid] = tneg(x[((size_t)(k + 1) << shift) * q + tid]);
+    T = (int)hm + (int)hp;
+    M0 = hm ? m0 + blk * qq : m1 + blk * qq;
+    M1 = m1 + blk * qq;
+  } else if (MODE == R_LAST) {
+    M0 = m0;
+  } else {  // R_BWD
+    k = 2 * blk + 1;
+    T = k + 1 < nl ? 3 : 2;
+    M0 = m0 + blk * qq;
+    M1 = m1 + blk * qq;
+    M2 = m2 + blk * qq;
+  }
+  const int V = T * q;
+  // factor elements first: every load of this thread in flight at once
+  C mv[kRowCols];
+#pragma unroll
+  for (int j = 0; j < kRowCols; ++j) {
+    const int v = grp + G * j;
+    mv[j] = tmk<C>(0, 0);
+    if (act && v < V) {
+      const int tt = v >= 2 * q ? 2 : (v >= q ? 1 : 0);
+      const C* Mt = tt == 0 ? M0 : (tt == 1 ? M1 : M2);
+      mv[j] = Mt[(size_t)(v - tt * q) * q + r0 + rl];
     }
-    M[0] = m0 + blk * qq;
-    M[1] = m1 + blk * qq;
-    M[2] = m2 + blk * qq;
-    T = hp ? 3 : 2;
-  } else {
-    k = 0;
-    if (tid < q) xs[tid] = x[tid];
-    M[0] = m0;
-    T = 1;
+  }
+  // inputs x_t (flat over the T*q virtual columns)
+  for (int e = tid; e < V; e += 256) {
+    const int tt = e >= 2 * q ? 2 : (e >= q ? 1 : 0), c = e - tt * q;
+    C v;
+    if (MODE == R_ODD0) {
+      v = g[(size_t)k * q + c];
+    } else if (MODE == R_FWD) {
+      const int row = (tt == 0 && hm) ? k - 1 : k + 1;
+      v = t[((size_t)row << shift) * q + c];
+    } else if (MODE == R_LAST) {
+      v = t[c];
+    } else if (MODE == R_BWD) {
+      if (tt == 0) v = t[((size_t)k << shift) * q + c];
+      else v = tneg(y[((size_t)(tt == 1 ? k - 1 : k + 1) << shift) * q + c]);
+    } else {  // R_BWD0
+      const C* cf = coef + ((size_t)k * q + c) * 9;
+      v = tmk<C>(0, 0);
+      for (int dZ = -1; dZ <= 1; ++dZ) {
+        const int rr = c + dZ;
+        if (rr < 0 || rr >= q) continue;
+        v = tfma(cf[(dZ + 1) * 3 + 0], y[(size_t)(k - 1) * q + rr], v);
+        if (k + 1 < n) v = tfma(cf[(dZ + 1) * 3 + 2], y[(size_t)(k + 1) * q + rr], v);
+      }
+    }
+    xs[e] = v;
   }
   __syncthreads();
-  const GemvCtx<C, NT> g(q, T, tid);
-  const C y = gemv_sum(g, gemv_terms(g, M, xs, q, tmk<C>(0, 0)), part, q);
-  const size_t o = ((size_t)k << shift) * q + tid;
-  if (tid < q) {
-    if (MODE == STEP_FWD)
-      x[o] = tsub(x[o], y);
-    else
-      x[o] = y;
+  C acc = tmk<C>(0, 0);
+#pragma unroll
+  for (int j = 0; j < kRowCols; ++j) acc = tfma(mv[j], xs[min(grp + G * j, V - 1)], acc);
+  part[tid] = acc;  // part[grp * R + rl]
+  __syncthreads();
+  if (tid < R && r0 + tid < q) {
+    C sum = tmk<C>(0, 0);
+    for (int gg = 0; gg < G; ++gg) sum = tadd(sum, part[gg * R + tid]);
+    const int r = r0 + tid;
+    if (MODE == R_ODD0) y[(size_t)k * q + r] = sum;
+    else if (MODE == R_FWD) { C* o = t + ((size_t)k << shift) * q + r; *o = tsub(*o, sum); }
+    else if (MODE == R_LAST) y[r] = sum;
+    else if (MODE == R_BWD) y[((size_t)k << shift) * q + r] = sum;
+    else { C* o = y + (size_t)k * q + r; *o = tsub(*o, sum); }
   }
+}
+
+// level 0, even blocks: t_k = g_k - L_k z_{k-1} - U_k z_{k+1} with z_j = y_j
+template <typename C>
+__global__ void k_even0(const C* __restrict__ g, const C* __restrict__ y, C* __restrict__ t,
+                        const C* __restrict__ coef, int n, int q) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = 2 * blockIdx.y;
+  if (r >= q) return;
+  const C* cf = coef + ((size_t)k * q + r) * 9;
+  C acc = g[(size_t)k * q + r];
+  for (int dZ = -1; dZ <= 1; ++dZ) {
+    const int rr = r + dZ;
+    if (rr < 0 || rr >= q) continue;
+    if (k >= 1) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 0], y[(size_t)(k - 1) * q + rr]));
+    if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], y[(size_t)(k + 1) * q + rr]));
+  }
+  t[(size_t)k * q + r] = acc;
 }
 
 // ---------------------------------------------------------------- batched
@@ -515,66 +543,6 @@ __global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restric
     if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr]));
   }
   xb[(size_t)k * q + r] = acc;
-}
-
-// level 0, odd blocks: z_k = Dinv_k b_k (in place)
-template <typename C, int NT>
-__global__ __launch_bounds__(NT) void k_fwd0_odd(C* __restrict__ x, const C* __restrict__ dinv, int q) {
-  __shared__ C xs[kMaxQ];
-  __shared__ C part[(NT / 64) * 128];
-  const int k = 2 * blockIdx.x + 1;
-  if ((int)threadIdx.x < q) xs[threadIdx.x] = x[(size_t)k * q + threadIdx.x];
-  __syncthreads();
-  const GemvCtx<C, NT> g(q, 1, threadIdx.x);
-  const C* M[1] = {dinv + blockIdx.x * (size_t)q * q};
-  const C y = gemv_sum(g, gemv_terms(g, M, xs, q, tmk<C>(0, 0)), part, q);
-  if ((int)threadIdx.x < q) x[(size_t)k * q + threadIdx.x] = y;
-}
-
-// level 0, even blocks: b_k -= L_k z_{k-1} + U_k z_{k+1} (L, U from coef)
-template <typename C>
-__global__ void k_fwd0_even(C* __restrict__ x, const C* __restrict__ coef, int n, int q) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = 2 * blockIdx.y;
-  if (r >= q) return;
-  const C* cf = coef + ((size_t)k * q + r) * 9;
-  C acc = x[(size_t)k * q + r];
-  for (int dZ = -1; dZ <= 1; ++dZ) {
-    const int rr = r + dZ;
-    if (rr < 0 || rr >= q) continue;
-    if (k >= 1) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 0], x[(size_t)(k - 1) * q + rr]));
-    if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], x[(size_t)(k + 1) * q + rr]));
-  }
-  x[(size_t)k * q + r] = acc;
-}
-
-// level 0, odd blocks: x_k = z_k - Dinv_k (L_k x_{k-1} + U_k x_{k+1})
-template <typename C, int NT>
-__global__ __launch_bounds__(NT) void k_bwd0(C* __restrict__ x, const C* __restrict__ dinv,
-                                             const C* __restrict__ coef, int n, int q) {
-  __shared__ C t[kMaxQ];
-  __shared__ C part[(NT / 64) * 128];
-  const int k = 2 * blockIdx.x + 1;
-  const int r = threadIdx.x;
-  if (r < q) {
-    const C* cf = coef + ((size_t)k * q + r) * 9;
-    C acc = tmk<C>(0, 0);
-    for (int dZ = -1; dZ <= 1; ++dZ) {
-      const int rr = r + dZ;
-      if (rr < 0 || rr >= q) continue;
-      acc = tfma(cf[(dZ + 1) * 3 + 0], x[(size_t)(k - 1) * q + rr], acc);
-      if (k + 1 < n) acc = tfma(cf[(dZ + 1) * 3 + 2], x[(size_t)(k + 1) * q + rr], acc);
-    }
-    t[r] = acc;
-  }
-  __syncthreads();
-  const GemvCtx<C, NT> g(q, 1, threadIdx.x);
-  const C* M[1] = {dinv + blockIdx.x * (size_t)q * q};
-  const C y = gemv_sum(g, gemv_terms(g, M, t, q, tmk<C>(0, 0)), part, q);
-  if ((int)threadIdx.x < q) {
-    const size_t o = (size_t)k * q + threadIdx.x;
-    x[o] = tsub(x[o], y);
-  }
 }
 
 // ------------------------------------------------------- sweep helpers
@@ -1016,25 +984,17 @@ ls_status slabs_build(ls_plan* p) {
     return LS_ESINGULAR;
   }
   const size_t wv = (size_t)n * qmax * p->opt.max_batch;
+  const size_t w1 = (size_t)n * qmax;  // single-right-hand-side elimination scratch
   if (p->fp32) {
     LS_TRY(plan_alloc(p, (void**)&p->slab_work32, wv * sizeof(fcplx)));
     LS_TRY(plan_alloc(p, (void**)&p->slab_work32b, wv * sizeof(fcplx)));
+    LS_TRY(plan_alloc(p, (void**)&p->slab_elim32, w1 * sizeof(fcplx)));
   } else {
     LS_TRY(plan_alloc(p, (void**)&p->slab_work, wv * sizeof(cplx)));
     LS_TRY(plan_alloc(p, (void**)&p->slab_work2, wv * sizeof(cplx)));
+    LS_TRY(plan_alloc(p, (void**)&p->slab_elim, w1 * sizeof(cplx)));
   }
   return LS_OK;
-}
-
-// Workgroup size per level: 256 threads when the level has many blocks,
-// 1024 when it has few (the deep levels are latency bound).
-template <typename C, int MODE>
-static void launch_step(ls_plan* p, int nb, C* x, const C* m0, const C* m1, const C* m2, int q,
-                        int nl, int shift) {
-  if (nb >= 128)
-    k_step<C, MODE, 256><<<nb, 256, 0, p->stream>>>(x, m0, m1, m2, q, nl, shift);
-  else
-    k_step<C, MODE, 1024><<<nb, 1024, 0, p->stream>>>(x, m0, m1, m2, q, nl, shift);
 }
 
 template <typename C>
@@ -1070,30 +1030,34 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
   return LS_OK;
 }
 
+// One right-hand side: y = C_slab^{-1} g (g untouched, t scratch).
 template <typename C>
-static ls_status solve_levels(ls_plan* p, const Slab& s, const C* fac, const C* coef, C* x) {
+static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* g, C* t, C* y) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
-  if (nlev == 1) {
-    launch_step<C, STEP_LAST>(p, 1, x, fac + s.levels[0].off_dinv, nullptr, nullptr, q, 1, 0);
+  const int RS = row_splits(q);
+  auto step = [&](auto kern, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
+    kern<<<nb * RS, 256, 0, p->stream>>>(g, t, y, a0, a1, a2, coef, n, q, nl, shift, RS);
+  };
+  if (nlev == 1) {  // a single block row
+    LS_HIP(hipMemcpyAsync(t, g, sizeof(C) * q, hipMemcpyDeviceToDevice, p->stream));
+    step(k_rstep<C, R_LAST>, 1, fac + s.levels[0].off_dinv, nullptr, nullptr, 1, 0);
     LS_HIP(hipGetLastError());
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
-  k_fwd0_odd<C, 256><<<L0.nl / 2, 256, 0, p->stream>>>(x, fac + L0.off_dinv, q);
-  k_fwd0_even<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(x, coef, n, q);
+  step(k_rstep<C, R_ODD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  k_even0<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(g, y, t, coef, n, q);
   for (int l = 1; l < nlev - 1; ++l) {
     const SlabLevel& L = s.levels[l];
-    launch_step<C, STEP_FWD>(p, (L.nl + 1) / 2, x, fac + L.off_pm, fac + L.off_pp, nullptr, q,
-                             L.nl, l);
+    step(k_rstep<C, R_FWD>, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
   }
-  launch_step<C, STEP_LAST>(p, 1, x, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, q, 1, 0);
+  step(k_rstep<C, R_LAST>, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
   for (int l = nlev - 2; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
-    launch_step<C, STEP_BWD>(p, L.nl / 2, x, fac + L.off_dinv, fac + L.off_dinvl,
-                             fac + L.off_dinvu, q, L.nl, l);
+    step(k_rstep<C, R_BWD>, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu, L.nl, l);
   }
-  k_bwd0<C, 256><<<L0.nl / 2, 256, 0, p->stream>>>(x, fac + L0.off_dinv, coef, n, q);
+  step(k_rstep<C, R_BWD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -1108,6 +1072,7 @@ struct SB<cplx> {
   static const cplx* fac(const Slab& s) { return s.fac; }
   static const cplx* coef(const Slab& s) { return s.coef; }
   static cplx* work(ls_plan* p, int k) { return k ? p->slab_work2 : p->slab_work; }
+  static cplx* elim(ls_plan* p) { return p->slab_elim; }
   static cplx* vtmp(ls_plan* p) { return p->vtmp; }
 };
 template <>
@@ -1117,19 +1082,22 @@ struct SB<fcplx> {
   static const fcplx* fac(const Slab& s) { return s.fac32; }
   static const fcplx* coef(const Slab& s) { return s.coef32; }
   static fcplx* work(ls_plan* p, int k) { return k ? p->slab_work32b : p->slab_work32; }
+  static fcplx* elim(ls_plan* p) { return p->slab_elim32; }
   static fcplx* vtmp(ls_plan* p) { return p->vtmp32; }
 };
 
+// y = C_slab^{-1} g for B right-hand sides [B][n][q] (g untouched, y != g).
+// One right-hand side runs the row-split out-of-place steps; several run
+// the batched in-place steps on a copy.
 template <typename T>
-static ls_status solve_t(ls_plan* p, Slab& s, T* x, int B = 1) {
-  if (B == 1) return solve_levels<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), x);
-  return solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), x, (size_t)p->n * s.q, B);
+static ls_status solve_t(ls_plan* p, Slab& s, const T* g, T* y, int B) {
+  if (B == 1) return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), g, SB<T>::elim(p), y);
+  LS_HIP(hipMemcpyAsync(y, g, (size_t)B * p->n * s.q * sizeof(T), hipMemcpyDeviceToDevice, p->stream));
+  return solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), y, (size_t)p->n * s.q, B);
 }
 
-ls_status slab_solve_frame(ls_plan* p, Slab& s, cplx* x) { return solve_t<cplx>(p, s, x); }
-ls_status slab_solve_frame(ls_plan* p, Slab& s, fcplx* x) { return solve_t<fcplx>(p, s, x); }
-ls_status slab_solve_batch(ls_plan* p, Slab& s, cplx* x, int B) { return solve_t<cplx>(p, s, x, B); }
-ls_status slab_solve_batch(ls_plan* p, Slab& s, fcplx* x, int B) { return solve_t<fcplx>(p, s, x, B); }
+ls_status slab_solve(ls_plan* p, Slab& s, const cplx* g, cplx* y, int B) { return solve_t<cplx>(p, s, g, y, B); }
+ls_status slab_solve(ls_plan* p, Slab& s, const fcplx* g, fcplx* y, int B) { return solve_t<fcplx>(p, s, g, y, B); }
 
 template <typename T>
 static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B) {
@@ -1171,20 +1139,17 @@ static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumula
           s.b + 1 - s.z0, -1, +1.0, SB<T>::w(up), up.q, s.b - up.z0, nullptr, 0, 0);
       LS_HIP(hipGetLastError());
     }
-    LS_HIP(hipMemcpyAsync(SB<T>::w(s), SB<T>::g(s), (size_t)B * n * s.q * sizeof(T),
-                          hipMemcpyDeviceToDevice, p->stream));
-    LS_TRY(solve_t<T>(p, s, SB<T>::w(s), B));
+    LS_TRY(solve_t<T>(p, s, SB<T>::g(s), SB<T>::w(s), B));
   }
   // upward sweep: l = 0 .. L-1
-  T* vprev = SB<T>::work(p, 0);
-  T* vcur = SB<T>::work(p, 1);
+  const T* vprev = nullptr;
   for (int l = 0; l < L; ++l) {
     Slab& s = S[l];
+    T* vcur;
     if (l == 0) {
-      // g^0 is unchanged: v^0 = w^0
-      LS_HIP(hipMemcpyAsync(vcur, SB<T>::w(s), (size_t)B * n * s.q * sizeof(T),
-                            hipMemcpyDeviceToDevice, p->stream));
+      vcur = SB<T>::w(s);  // g^0 is unchanged: v^0 = w^0
     } else {
+      vcur = SB<T>::work(p, vprev == SB<T>::work(p, 0) ? 1 : 0);
       const Slab& dn = S[l - 1];
       // g^l += -delta_a C^l_{a,a-1} v0 + delta_{a-1} C^l_{a-1,a} v1 with
       // v0 = v^{l-1}(a-1), v1 = v^{l-1}(a) + w^l(a)
@@ -1193,12 +1158,10 @@ static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumula
           s.a - s.z0, -1, -1.0, vprev, dn.q, s.a - 1 - dn.z0,
           s.a - 1 - s.z0, +1, +1.0, vprev, dn.q, s.a - dn.z0, SB<T>::w(s), s.q, s.a - s.z0);
       LS_HIP(hipGetLastError());
-      LS_HIP(hipMemcpyAsync(vcur, SB<T>::g(s), (size_t)B * n * s.q * sizeof(T),
-                            hipMemcpyDeviceToDevice, p->stream));
-      LS_TRY(solve_t<T>(p, s, vcur, B));
+      LS_TRY(solve_t<T>(p, s, SB<T>::g(s), vcur, B));
     }
     LS_TRY(scatter<T>(p, s, vcur, v, accumulate, B));
-    std::swap(vprev, vcur);
+    vprev = vcur;
   }
   return LS_OK;
 }
