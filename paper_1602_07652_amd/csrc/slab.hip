@@ -247,18 +247,23 @@ __global__ __launch_bounds__(256) void k_gemm(const cplx* const* __restrict__ Ap
 // Workgroup (block, row tile): rows [r0, r0 + R) of the block, R = q / RS.
 // Thread (rl, grp) = (tid % R, tid / R) takes the virtual columns v = grp,
 // grp + G, ... (G = 256 / R) of the T*q columns and loads all its factor
-// elements (at most kRowCols) into registers before anything else, so a
+// elements (at most RCols::N) into registers before anything else, so a
 // level costs about one memory round trip however deep it is; the inputs
 // x_t are staged in LDS meanwhile and the G partial sums added in LDS.
 enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4 };
-constexpr int kRowCols = 24;
+// factor columns a thread preloads: one, two or three matrices per step
+template <int MODE>
+struct RCols {
+  static constexpr int T = MODE == R_BWD ? 3 : (MODE == R_FWD ? 2 : 1);
+  static constexpr int N = 8 * T;
+};
 
-// Row tiles per block for extended thickness q (the fewest with at most
-// kRowCols columns per thread when a step has three factor matrices).
-inline int row_splits(int q) {
+// Row tiles per block for extended thickness q: the fewest with at most
+// ncol columns per thread for a step with t factor matrices.
+inline int row_splits(int q, int t, int ncol) {
   for (int rs = 1; rs <= q; ++rs) {
     const int R = (q + rs - 1) / rs, G = 256 / R;
-    if (G >= 1 && (3 * q + G - 1) / G <= kRowCols) return rs;
+    if (G >= 1 && (t * q + G - 1) / G <= ncol) return rs;
   }
   return q;
 }
@@ -268,7 +273,7 @@ inline int row_splits(int q) {
 //   R_FWD   level l, k even: t_k -= Pm_k t_{k-1} + Pp_k t_{k+1}
 //   R_LAST  top level:       y_0 = Dinv t_0
 //   R_BWD   level l, k odd:  y_k = Dinv_k t_k - (Dinv L)_k y_{k-1} - (Dinv U)_k y_{k+1}
-//   R_BWD0  level 0, k odd:  y_k -= Dinv_k (L_k y_{k-1} + U_k y_{k+1})  (L, U from coef)
+//   R_BWD0  level 0, k odd:  y_k -= Dinv_k t_k, t_k = L_k y_{k-1} + U_k y_{k+1} (k_odd0_lu)
 template <typename C, int MODE>
 __global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __restrict__ t, C* __restrict__ y,
                                               const C* __restrict__ m0, const C* __restrict__ m1,
@@ -308,9 +313,10 @@ __global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __res
   }
   const int V = T * q;
   // factor elements first: every load of this thread in flight at once
-  C mv[kRowCols];
+  constexpr int NC = RCols<MODE>::N;
+  C mv[NC];
 #pragma unroll
-  for (int j = 0; j < kRowCols; ++j) {
+  for (int j = 0; j < NC; ++j) {
     const int v = grp + G * j;
     mv[j] = tmk<C>(0, 0);
     if (act && v < V) {
@@ -333,22 +339,15 @@ __global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __res
     } else if (MODE == R_BWD) {
       if (tt == 0) v = t[((size_t)k << shift) * q + c];
       else v = tneg(y[((size_t)(tt == 1 ? k - 1 : k + 1) << shift) * q + c]);
-    } else {  // R_BWD0
-      const C* cf = coef + ((size_t)k * q + c) * 9;
-      v = tmk<C>(0, 0);
-      for (int dZ = -1; dZ <= 1; ++dZ) {
-        const int rr = c + dZ;
-        if (rr < 0 || rr >= q) continue;
-        v = tfma(cf[(dZ + 1) * 3 + 0], y[(size_t)(k - 1) * q + rr], v);
-        if (k + 1 < n) v = tfma(cf[(dZ + 1) * 3 + 2], y[(size_t)(k + 1) * q + rr], v);
-      }
+    } else {  // R_BWD0: L_k y_{k-1} + U_k y_{k+1}, formed by k_odd0_lu in t's odd rows
+      v = t[(size_t)k * q + c];
     }
     xs[e] = v;
   }
   __syncthreads();
   C acc = tmk<C>(0, 0);
 #pragma unroll
-  for (int j = 0; j < kRowCols; ++j) acc = tfma(mv[j], xs[min(grp + G * j, V - 1)], acc);
+  for (int j = 0; j < NC; ++j) acc = tfma(mv[j], xs[min(grp + G * j, V - 1)], acc);
   part[tid] = acc;  // part[grp * R + rl]
   __syncthreads();
   if (tid < R && r0 + tid < q) {
@@ -361,6 +360,24 @@ __global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __res
     else if (MODE == R_BWD) y[((size_t)k << shift) * q + r] = sum;
     else { C* o = y + (size_t)k * q + r; *o = tsub(*o, sum); }
   }
+}
+
+// level 0, odd blocks: t_k = L_k y_{k-1} + U_k y_{k+1} (L, U from coef;
+// the odd rows of t are free once the forward elimination is done)
+template <typename C>
+__global__ void k_odd0_lu(const C* __restrict__ y, C* __restrict__ t, const C* __restrict__ coef, int n, int q) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = 2 * blockIdx.y + 1;
+  if (r >= q) return;
+  const C* cf = coef + ((size_t)k * q + r) * 9;
+  C acc = tmk<C>(0, 0);
+  for (int dZ = -1; dZ <= 1; ++dZ) {
+    const int rr = r + dZ;
+    if (rr < 0 || rr >= q) continue;
+    acc = tfma(cf[(dZ + 1) * 3 + 0], y[(size_t)(k - 1) * q + rr], acc);
+    if (k + 1 < n) acc = tfma(cf[(dZ + 1) * 3 + 2], y[(size_t)(k + 1) * q + rr], acc);
+  }
+  t[(size_t)k * q + r] = acc;
 }
 
 // level 0, even blocks: t_k = g_k - L_k z_{k-1} - U_k z_{k+1} with z_j = y_j
@@ -1035,29 +1052,36 @@ template <typename C>
 static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* g, C* t, C* y) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
-  const int RS = row_splits(q);
-  auto step = [&](auto kern, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
+  auto step = [&](auto kern, auto mode, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
+    using RC = RCols<decltype(mode)::value>;
+    const int RS = row_splits(q, RC::T, RC::N);
     kern<<<nb * RS, 256, 0, p->stream>>>(g, t, y, a0, a1, a2, coef, n, q, nl, shift, RS);
   };
+  using ModeOdd0 = std::integral_constant<int, R_ODD0>;
+  using ModeFwd = std::integral_constant<int, R_FWD>;
+  using ModeLast = std::integral_constant<int, R_LAST>;
+  using ModeBwd = std::integral_constant<int, R_BWD>;
+  using ModeBwd0 = std::integral_constant<int, R_BWD0>;
   if (nlev == 1) {  // a single block row
     LS_HIP(hipMemcpyAsync(t, g, sizeof(C) * q, hipMemcpyDeviceToDevice, p->stream));
-    step(k_rstep<C, R_LAST>, 1, fac + s.levels[0].off_dinv, nullptr, nullptr, 1, 0);
+    step(k_rstep<C, R_LAST>, ModeLast{}, 1, fac + s.levels[0].off_dinv, nullptr, nullptr, 1, 0);
     LS_HIP(hipGetLastError());
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
-  step(k_rstep<C, R_ODD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
   k_even0<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(g, y, t, coef, n, q);
   for (int l = 1; l < nlev - 1; ++l) {
     const SlabLevel& L = s.levels[l];
-    step(k_rstep<C, R_FWD>, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
+    step(k_rstep<C, R_FWD>, ModeFwd{}, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
   }
-  step(k_rstep<C, R_LAST>, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
+  step(k_rstep<C, R_LAST>, ModeLast{}, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
   for (int l = nlev - 2; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
-    step(k_rstep<C, R_BWD>, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu, L.nl, l);
+    step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu, L.nl, l);
   }
-  step(k_rstep<C, R_BWD0>, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  k_odd0_lu<C><<<dim3((q + 127) / 128, L0.nl / 2), 128, 0, p->stream>>>(y, t, coef, n, q);
+  step(k_rstep<C, R_BWD0>, ModeBwd0{}, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
