@@ -248,10 +248,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 variant")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
     ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
-    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned"],
+    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned", "apply"],
                     help="profiling sub-runs: slab = only slab solves of the bench workload's "
                          "interior layer; copy = 1 GiB device copies (counter calibration); "
-                         "batched = only the multi-grid variant")
+                         "batched = only the multi-grid variant; learned = only the learned-form "
+                         "variant; apply = only ls_apply of the bench workload at batch 8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on a "
@@ -290,6 +291,22 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"plan created in {setup_s:.2f} s")
+    if args.mode == "apply":
+        Bt = 8
+        vb = torch.randn((Bt, n, n), dtype=torch.complex128, device=dev)
+        yb = torch.empty_like(vb)
+        for _ in range(2):
+            plan.apply(vb, out=yb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.slab_reps):
+            plan.apply(vb, out=yb)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.slab_reps
+        print(json.dumps({"mode": "apply", "batch": Bt, "reps": args.slab_reps, "ms": dt * 1e3,
+                          "alg_bytes": apply_bytes(n, Bt)}))
+        plan.close()
+        return
     if args.mode == "slab":
         lims = plan.slab_info(0, 1)
         q = lims[3] - lims[2] + 1

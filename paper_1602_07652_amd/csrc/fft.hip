@@ -140,7 +140,8 @@ struct ColCfg {
   static constexpr int NT = NT0 > 1024 ? 1024 : (NT0 < 64 ? 64 : NT0);
   static constexpr int STRIDE = N + 1;  // pad: adjacent columns in different banks
 };
-constexpr int kColVariants = 3;
+constexpr int kRowHalf = 1;  // row passes: half tile (two workgroups per CU)
+constexpr int kColVariants = 5;  // 0, 1: register passes, full / half tile (P = 1024..4096); 2-4: LDS passes V = 0..2
 
 template <typename T>
 __device__ __forceinline__ size_t tiled(int b, int n, int N, int j, int kx) {
@@ -230,6 +231,391 @@ __global__ __launch_bounds__((ColCfg<T, LOGN, V>::NT)) void k_cols_conv(T* __res
   for (int e = tid; e < CPW * n; e += C::NT) {
     const int j = e / CPW, cc = e % CPW;
     Xb[(size_t)j * W + cc] = buf[cc * S + j];
+  }
+}
+
+// ---------------------------------------------------------------------
+// K2 with register-resident radix-16/8 passes (P = 1024, 2048, 4096).
+// Each column is transformed by Stockham passes whose radix-R butterflies
+// live in registers (R = 16 or 8 points per butterfly), so a transform is
+// 3 passes with 2 exchanges through LDS instead of 6 radix-2/4 passes.
+// The forward transform starts from global memory (only the n nonzero
+// inputs are loaded) and ends in natural order in registers; the spectrum
+// multiply happens there, and the inverse transform starts from the same
+// registers (its first radix equals the forward's last, so each thread
+// already holds the element set its first butterfly needs); its last pass
+// writes only the n outputs that are kept.  LDS rows are padded by one
+// element every 16 so strided butterfly reads and writes spread over the
+// banks.
+
+// cos / sin of 2 pi m / 16, m = 0..15
+__device__ __constant__ const double kC16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+__device__ __constant__ const double kS16[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// e^{-+2 pi i m / 16} (forward: minus)
+template <typename T, bool INV>
+__device__ __forceinline__ T w16(int m) {
+  return tmk<T>(kC16[m & 15], INV ? kS16[m & 15] : -kS16[m & 15]);
+}
+
+// In-register DFTs, natural order in and out.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(T* a) {
+  T e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  T o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  radix4<T, INV>(e0, e1, e2, e3);
+  radix4<T, INV>(o0, o1, o2, o3);
+  const T E[4] = {e0, e1, e2, e3};
+  T O[4] = {o0, o1, o2, o3};
+#pragma unroll
+  for (int k = 1; k < 4; ++k) O[k] = tmul(O[k], w16<T, INV>(2 * k));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = tadd(E[k], O[k]);
+    a[k + 4] = tsub(E[k], O[k]);
+  }
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(T* a) {
+  // n = 4 n1 + n2: inner DFT over n1 for each n2, twiddle W16^{n2 k1},
+  // outer DFT over n2: X[k1 + 4 k2]
+  T y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    T b0 = a[n2], b1 = a[n2 + 4], b2 = a[n2 + 8], b3 = a[n2 + 12];
+    radix4<T, INV>(b0, b1, b2, b3);
+    y[n2][0] = b0;
+    y[n2][1] = n2 ? tmul(b1, w16<T, INV>(n2)) : b1;
+    y[n2][2] = n2 ? tmul(b2, w16<T, INV>(2 * n2)) : b2;
+    y[n2][3] = n2 ? tmul(b3, w16<T, INV>(3 * n2)) : b3;
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    T c0 = y[0][k1], c1 = y[1][k1], c2 = y[2][k1], c3 = y[3][k1];
+    radix4<T, INV>(c0, c1, c2, c3);
+    a[k1] = c0;
+    a[k1 + 4] = c1;
+    a[k1 + 8] = c2;
+    a[k1 + 12] = c3;
+  }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_r(T* a) {
+  if constexpr (R == 16) dft16<T, INV>(a);
+  else dft8<T, INV>(a);
+}
+
+// Stockham pass on one butterfly j (span NS, radix R, length N): inputs
+// x[j + r N/R] twiddled by W_{NS R}^{r (j mod NS)}, outputs to
+// (j - k) R + k + r NS with k = j mod NS.
+// The powers w^r, r < R, of the butterfly's twiddle w = W_{NS R}^k come
+// from the table at r = 1, 2, 4, 8 and one complex product each for the
+// others (at most one extra rounding).
+template <typename T, int N, int R, int NS, bool INV>
+__device__ __forceinline__ void twiddle_r(T* a, int j, const T* __restrict__ tw) {
+  if constexpr (NS > 1) {
+    const int k = j & (NS - 1);
+    constexpr int st = N / (NS * R);
+    T w[R];
+    w[1] = tw[k * st];
+    w[2] = tw[2 * k * st];
+    w[4] = tw[4 * k * st];
+    if constexpr (R == 16) w[8] = tw[8 * k * st];
+    w[3] = tmul(w[2], w[1]);
+    w[5] = tmul(w[4], w[1]);
+    w[6] = tmul(w[4], w[2]);
+    w[7] = tmul(w[4], w[3]);
+    if constexpr (R == 16) {
+#pragma unroll
+      for (int r = 9; r < 16; ++r) w[r] = tmul(w[8], w[r - 8]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      T x = w[r];
+      if (INV) x.y = -x.y;
+      a[r] = tmul(a[r], x);
+    }
+  }
+}
+
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// radices of the forward transform; the inverse uses them reversed
+template <int LOGN> struct RegPlan;
+template <> struct RegPlan<10> { static constexpr int R0 = 16, R1 = 8, R2 = 8; };
+template <> struct RegPlan<11> { static constexpr int R0 = 16, R1 = 16, R2 = 8; };
+template <> struct RegPlan<12> { static constexpr int R0 = 16, R1 = 16, R2 = 16; };
+
+// Columns per workgroup: the most whose padded LDS columns fit in 150 KB
+// with at most 1024 threads (one radix-16 butterfly each); variant H = 1
+// halves it.
+template <typename T, int LOGN, int H = 0>
+struct RegCfg {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int ROW = N + N / 16 + 1;  // padded column (1 per 16, +1 across columns)
+  static constexpr int fit(int c) {
+    return (c * 2 * ROW * (int)sizeof(T) <= 153600 && c * 2 * N / 16 <= 1024) ? fit(2 * c) : c;
+  }
+  static constexpr int CPW = fit(1) >> H;
+  static constexpr int NT = CPW * N / 16;
+  static constexpr size_t lds() { return (size_t)CPW * ROW * sizeof(T); }
+};
+
+// Butterfly bi of a pass -> (column, butterfly index): columns fastest, so
+// the lanes of a wave that touch global memory pair up within lines.
+template <int CPW>
+__device__ __forceinline__ void bsplit(int bi, int& cc, int& j) {
+  cc = bi % CPW;
+  j = bi / CPW;
+}
+
+// Middle pass: LDS -> registers -> LDS.
+template <typename T, int N, int R, int NS, int CPW, int ROW, int NT, bool INV>
+__device__ __forceinline__ void reg_pass(T* buf, const T* __restrict__ tw, int tid) {
+  constexpr int NB = N / R, PER = CPW * NB / NT;
+  T a[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    int cc, j;
+    bsplit<CPW>(tid + NT * q, cc, j);
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[q][r] = buf[cc * ROW + lpad(j + r * NB)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    int cc, j;
+    bsplit<CPW>(tid + NT * q, cc, j);
+    twiddle_r<T, N, R, NS, INV>(a[q], j, tw);
+    dft_r<T, R, INV>(a[q]);
+    const int k = j & (NS - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[cc * ROW + lpad((j - k) * R + k + r * NS)] = a[q][r];
+  }
+  __syncthreads();
+}
+
+template <typename T, int LOGN, int H>
+__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_cols_reg(T* __restrict__ X, const T* __restrict__ spec,
+                                                                     const T* __restrict__ tw, int n, int ss,
+                                                                     int groups_per_rhs, int total_groups) {
+  using C = RegCfg<T, LOGN, H>;
+  using PL = RegPlan<LOGN>;
+  constexpr int N = C::N, CPW = C::CPW, ROW = C::ROW, W = Tile<T>::W, NT = C::NT;
+  constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int g = xcd_remap(blockIdx.x, total_groups);
+  const int b = g / groups_per_rhs;
+  const int c0 = (g % groups_per_rhs) * CPW;
+  T* Xb = X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
+  auto at = [&](int cc, int j) -> size_t { return (size_t)j * W + cc; };
+  // forward pass 0 (radix 16, span 1): straight from memory, pruned input
+  {
+    constexpr int NB = N / R0;
+    int cc, j;
+    bsplit<CPW>(tid, cc, j);
+    T a[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int e = j + r * NB;
+      a[r] = e < n ? Xb[at(cc, e)] : tmk<T>(0, 0);
+    }
+    dft_r<T, R0, false>(a);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) buf[cc * ROW + lpad(j * R0 + r)] = a[r];
+  }
+  __syncthreads();
+  reg_pass<T, N, R1, R0, CPW, ROW, NT, false>(buf, tw, tid);
+  // forward last pass (span R0 R1), spectrum multiply and inverse first pass
+  // in registers: butterfly j holds elements j + r N/R2 in natural order
+  {
+    constexpr int NB = N / R2, NS = R0 * R1, PER = CPW * NB / NT;
+    T a[PER][R2];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int cc, j;
+      bsplit<CPW>(tid + NT * q, cc, j);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) a[q][r] = buf[cc * ROW + lpad(j + r * NB)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int cc, j;
+      bsplit<CPW>(tid + NT * q, cc, j);
+      twiddle_r<T, N, R2, NS, false>(a[q], j, tw);
+      dft_r<T, R2, false>(a[q]);
+      const int kx = c0 + cc;
+      const int kxq = kx <= N / 2 ? kx : N - kx;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int ky = j + r * NB;
+        const int kyq = ky <= N / 2 ? ky : N - ky;
+        a[q][r] = tmul(a[q][r], spec[(size_t)kxq * ss + kyq]);
+      }
+      dft_r<T, R2, true>(a[q]);  // inverse pass 0 (span 1)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) buf[cc * ROW + lpad(j * R2 + r)] = a[q][r];
+    }
+  }
+  __syncthreads();
+  reg_pass<T, N, R1, R2, CPW, ROW, NT, true>(buf, tw, tid);
+  // inverse last pass (radix R0, span R2 R1): natural order, keep n outputs
+  {
+    constexpr int NB = N / R0, NS = R2 * R1;
+    int cc, j;
+    bsplit<CPW>(tid, cc, j);
+    T a[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) a[r] = buf[cc * ROW + lpad(j + r * NB)];
+    twiddle_r<T, N, R0, NS, true>(a, j, tw);
+    dft_r<T, R0, true>(a);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int e = j + r * NB;
+      if (e < n) Xb[at(cc, e)] = a[r];
+    }
+  }
+}
+
+// K1 / K3 with the same register passes: CPW rows per workgroup; the first
+// and last passes touch global memory with consecutive lanes on
+// consecutive elements of a row (the middle pass only touches LDS).
+template <int NB>
+__device__ __forceinline__ void rsplit(int bi, int& cc, int& j) {
+  cc = bi / NB;
+  j = bi % NB;
+}
+
+template <typename T, typename R, int LOGN, int H>
+__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_rows_fwd_reg(const T* __restrict__ v,
+                                                                          const R* __restrict__ m,
+                                                                          T* __restrict__ X,
+                                                                          const T* __restrict__ tw, int n,
+                                                                          int total_rows) {
+  using C = RegCfg<T, LOGN, H>;
+  using PL = RegPlan<LOGN>;
+  constexpr int N = C::N, CPW = C::CPW, ROW = C::ROW, NT = C::NT;
+  constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * CPW;
+  {  // pass 0 (radix 16, span 1) from memory: pad(m . v), n nonzero inputs
+    constexpr int NB = N / R0;
+    int cc, j;
+    rsplit<NB>(tid, cc, j);
+    const int row = row0 + cc;
+    const bool live = row < total_rows;
+    const int jr = live ? row % n : 0;
+    T a[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int i = j + r * NB;
+      a[r] = tmk<T>(0, 0);
+      if (live && i < n) {
+        const T vv = v[(size_t)row * n + i];
+        const R mm = m[(size_t)jr * n + i];
+        a[r].x = vv.x * mm;
+        a[r].y = vv.y * mm;
+      }
+    }
+    dft_r<T, R0, false>(a);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) buf[cc * ROW + lpad(j * R0 + r)] = a[r];
+  }
+  __syncthreads();
+  reg_pass<T, N, R1, R0, CPW, ROW, NT, false>(buf, tw, tid);
+  {  // last pass: natural order straight to the tiled intermediate
+    constexpr int NB = N / R2, NS = R0 * R1, PER = CPW * NB / NT;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int cc, j;
+      rsplit<NB>(tid + NT * q, cc, j);
+      T a[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) a[r] = buf[cc * ROW + lpad(j + r * NB)];
+      twiddle_r<T, N, R2, NS, false>(a, j, tw);
+      dft_r<T, R2, false>(a);
+      const int row = row0 + cc;
+      if (row < total_rows) {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) X[tiled<T>(row / n, n, N, row % n, j + r * NB)] = a[r];
+      }
+    }
+  }
+}
+
+template <typename T, int LOGN, int H>
+__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_rows_inv_reg(const T* __restrict__ X,
+                                                                          const T* v, T* y,
+                                                                          const T* __restrict__ tw, int n,
+                                                                          int total_rows, double a_s,
+                                                                          double b_s) {
+  using C = RegCfg<T, LOGN, H>;
+  using PL = RegPlan<LOGN>;
+  constexpr int N = C::N, CPW = C::CPW, ROW = C::ROW, NT = C::NT;
+  constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * CPW;
+  {  // pass 0 from the tiled intermediate
+    constexpr int NB = N / R0;
+    int cc, j;
+    rsplit<NB>(tid, cc, j);
+    const int row = row0 + cc;
+    T a[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r)
+      a[r] = row < total_rows ? X[tiled<T>(row / n, n, N, row % n, j + r * NB)] : tmk<T>(0, 0);
+    dft_r<T, R0, true>(a);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) buf[cc * ROW + lpad(j * R0 + r)] = a[r];
+  }
+  __syncthreads();
+  reg_pass<T, N, R1, R0, CPW, ROW, NT, true>(buf, tw, tid);
+  {  // last pass: natural order, the n kept outputs, y = a v + b conv
+    constexpr int NB = N / R2, NS = R0 * R1, PER = CPW * NB / NT;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int cc, j;
+      rsplit<NB>(tid + NT * q, cc, j);
+      T a[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) a[r] = buf[cc * ROW + lpad(j + r * NB)];
+      twiddle_r<T, N, R2, NS, true>(a, j, tw);
+      dft_r<T, R2, true>(a);
+      const int row = row0 + cc;
+      if (row >= total_rows) continue;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int i = j + r * NB;
+        if (i >= n) continue;
+        const size_t idx = (size_t)row * n + i;
+        T conv = a[r];
+        conv.x *= b_s;
+        conv.y *= b_s;
+        if (a_s != 0.0) {
+          const T vv = v[idx];
+          conv.x = fma((decltype(conv.x))a_s, vv.x, conv.x);
+          conv.y = fma((decltype(conv.y))a_s, vv.y, conv.y);
+        }
+        y[idx] = conv;
+      }
+    }
   }
 }
 
@@ -348,6 +734,23 @@ ls_status run_cols(const ApplyView<T, typename CT<T>::R>& av, int batch) {
   return LS_OK;
 }
 
+template <typename T, int LOGN, int H>
+ls_status run_cols_reg(const ApplyView<T, typename CT<T>::R>& av, int batch) {
+  using RC = RegCfg<T, LOGN, H>;
+  constexpr int N = 1 << LOGN;
+  static bool attr_done = false;
+  if (!attr_done) {
+    LS_HIP(set_lds(k_cols_reg<T, LOGN, H>, RC::lds()));
+    attr_done = true;
+  }
+  const int gpr = N / RC::CPW;
+  const int groups = gpr * batch;
+  k_cols_reg<T, LOGN, H><<<groups, RC::NT, RC::lds(), av.stream>>>(av.work, av.spec, av.tw, av.n, av.ss,
+                                                                    gpr, groups);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
 template <typename T, typename R, int LOGN>
 ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, double a, double b) {
   using RC = RowCfg<LOGN>;
@@ -361,16 +764,41 @@ ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, doub
     LS_HIP(set_lds(k_rows_inv<T, LOGN>, lds_r));
     attr_done = true;
   }
-  k_rows_fwd<T, R, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
-      v, av.m, av.work, av.tw, n, rows);
+  constexpr bool reg = LOGN >= 10 && LOGN <= 12;
+  using RR = RegCfg<T, LOGN, kRowHalf>;
+  if constexpr (reg) {
+    static bool reg_attr = false;
+    if (!reg_attr) {
+      LS_HIP(set_lds(k_rows_fwd_reg<T, R, LOGN, kRowHalf>, RR::lds()));
+      LS_HIP(set_lds(k_rows_inv_reg<T, LOGN, kRowHalf>, RR::lds()));
+      reg_attr = true;
+    }
+    k_rows_fwd_reg<T, R, LOGN, kRowHalf><<<(rows + RR::CPW - 1) / RR::CPW, RR::NT, RR::lds(), av.stream>>>(
+        v, av.m, av.work, av.tw, n, rows);
+  } else {
+    k_rows_fwd<T, R, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
+        v, av.m, av.work, av.tw, n, rows);
+  }
   LS_HIP(hipGetLastError());
   switch (av.col_variant) {
-    case 1: LS_TRY((run_cols<T, LOGN, 1>(av, batch))); break;
-    case 2: LS_TRY((run_cols<T, LOGN, 2>(av, batch))); break;
-    default: LS_TRY((run_cols<T, LOGN, 0>(av, batch))); break;
+    case 1:
+      if constexpr (reg) LS_TRY((run_cols_reg<T, LOGN, 1>(av, batch)));
+      else LS_TRY((run_cols<T, LOGN, 1>(av, batch)));
+      break;
+    case 2: LS_TRY((run_cols<T, LOGN, 0>(av, batch))); break;
+    case 3: LS_TRY((run_cols<T, LOGN, 1>(av, batch))); break;
+    case 4: LS_TRY((run_cols<T, LOGN, 2>(av, batch))); break;
+    default:
+      if constexpr (reg) LS_TRY((run_cols_reg<T, LOGN, 0>(av, batch)));
+      else LS_TRY((run_cols<T, LOGN, 0>(av, batch)));
+      break;
   }
-  k_rows_inv<T, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
-      av.work, v, y, av.tw, n, rows, a, b);
+  if constexpr (reg)
+    k_rows_inv_reg<T, LOGN, kRowHalf><<<(rows + RR::CPW - 1) / RR::CPW, RR::NT, RR::lds(), av.stream>>>(
+        av.work, v, y, av.tw, n, rows, a, b);
+  else
+    k_rows_inv<T, LOGN><<<(rows + RC::COUNT - 1) / RC::COUNT, RC::NT, lds_r, av.stream>>>(
+        av.work, v, y, av.tw, n, rows, a, b);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }

@@ -39,17 +39,21 @@ def test_graph_replays_match_eager(precision):
     pe.close()
 
 
-def test_autotuned_fft_variants_agree():
-    n = 200
+@pytest.mark.parametrize("n", [200, 400])
+def test_autotuned_fft_variants_agree(n):
+    """Whatever column-pass variant the autotuner keeps (LDS radix-4 passes
+    or register radix-16/8 passes), the operator matches the oracle; the
+    variants differ only in rounding."""
     m, _ = li.gaussian_bumps_medium(n, seed=2)
     pa, omega = make(n, m, precond=2, autotune=1, max_batch=2)
     pb, _ = make(n, m, precond=2, autotune=0, max_batch=2)
     v = dev(li.random_complex((2, n, n), 9))
     ya, yb = host(pa.apply(v)), host(pb.apply(v))
     W = kernel.kernel_samples(n, 1.0 / n, omega)
-    e = rel(ya, kernel.apply_H(W, m, host(v), omega))
-    banner(f"autotuned apply rel err {e:.3e}; variants equal: {np.array_equal(ya, yb)}")
-    assert e < 1e-13 and np.array_equal(ya, yb)
+    ref = kernel.apply_H(W, m, host(v), omega)
+    ea, eb = rel(ya, ref), rel(yb, ref)
+    banner(f"n={n} autotuned apply rel err {ea:.3e}, default variant {eb:.3e}, between {rel(ya, yb):.3e}")
+    assert ea < 1e-13 and eb < 1e-13 and rel(ya, yb) < 1e-14
     pa.close()
     pb.close()
 

@@ -46,7 +46,8 @@ def test_kernel_samples_and_spectrum(n):
     p.close()
 
 
-@pytest.mark.parametrize("n,batch", [(8, 1), (37, 3), (64, 2), (100, 1), (129, 2), (256, 1), (1024, 2)])
+@pytest.mark.parametrize("n,batch", [(8, 1), (37, 3), (64, 2), (100, 1), (129, 2), (256, 1), (300, 2),
+                                     (1024, 2), (2048, 1)])
 def test_apply_matches_oracle(n, batch):
     m, _ = li.gaussian_bumps_medium(n, seed=n)
     p, omega = make_plan(n, n / 10.0, m, precond=2, max_batch=batch)
