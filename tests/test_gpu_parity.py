@@ -218,3 +218,38 @@ def test_batched_sweep_and_precond_match_oracle():
         banner(f"batched precond k={k} rel err {e:.3e}")
         assert e < 1e-8
     p.close()
+
+
+@pytest.fixture(scope="module")
+def bench_shape():
+    """The 1024^2 bench workload (8 bumps, omega = 2 pi 100, 16 layers,
+    extension 10) with the oracle's stencils."""
+    cfg = li.config_inputs("c2_1024_bumps")
+    n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    al, be, _ = sparsify.stencils(W, n)
+    p, om = make_plan(n, omega / (2 * np.pi), m, slabs=16, ext=10, max_batch=8)
+    assert abs(om - omega) <= 1e-12 * omega
+    yield n, omega, m, al, be, p
+    p.close()
+
+
+@pytest.mark.parametrize("orient,l", [(0, 1), (1, 1), (0, 0), (1, 15)])
+def test_slab_solve_at_bench_shape(bench_shape, orient, l):
+    """Full-size slab solves (n = 1024, q = 74..84) in the launch
+    configuration the benchmark times, against SuperLU on the oracle's slab
+    matrix."""
+    import scipy.sparse.linalg as spla
+    n, omega, m, al, be, p = bench_shape
+    a_, b_ = (al, be) if orient == 0 else (al.transpose(1, 0, 3, 2), be.transpose(1, 0, 3, 2))
+    mm = m if orient == 0 else m.T.copy()
+    parts = slabs.layer_partition(n, 16, 10)
+    assert p.slab_info(orient, l) == parts[l]
+    Cl = slabs.assemble_slab(a_, b_, mm, omega, parts[l], 10, 0.0)
+    q = parts[l][3] - parts[l][2] + 1
+    b = li.random_complex((n, q), seed=100 + 10 * l + orient)
+    x = host(p.slab_solve(orient, l, dev(b)))
+    x_ref = spla.spsolve(Cl.tocsc(), b.T.reshape(-1)).reshape(q, n).T
+    e = rel(x, x_ref)
+    banner(f"bench-shape slab orient={orient} l={l} q={q} rel err {e:.3e}")
+    assert e < 1e-9
