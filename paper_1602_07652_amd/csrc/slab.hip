@@ -236,6 +236,13 @@ __global__ __launch_bounds__(256) void k_gemm(const cplx* const* __restrict__ Ap
     }
 }
 
+// consecutive logical workgroups (the tiles of one block) on one XCD
+__device__ __forceinline__ int bstep_remap(int id, int total) {
+  const int per = total / 8;
+  if (per == 0 || id >= per * 8) return id;
+  return (id % 8) * per + id / 8;
+}
+
 // ------------------------------------------------------------ solve kernels
 // Single right-hand side.  The solve reads the right-hand side g, keeps the
 // eliminated right-hand sides of the even block rows in a scratch t, and
@@ -281,7 +288,10 @@ __global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __res
                                               int q, int nl, int shift, int RS) {
   __shared__ C xs[3 * kMaxQ];
   __shared__ C part[256];
-  const int blk = blockIdx.x / RS, rs = blockIdx.x % RS;
+  // the RS row tiles of a block on one XCD: they share the 128-byte lines
+  // that straddle tile boundaries through that XCD's L2
+  const int lid = bstep_remap(blockIdx.x, gridDim.x);
+  const int blk = lid / RS, rs = lid % RS;
   const int R = (q + RS - 1) / RS, r0 = rs * R;
   const int tid = threadIdx.x;
   const int rl = tid % R, grp = tid / R, G = 256 / R;
@@ -427,13 +437,6 @@ template <> struct BVariants<cplx> {
   static constexpr int BT[3] = {8, 4, 2};
   static constexpr int NT[3] = {256, 512, 1024};
 };
-
-// consecutive logical workgroups (the tiles of one block) on one XCD
-__device__ __forceinline__ int bstep_remap(int id, int total) {
-  const int per = total / 8;
-  if (per == 0 || id >= per * 8) return id;
-  return (id % 8) * per + id / 8;
-}
 
 template <typename C, int MODE, int BT, int NT>
 __global__ __launch_bounds__(NT) void k_bstep(C* __restrict__ x, size_t xs_b, int B,
