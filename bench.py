@@ -210,6 +210,67 @@ def learned_variant(tol, log_fn, weights):
             "speedup": arms["plain"]["wall_s"] / arms["learned"]["wall_s"]}
 
 
+def fno_flops(n, S):
+    """Multiply-add flops (2 per MAC) of one forward pass of the network on
+    S samples of n x n: lift, per layer the two DFT products along x, the
+    two along z (real-stacked complex), the mode mix and the pointwise map,
+    and the projection."""
+    P, W, M, Hd = n * n, 32, 16, 128
+    layer = (2 * (S * W * n) * n * 32          # x-DFT  [S*32*n x n] . [n x 32]
+             + 2 * 2 * (S * W) * 64 * M * n    # z-DFT  two [64 x n] . [n x 16]
+             + 8 * 2 * M * M * W * W * S       # mode mix, complex 32 x 32 per mode
+             + 2 * (S * W) * n * 64 * 32       # inverse z  [n x 64] . [64 x 32]
+             + 2 * (S * W * n) * 32 * n        # inverse x  [S*32*n x 32] . [32 x n]
+             + 2 * S * W * W * P)              # pointwise W v
+    return 2 * S * P * 5 * W + 4 * layer + 2 * S * P * (W * Hd + Hd * 2)
+
+
+def fno_variant(log_fn, weights):
+    """Timing of the network's kernels: one training step (forward with
+    stored activations, loss, backward, Adam) on 16 samples of 256^2, and
+    inference on 8 samples of 1024^2; flops from fno_flops (backward counted
+    as twice the forward)."""
+    import numpy as np
+    import torch
+    from paper_1602_07652_amd import Fno
+    from paper_1602_07652_amd.fno_train import load_weights
+    dev = torch.device("cuda:0")
+    params, _ = load_weights(weights)
+    out = {}
+    for n, S, train in ((256, 16, True), (1024, 8, False)):
+        net = Fno(max_batch=S, max_n=n)
+        net.set_params(params)
+        g = torch.Generator(device=dev).manual_seed(0)
+        x = torch.randn((S, 5, n, n), device=dev, generator=g)
+        t = torch.randn((S, 2, n, n), device=dev, generator=g)
+        grad = torch.empty(net.nparams, dtype=torch.float32, device=dev)
+
+        def step(k):
+            if train:
+                y = net.forward(x, keep=True)
+                _, dy = net.loss(y, t)
+                net.backward(dy, grad)
+                net.adam(grad, 1e-6, k)
+            else:
+                net.forward(x)
+        for k in range(1, 3):
+            step(k)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for k in range(3, 3 + reps):
+            step(k)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        fl = fno_flops(n, S) * (3 if train else 1)
+        key = f"{'train_step' if train else 'inference'}_{n}x{n}_S{S}"
+        out[key] = {"ms": ms, "gflop": fl / 1e9, "tflops": fl / (ms * 1e-3) / 1e12,
+                    "mfma_frac_of_bf16_peak": fl / (ms * 1e-3) / 2.5e15}
+        log_fn(f"fno {key}: {ms:.2f} ms, {fl / 1e9:.1f} GFLOP, {fl / (ms * 1e-3) / 1e12:.1f} TFLOP/s")
+        net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,11 +282,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 variant")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
     ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
-    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned", "apply"],
+    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned", "apply", "fno"],
                     help="profiling sub-runs: slab = only slab solves of the bench workload's "
                          "interior layer; copy = 1 GiB device copies (counter calibration); "
                          "batched = only the multi-grid variant; learned = only the learned-form "
-                         "variant; apply = only ls_apply of the bench workload at batch 8")
+                         "variant; apply = only ls_apply of the bench workload at batch 8; "
+                         "fno = only the network's training step and inference")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on a "
@@ -253,6 +315,9 @@ def main():
     weights = args.weights or DEFAULT_WEIGHTS
     if args.mode == "learned":
         print(json.dumps({"mode": "learned", "learned": learned_variant(args.tol, log, weights)}))
+        return
+    if args.mode == "fno":
+        print(json.dumps({"mode": "fno", "fno": fno_variant(log, weights)}))
         return
     cfg = li.config_inputs("c2_1024_bumps")
     n, omega, L, ext = cfg["n"], cfg["omega"], cfg["slabs"], 10

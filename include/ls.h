@@ -74,7 +74,7 @@ typedef struct {
   int max_outer;         /* outer flexible-GMRES iteration limit (no restart) */
   int max_inner;         /* inner GMRES iteration limit */
   double shift_c;        /* complex shift in the cut-off region, omega^2 sigma = shift_c*omega (Section 3.3) */
-  int precision;         /* LS_FP64 */
+  int precision;         /* LS_FP64 or LS_FP32_REFINE */
   int precond;           /* LS_PREC_* */
   int inner_fixed_iters; /* > 0: inner GMRES runs exactly this many iterations */
   int max_batch;         /* largest `batch` passed to ls_apply / ls_rhs_from_incident */
@@ -104,8 +104,8 @@ void ls_options_default(ls_options* opt);
  * medium.  n >= 8 with 2n-1 <= 4096 (the padded FFT side P is the power of
  * two >= 2n-1); h > 0; omega > 0; m: DEVICE pointer to n*n doubles
  * (m(x_{i,j}) at index j*n + i), copied -- the caller keeps ownership.
- * Each extended layer must satisfy q = thickness + extensions <= 128 and
- * each layer must be at least ext rows thick.  opt may be NULL (defaults).
+ * Each extended layer must satisfy q = thickness + extensions <= 96
+ * (LS_EUNSUPPORTED otherwise) and each layer must be at least ext rows thick.  opt may be NULL (defaults).
  * stream: hipStream_t as void*; NULL makes the plan create its own blocking
  * stream (ordered with the null stream, and capturable into graphs).  On
  * success *out owns all device memory of the plan.  Steps: kernel samples w and the circulant spectrum (Section 2),
