@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # calibrated by the same counters on a 1 GiB device copy (fetch x2, write
 # x1); profiles/slab_solve_bench_1024.md holds the figures.  Re-measure when
 # the slab-solve kernels change.
-SLAB_TRAFFIC_BYTES = 430.36e6
+SLAB_TRAFFIC_BYTES = 450.09e6
 
 
 def log(msg):

@@ -111,6 +111,14 @@ struct Slab {
   fcplx* fac32;
   fcplx* g32;
   fcplx* w32;
+  // Top of the reduction as one dense operator: the levels from top_level
+  // up (top_level >= 1, at most 16 blocks there) solved by y = top t on the
+  // top_n = nl * q unknowns of that level; row-major [top_n][top_n].
+  // top_level = -1: no such operator (the chain runs every level).
+  int top_level;
+  int top_n;
+  cplx* top;
+  fcplx* top32;
 };
 
 // Contiguous set of grid vectors used as a Krylov basis.

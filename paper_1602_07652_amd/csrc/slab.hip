@@ -390,6 +390,64 @@ __global__ void k_odd0_lu(const C* __restrict__ y, C* __restrict__ t, const C* _
   t[(size_t)k * q + r] = acc;
 }
 
+// The top levels of the reduction (from level top_level, at most
+// kTopBlocks blocks) as one dense operator: y_top = Top t_top on the
+// Nt = nl * q unknowns of that level (rows j << top_level of the frame).
+// One wave per output row streams its row of Top (all kTopK loads per lane
+// in flight), the inputs sit in LDS, and the row sum is a wave reduction.
+constexpr int kTopBlocks = 16;
+constexpr int kTopK = 24;                 // ceil(kTopBlocks * kMaxQ / 64)
+constexpr int kTopMax = kTopBlocks * kMaxQ;
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_top(const C* __restrict__ top, const C* __restrict__ t,
+                                             C* __restrict__ y, int Nt, int q, int shift) {
+  __shared__ C tv[kTopMax];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 4 + w;
+  C mv[kTopK];
+#pragma unroll
+  for (int k = 0; k < kTopK; ++k) {
+    const int b = lane + 64 * k;
+    mv[k] = (o < Nt && b < Nt) ? top[(size_t)o * Nt + b] : tmk<C>(0, 0);
+  }
+  for (int e = threadIdx.x; e < Nt; e += 256) {
+    const int j = e / q, r = e - j * q;
+    tv[e] = t[((size_t)j << shift) * q + r];
+  }
+  __syncthreads();
+  C acc = tmk<C>(0, 0);
+#pragma unroll
+  for (int k = 0; k < kTopK; ++k) acc = tfma(mv[k], tv[min(lane + 64 * k, Nt - 1)], acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+  }
+  if (lane == 0 && o < Nt) {
+    const int j = o / q, r = o - j * q;
+    y[((size_t)j << shift) * q + r] = acc;
+  }
+}
+
+// x[b][b] = 1, 0 elsewhere (Nt x Nt)
+__global__ void k_identity(cplx* __restrict__ x, int Nt) {
+  const size_t cnt = (size_t)Nt * Nt;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (size_t)gridDim.x * blockDim.x)
+    x[e] = cmk(e / Nt == e % Nt ? 1.0 : 0.0, 0.0);
+}
+
+// out[o][b] = in[b][o] (rounded to the storage type)
+template <typename T>
+__global__ void k_transpose_to(const cplx* __restrict__ in, T* __restrict__ out, int Nt) {
+  const size_t cnt = (size_t)Nt * Nt;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t o = e / Nt, b = e % Nt;
+    const cplx v = in[b * Nt + o];
+    out[e] = tmk<T>(v.x, v.y);
+  }
+}
+
 // level 0, even blocks: t_k = g_k - L_k z_{k-1} - U_k z_{k+1} with z_j = y_j
 template <typename C>
 __global__ void k_even0(const C* __restrict__ g, const C* __restrict__ y, C* __restrict__ t,
@@ -679,6 +737,53 @@ static void bstep(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C* a1
     bstep_go<C, MODE, 1>(p, x, xs_b, B, a0, a1, a2, coef, q, nl, shift, nb);
   else
     bstep_go<C, MODE, 2>(p, x, xs_b, B, a0, a1, a2, coef, q, nl, shift, nb);
+}
+
+// Top operator of one slab from its FP64 factors: the levels from the
+// first with at most kTopBlocks blocks up to the top and back, applied to the
+// Nt identity columns in a compact frame [Nt][nl][q] (row j of that level at
+// j; level l >= top_level then has shift l - top_level), then transposed to
+// row-major.  work: work_cap complex scratch; a slab whose Nt^2 does not fit
+// keeps the level-by-level chain.
+static ls_status build_top(ls_plan* p, Slab& s, const cplx* fac, cplx* work, size_t work_cap) {
+  const int nlev = (int)s.levels.size();
+  int ls = -1;
+  for (int l = 1; l < nlev; ++l)
+    if (s.levels[l].nl <= kTopBlocks) {
+      ls = l;
+      break;
+    }
+  s.top_level = -1;
+  s.top_n = 0;
+  if (ls < 1 || s.levels[ls].nl < 2) return LS_OK;
+  const int q = s.q, Nt = s.levels[ls].nl * q;
+  if ((size_t)Nt * Nt > work_cap || Nt > kTopMax) return LS_OK;
+  const int blocks = (int)std::min<size_t>(4096, ((size_t)Nt * Nt + 255) / 256);
+  k_identity<<<blocks, 256, 0, p->stream>>>(work, Nt);
+  for (int l = ls; l < nlev - 1; ++l) {
+    const SlabLevel& L = s.levels[l];
+    bstep<cplx, BSTEP_FWD>(p, work, (size_t)Nt, Nt, fac + L.off_pm, fac + L.off_pp, nullptr, s.coef, q,
+                           L.nl, l - ls, (L.nl + 1) / 2);
+  }
+  bstep<cplx, BSTEP_LAST>(p, work, (size_t)Nt, Nt, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr,
+                          s.coef, q, 1, 0, 1);
+  for (int l = nlev - 2; l >= ls; --l) {
+    const SlabLevel& L = s.levels[l];
+    bstep<cplx, BSTEP_BWD>(p, work, (size_t)Nt, Nt, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu,
+                           s.coef, q, L.nl, l - ls, L.nl / 2);
+  }
+  const size_t bytes = (size_t)Nt * Nt;
+  if (p->fp32) {
+    LS_TRY(plan_alloc(p, (void**)&s.top32, bytes * sizeof(fcplx)));
+    k_transpose_to<fcplx><<<blocks, 256, 0, p->stream>>>(work, s.top32, Nt);
+  } else {
+    LS_TRY(plan_alloc(p, (void**)&s.top, bytes * sizeof(cplx)));
+    k_transpose_to<cplx><<<blocks, 256, 0, p->stream>>>(work, s.top, Nt);
+  }
+  LS_HIP(hipGetLastError());
+  s.top_level = ls;
+  s.top_n = Nt;
+  return LS_OK;
 }
 
 struct PtrBatch {
@@ -976,6 +1081,7 @@ ls_status slabs_build(ls_plan* p) {
           s.coef, tables, p->m, n, s.q, s.z0, s.a, s.b, std::max(ext, 2), o, w2, sigma);
       if (hipGetLastError() != hipSuccess) { ls_set_error("assembly launch failed"); st = LS_EDEVICE; break; }
       if ((st = factor_slab(p, s, work, status)) != LS_OK) break;
+      if ((st = build_top(p, s, s.fac, work, work_elems)) != LS_OK) break;
       if (p->fp32) {
         // FP64 factorisation, FP32 storage for the solves
         k_down_copy<<<(unsigned)((s.fac_elems + 255) / 256), 256, 0, p->stream>>>(s.fac, s.fac32,
@@ -1052,7 +1158,8 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
 
 // One right-hand side: y = C_slab^{-1} g (g untouched, t scratch).
 template <typename C>
-static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* g, C* t, C* y) {
+static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* top, const C* g,
+                            C* t, C* y) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
   auto step = [&](auto kern, auto mode, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
@@ -1074,12 +1181,18 @@ static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* co
   const SlabLevel& L0 = s.levels[0];
   step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
   k_even0<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(g, y, t, coef, n, q);
-  for (int l = 1; l < nlev - 1; ++l) {
+  // levels from `top` up: one dense operator when the plan built it
+  const int top_l = (s.top_level >= 1 && top) ? s.top_level : nlev - 1;
+  for (int l = 1; l < top_l; ++l) {
     const SlabLevel& L = s.levels[l];
     step(k_rstep<C, R_FWD>, ModeFwd{}, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
   }
-  step(k_rstep<C, R_LAST>, ModeLast{}, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
-  for (int l = nlev - 2; l >= 1; --l) {
+  if (top_l < nlev - 1) {
+    k_top<C><<<(s.top_n + 3) / 4, 256, 0, p->stream>>>(top, t, y, s.top_n, q, top_l);
+  } else {
+    step(k_rstep<C, R_LAST>, ModeLast{}, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
+  }
+  for (int l = top_l - 1; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
     step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu, L.nl, l);
   }
@@ -1100,6 +1213,7 @@ struct SB<cplx> {
   static const cplx* coef(const Slab& s) { return s.coef; }
   static cplx* work(ls_plan* p, int k) { return k ? p->slab_work2 : p->slab_work; }
   static cplx* elim(ls_plan* p) { return p->slab_elim; }
+  static const cplx* top(const Slab& s) { return s.top; }
   static cplx* vtmp(ls_plan* p) { return p->vtmp; }
 };
 template <>
@@ -1110,6 +1224,7 @@ struct SB<fcplx> {
   static const fcplx* coef(const Slab& s) { return s.coef32; }
   static fcplx* work(ls_plan* p, int k) { return k ? p->slab_work32b : p->slab_work32; }
   static fcplx* elim(ls_plan* p) { return p->slab_elim32; }
+  static const fcplx* top(const Slab& s) { return s.top32; }
   static fcplx* vtmp(ls_plan* p) { return p->vtmp32; }
 };
 
@@ -1118,7 +1233,7 @@ struct SB<fcplx> {
 // the batched in-place steps on a copy.
 template <typename T>
 static ls_status solve_t(ls_plan* p, Slab& s, const T* g, T* y, int B) {
-  if (B == 1) return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), g, SB<T>::elim(p), y);
+  if (B == 1) return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), SB<T>::top(s), g, SB<T>::elim(p), y);
   LS_HIP(hipMemcpyAsync(y, g, (size_t)B * p->n * s.q * sizeof(T), hipMemcpyDeviceToDevice, p->stream));
   return solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), y, (size_t)p->n * s.q, B);
 }

@@ -253,3 +253,57 @@ def test_slab_solve_at_bench_shape(bench_shape, orient, l):
     e = rel(x, x_ref)
     banner(f"bench-shape slab orient={orient} l={l} q={q} rel err {e:.3e}")
     assert e < 1e-9
+
+
+def test_zero_right_hand_side_gives_zero():
+    n = 48
+    m = li.gaussian_disk_medium(n)
+    p, _ = make_plan(n, 4.8, m, slabs=2, ext=6, max_batch=2)
+    f = torch.zeros((2, n, n), dtype=torch.complex128, device="cuda")
+    f[1] = dev(li.random_complex((n, n), 3))
+    u, info = p.solve(f, tol=1e-8)
+    banner(f"zero rhs: {info[0]} / nonzero: {info[1]}")
+    assert torch.count_nonzero(u[0]).item() == 0 and info[0]["converged"] == 1
+    assert info[1]["converged"] == 1
+    p.close()
+
+
+def test_single_slab_is_the_exact_local_solve():
+    """L = 1: the one slab is the whole grid, C^1 = C, so Alg. 2 solves the
+    sparsified system exactly and the inner GMRES stops after one iteration."""
+    n = 64
+    m = li.gaussian_disk_medium(n)
+    p, omega = make_plan(n, 6.0, m, slabs=1, ext=10)
+    P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=1, ext=10, precond="exact")
+    r = li.random_complex((n, n), 4)
+    z = host(p.precond_apply(dev(r)))
+    e = rel(z, P.precond_apply(r))
+    banner(f"L=1 precond vs exact C^-1 A r: {e:.3e}")
+    assert e < 1e-9
+    p.close()
+
+
+def test_batch_larger_than_max_batch_is_chunked():
+    n = 64
+    m, _ = li.gaussian_bumps_medium(n, seed=8)
+    p, omega = make_plan(n, 6.4, m, slabs=2, ext=6, max_batch=2)
+    uI = np.stack([li.plane_wave(n, omega, 0.5 * k) for k in range(5)])
+    # ls_apply / ls_rhs_from_incident take at most max_batch vectors; ls_solve
+    # takes any batch and works through it max_batch at a time
+    f = torch.cat([p.rhs_from_incident(dev(uI[k:k + 2])) for k in range(0, 5, 2)])
+    u, infos = p.solve(f, tol=1e-9)
+    for k in range(5):
+        uk, _ = p.solve(f[k].contiguous(), tol=1e-9)
+        e = rel(host(u[k]), host(uk))
+        banner(f"chunked batch k={k}: vs single {e:.2e} info {infos[k]}")
+        assert infos[k]["converged"] == 1 and e < 1e-7
+    p.close()
+
+
+def test_too_thick_layer_is_refused():
+    from paper_1602_07652_amd import LSError
+    n = 200
+    with pytest.raises(LSError) as ei:
+        make_plan(n, 20.0, np.zeros((n, n)), slabs=2, ext=10)     # q = 120 > 96
+    banner(f"refused: {ei.value}")
+    assert "96" in str(ei.value)
