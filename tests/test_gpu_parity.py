@@ -307,3 +307,36 @@ def test_too_thick_layer_is_refused():
         make_plan(n, 20.0, np.zeros((n, n)), slabs=2, ext=10)     # q = 120 > 96
     banner(f"refused: {ei.value}")
     assert "96" in str(ei.value)
+
+
+def test_apply_properties_at_bench_shape(bench_shape):
+    """Properties of H that hold at any size, checked on the 1024^2 bench
+    plan: linearity; D H complex symmetric (w is even, so
+    v^T D H w = w^T D H v with D = diag(m)); f(u_I) = -(H - I) u_I; and
+    outputs sampled against the O(N) direct sum (H v)_k = v_k +
+    w^2 sum_p w_{k-p} m_p v_p."""
+    n, omega, m, al, be, p = bench_shape
+    v = li.random_complex((n, n), 61)
+    w = li.random_complex((n, n), 62)
+    a, b = 0.7 - 0.2j, -1.3 + 0.4j
+    Hv = host(p.apply(dev(v)))
+    Hw = host(p.apply(dev(w)))
+    Hl = host(p.apply(dev(a * v + b * w)))
+    e_lin = rel(Hl, a * Hv + b * Hw)
+    lhs, rhs = np.sum(v * m * Hw), np.sum(w * m * Hv)
+    e_sym = abs(lhs - rhs) / abs(lhs)
+    f = host(p.rhs_from_incident(dev(v)))
+    e_rhs = rel(f, -(Hv - v))
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    rng = np.random.default_rng(63)
+    pts = rng.integers(0, n, size=(24, 2))
+    mv = m * v
+    worst = 0.0
+    for j, i in pts:
+        # W[n-1 + dj, n-1 + di] = w at offset (dj, di) = (j - jp, i - ip)
+        Wk = W[n - 1 + j - np.arange(n)[:, None], n - 1 + i - np.arange(n)[None, :]]
+        direct = v[j, i] + omega**2 * np.sum(Wk * mv)
+        worst = max(worst, abs(Hv[j, i] - direct) / np.max(np.abs(Hv)))
+    banner(f"bench-shape H: linearity {e_lin:.2e}, D H symmetry {e_sym:.2e}, rhs identity {e_rhs:.2e}, "
+           f"direct-sum samples {worst:.2e}")
+    assert e_lin < 1e-14 and e_sym < 1e-12 and e_rhs < 1e-14 and worst < 1e-13
