@@ -209,7 +209,7 @@ struct ls_plan {
   std::vector<GraphEntry> graphs;
   cplx* solve_buf = nullptr;     // FP64 plans, learned solves: two grid-vector batches
   int col_variant64 = 0, col_variant32 = 0;  // autotuned FFT column-pass variants
-  float tune_ms64[5] = {0, 0, 0, 0, 0}, tune_ms32[5] = {0, 0, 0, 0, 0};
+  float tune_ms64[6] = {0, 0, 0, 0, 0, 0}, tune_ms32[6] = {0, 0, 0, 0, 0, 0};
 };
 
 inline ApplyView<cplx, double> view64(ls_plan* p) {
