@@ -605,6 +605,134 @@ __global__ __launch_bounds__(NT) void k_bstep(C* __restrict__ x, size_t xs_b, in
   }
 }
 
+// FP32 batched level step on matrix cores (v_mfma_f32_16x16x4f32): the
+// same y = sum_t M_t X_t as k_bstep for a tile of kMB right-hand sides.
+// Wave w owns output rows [16 w, 16 w + 16) of the block for all kMB
+// right-hand sides (two 16-column tiles).  The panels X_t are staged in LDS
+// as real and imaginary planes; each K step of 4 factor columns feeds one
+// factor element per lane (lane l: row 16 w + l % 16, column l / 16, read
+// straight from memory, U steps in flight) and 4 real MFMAs per complex
+// 16 x 16 x 4 product: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+constexpr int kMB = 32;
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int mq4(int q) { return (q + 3) & ~3; }
+inline size_t bstep_mfma_lds(int q) { return (size_t)2 * 3 * mq4(q) * (kMB + 1) * sizeof(float); }
+
+template <int MODE>
+__global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_t xs_b, int B,
+                                                    const fcplx* __restrict__ m0, const fcplx* __restrict__ m1,
+                                                    const fcplx* __restrict__ m2, const fcplx* __restrict__ coef,
+                                                    int n, int q, int nl, int shift, int tiles, int total) {
+  constexpr int U = 8, LB = kMB + 1;  // K steps in flight; padded panel row
+  extern __shared__ unsigned char lds_raw[];
+  const int q4 = mq4(q);
+  float* xr = reinterpret_cast<float*>(lds_raw);  // [3][q4][LB]
+  float* xi = xr + 3 * q4 * LB;
+  const int lid = bstep_remap(blockIdx.x, total);
+  const int blk = lid / tiles;
+  const int b0 = (lid % tiles) * kMB;
+  const int nbt = min(kMB, B - b0);
+  const size_t qq = (size_t)q * q;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  // panel t: global row rw_t, negated for t >= 1 in BWD, factor block M_t
+  int T = 0, k = 0, rw0 = 0, rw1 = 0, rw2 = 0;
+  const fcplx* M0 = nullptr;
+  const fcplx* M1 = nullptr;
+  const fcplx* M2 = nullptr;
+  if (MODE == BSTEP_FWD) {
+    k = 2 * blk;
+    const bool lo = k >= 1, hi = k + 1 < nl;
+    rw0 = lo ? (k - 1) << shift : (k + 1) << shift;
+    M0 = (lo ? m0 : m1) + blk * qq;
+    rw1 = (k + 1) << shift;
+    M1 = m1 + blk * qq;
+    T = (lo ? 1 : 0) + (hi ? 1 : 0);
+  } else if (MODE == BSTEP_BWD) {
+    k = 2 * blk + 1;
+    rw0 = k << shift; M0 = m0 + blk * qq;
+    rw1 = (k - 1) << shift; M1 = m1 + blk * qq;
+    rw2 = (k + 1) << shift; M2 = m2 + blk * qq;
+    T = k + 1 < nl ? 3 : 2;
+  } else if (MODE == BSTEP_LAST) {
+    k = 0; M0 = m0; T = 1;
+  } else {  // ODD0, BWD0
+    k = 2 * blk + 1; rw0 = k; M0 = m0 + blk * qq; T = 1;
+  }
+  // panels: element e -> (t, bb, c), c fastest; zero past q and past nbt
+  for (int e = tid; e < T * kMB * q4; e += NT) {
+    const int t = e / (kMB * q4), rem = e - t * kMB * q4;
+    const int bb = rem / q4, c = rem - bb * q4;
+    fcplx v = tmk<fcplx>(0, 0);
+    if (bb < nbt && c < q) {
+      const fcplx* xb = x + (size_t)(b0 + bb) * xs_b;
+      if (MODE == BSTEP_BWD0) {
+        const fcplx* cf = coef + ((size_t)k * q + c) * 9;
+        for (int dZ = -1; dZ <= 1; ++dZ) {
+          const int rr = c + dZ;
+          if (rr < 0 || rr >= q) continue;
+          v = tfma(cf[(dZ + 1) * 3 + 0], xb[(size_t)(k - 1) * q + rr], v);
+          if (k + 1 < n) v = tfma(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr], v);
+        }
+      } else {
+        v = xb[(size_t)(t == 0 ? rw0 : (t == 1 ? rw1 : rw2)) * q + c];
+        if (MODE == BSTEP_BWD && t > 0) v = tneg(v);
+      }
+    }
+    xr[(t * q4 + c) * LB + bb] = v.x;
+    xi[(t * q4 + c) * LB + bb] = v.y;
+  }
+  __syncthreads();
+  const int w = tid >> 6, l = tid & 63;
+  const int ra = 16 * w + (l & 15);  // factor row this lane feeds
+  const int kk = l >> 4;             // column within the K step
+  f32x4_t dre0 = {0, 0, 0, 0}, dim0 = {0, 0, 0, 0}, dre1 = {0, 0, 0, 0}, dim1 = {0, 0, 0, 0};
+  for (int t = 0; t < T; ++t) {
+    const fcplx* Mt = (t == 0 ? M0 : (t == 1 ? M1 : M2)) + ra;
+    const float* pr = xr + (size_t)t * q4 * LB + (l & 15);
+    const float* pi = xi + (size_t)t * q4 * LB + (l & 15);
+    for (int c0 = 0; c0 < q4; c0 += 4 * U) {
+      fcplx cur[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + 4 * u + kk;
+        cur[u] = (c < q && ra < q) ? Mt[(size_t)c * q] : tmk<fcplx>(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + 4 * u;
+        if (c >= q4) break;
+        const int o = (c + kk) * LB;
+        const float br0 = pr[o], bi0 = pi[o], br1 = pr[o + 16], bi1 = pi[o + 16];
+        const float ar = cur[u].x, ai = cur[u].y;
+        dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br0, dre0, 0, 0, 0);
+        dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi0, dre0, 0, 0, 0);
+        dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi0, dim0, 0, 0, 0);
+        dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br0, dim0, 0, 0, 0);
+        dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br1, dre1, 0, 0, 0);
+        dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi1, dre1, 0, 0, 0);
+        dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi1, dim1, 0, 0, 0);
+        dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br1, dim1, 0, 0, 0);
+      }
+    }
+  }
+  // D layout: lane l holds rows 4 (l / 16) + i of column l % 16
+  const size_t okq = (size_t)(MODE == BSTEP_FWD || MODE == BSTEP_BWD ? (k << shift) : k) * q;
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * w + 4 * (l >> 4) + i, bb = 16 * ct + (l & 15);
+      if (r >= q || bb >= nbt) continue;
+      const fcplx val = tmk<fcplx>(ct ? dre1[i] : dre0[i], ct ? dim1[i] : dim0[i]);
+      fcplx* o = x + (size_t)(b0 + bb) * xs_b + okq + r;
+      if (MODE == BSTEP_FWD || MODE == BSTEP_BWD0)
+        *o = tsub(*o, val);
+      else
+        *o = val;
+    }
+}
+
 template <typename C>
 __global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restrict__ coef, int n,
                               int q) {
@@ -724,6 +852,19 @@ static void bstep_go(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C*
 template <typename C, int MODE>
 static void bstep(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C* a1, const C* a2,
                   const C* coef, int q, int nl, int shift, int nb) {
+  if constexpr (std::is_same<C, fcplx>::value) {
+    // matrix cores when the level has enough (block, 32-RHS tile) pairs
+    const int tiles = (B + kMB - 1) / kMB;
+    // (block, tile) pairs >= 256 measured best against 64 and 128 thresholds
+    if (B >= 16 && (long)nb * tiles >= 256) {
+      static const hipError_t once = set_lds(k_bstep_mfma<MODE>, bstep_mfma_lds(kMaxQ));
+      (void)once;
+      const int total = nb * tiles;
+      k_bstep_mfma<MODE><<<total, 64 * ((q + 15) / 16), bstep_mfma_lds(q), p->stream>>>(
+          x, xs_b, B, a0, a1, a2, coef, p->n, q, nl, shift, tiles, total);
+      return;
+    }
+  }
   using V = BVariants<C>;
   int v = 2;
   for (int i = 0; i < 2; ++i) {
