@@ -82,6 +82,7 @@ typedef struct {
   int max_refine;        /* LS_FP32_REFINE: refinement sweeps limit */
   int use_graphs;        /* 1: the inner preconditioner runs as a captured hipGraph */
   int autotune;          /* 1: time the FFT column-pass tile variants at plan creation */
+  int fft_variant;       /* autotune 0: FFT column-pass variant to use, 0..7 (0: radix-16 register passes) */
 } ls_options;
 
 typedef struct {
@@ -96,7 +97,8 @@ typedef struct {
 
 /* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,
  * max_inner 50, shift_c 0, LS_FP64, LS_PREC_BD, inner_fixed_iters 0,
- * max_batch 1, lowp_tol 1e-5, max_refine 10, use_graphs 1, autotune 1.
+ * max_batch 1, lowp_tol 1e-5, max_refine 10, use_graphs 1, autotune 1,
+ * fft_variant 0.
  * Never fails. */
 void ls_options_default(ls_options* opt);
 

@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int), ("precond", ctypes.c_int),
         ("inner_fixed_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("lowp_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-        ("use_graphs", ctypes.c_int), ("autotune", ctypes.c_int),
+        ("use_graphs", ctypes.c_int), ("autotune", ctypes.c_int), ("fft_variant", ctypes.c_int),
     ]
 
 

@@ -290,6 +290,7 @@ ls_status f32_scratch(ls_plan* p, F32Scratch& s) {
 
 bool valid_opts(const ls_options& o) {
   if (o.use_graphs < 0 || o.use_graphs > 1 || o.autotune < 0 || o.autotune > 1) return false;
+  if (o.fft_variant < 0 || o.fft_variant >= kFftVariants) return false;
   return o.ext >= 0 && o.inner_tol > 0 && o.max_outer >= 1 && o.max_inner >= 1 &&
          (o.precision == LS_FP64 || o.precision == LS_FP32_REFINE) && o.precond >= LS_PREC_BD &&
          o.precond <= LS_PREC_NONE && o.inner_fixed_iters >= 0 && o.max_batch >= 1 &&
@@ -469,6 +470,7 @@ void ls_options_default(ls_options* o) {
   o->max_refine = 10;
   o->use_graphs = 1;
   o->autotune = 1;
+  o->fft_variant = 0;
 }
 
 const char* ls_status_str(ls_status s) {
@@ -529,6 +531,7 @@ static ls_status create_impl(ls_plan* p, const double* m) {
   LS_TRY(plan_alloc(p, (void**)&p->fft_work, sizeof(cplx) * (size_t)p->opt.max_batch * n * p->P));
   LS_TRY(plan_alloc(p, (void**)&p->vtmp, sizeof(cplx) * (size_t)3 * n * n * p->opt.max_batch));
   if (p->opt.precond != LS_PREC_NONE) LS_TRY(slabs_build(p));
+  p->col_variant64 = p->col_variant32 = p->opt.fft_variant;
   if (p->opt.autotune) LS_TRY(fft_autotune(p));
   LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
@@ -577,6 +580,9 @@ ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const dou
     delete p;
     return LS_EDEVICE;
   }
+  if (hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+      p->cus < 1)
+    p->cus = 256;
   if (p->stream == nullptr) {
     // a private blocking stream: ordered with the null stream like it, but
     // capturable into graphs

@@ -29,7 +29,10 @@ namespace {
 
 template <typename T>
 struct Tile {
-  static constexpr int W = 128 / (int)sizeof(T);  // columns per 128-byte line
+  // columns per 64-byte run: a 128-byte line holds two consecutive rows of
+  // the same W columns, so the column pass reads whole lines when a workgroup
+  // takes W columns and the row passes when one takes two rows
+  static constexpr int W = 64 / (int)sizeof(T);
 };
 
 template <typename T, bool INV>
@@ -142,8 +145,10 @@ struct ColCfg {
   static constexpr int STRIDE = N + 1;  // pad: adjacent columns in different banks
 };
 constexpr int kRowHalf = 1;  // row passes: half tile (two workgroups per CU)
-constexpr int kColVariants = 6;  // 0, 1: radix-16 register passes, full / half tile; 2-4: LDS passes V = 0..2;
-                                  // 5: radix-8 register passes (P = 1024..4096; smaller P: LDS passes)
+constexpr int kColVariants = kFftVariants;  // 0, 1: radix-16 register passes, full / half tile; 2-4: LDS passes V = 0..2;
+                                  // 5: radix-8 register passes; 6: even / odd half-length transforms, one
+                                  // column per workgroup; 7: as 0 with a quarter tile (P = 1024..4096;
+                                  // smaller P: LDS passes)
 
 template <typename T>
 __device__ __forceinline__ size_t tiled(int b, int n, int N, int j, int kx) {
@@ -362,8 +367,8 @@ template <> struct RegPlan<11> { static constexpr int R0 = 16, R1 = 16, R2 = 8; 
 template <> struct RegPlan<12> { static constexpr int R0 = 16, R1 = 16, R2 = 16; };
 
 // Columns per workgroup: the most whose padded LDS columns fit in 150 KB
-// with at most 1024 threads (one radix-16 butterfly each); variant H = 1
-// halves it.
+// with at most 1024 threads (one radix-16 butterfly each); variants H = 1, 2
+// halve and quarter it.
 template <typename T, int LOGN, int H = 0>
 struct RegCfg {
   static constexpr int N = 1 << LOGN;
@@ -375,8 +380,11 @@ struct RegCfg {
   static constexpr int fit(int c) {
     return (c * 2 * ROW * (int)sizeof(T) <= 153600 && c * 2 * N / 16 <= 1024) ? fit(2 * c) : c;
   }
-  static constexpr int CPW = fit(1) >> H;
+  // at most one tile of W columns (the group's columns share its rows)
+  static constexpr int C0 = fit(1) < Tile<T>::W ? fit(1) : Tile<T>::W;
+  static constexpr int CPW = (C0 >> H) > 0 ? (C0 >> H) : 1;
   static constexpr int NT = CPW * N / 16;
+  static_assert(CPW <= Tile<T>::W, "a column group stays inside one tile");
   static constexpr size_t lds() { return (size_t)CPW * ROW * sizeof(T); }
 };
 
@@ -389,7 +397,7 @@ __device__ __forceinline__ void bsplit(int bi, int& cc, int& j) {
 }
 
 // Middle pass: LDS -> registers -> LDS.
-template <typename T, int N, int R, int NS, int CPW, int ROW, int NT, bool INV>
+template <typename T, int N, int R, int NS, int CPW, int ROW, int NT, bool INV, int TN = N>
 __device__ __forceinline__ void reg_pass(T* buf, const T* __restrict__ tw, int tid) {
   constexpr int NB = N / R, PER = CPW * NB / NT;
   T a[PER][R];
@@ -403,7 +411,7 @@ __device__ __forceinline__ void reg_pass(T* buf, const T* __restrict__ tw, int t
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int bi = tid + NT * q, cc = bi / NB, j = bi % NB;
-    twiddle_r<T, N, R, NS, INV>(a[q], j, tw);
+    twiddle_r<T, TN, R, NS, INV>(a[q], j, tw);
     dft_r<T, R, INV>(a[q]);
     const int k = j & (NS - 1);
 #pragma unroll
@@ -412,36 +420,45 @@ __device__ __forceinline__ void reg_pass(T* buf, const T* __restrict__ tw, int t
   __syncthreads();
 }
 
+// One group of CPW columns of K2.  Pass 0 takes its inputs (elements
+// j + r N/R0 of column cc, zero past n) from registers, so that a persistent
+// workgroup can load the next group while it transforms this one.
 template <typename T, int LOGN, int H>
-__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_cols_reg(T* __restrict__ X, const T* __restrict__ spec,
-                                                                     const T* __restrict__ tw, int n, int ss,
-                                                                     int groups_per_rhs, int total_groups) {
+__device__ __forceinline__ void cols_reg_load(const T* __restrict__ Xb, T* a, int tid, int n) {
+  using C = RegCfg<T, LOGN, H>;
+  constexpr int N = C::N, CPW = C::CPW, W = Tile<T>::W, R0 = RegPlan<LOGN>::R0, NB = N / R0;
+  int cc, j;
+  bsplit<CPW>(tid, cc, j);
+#pragma unroll
+  for (int r = 0; r < R0; ++r) {
+    const int e = j + r * NB;
+    a[r] = e < n ? Xb[(size_t)e * W + cc] : tmk<T>(0, 0);
+  }
+}
+
+template <typename T, int LOGN, int H>
+__device__ __forceinline__ T* cols_reg_base(T* X, int g, int groups_per_rhs, int n, int& c0) {
+  constexpr int N = 1 << LOGN, CPW = RegCfg<T, LOGN, H>::CPW, W = Tile<T>::W;
+  const int b = g / groups_per_rhs;
+  c0 = (g % groups_per_rhs) * CPW;
+  return X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
+}
+
+template <typename T, int LOGN, int H>
+__device__ __forceinline__ void cols_reg_group(T* __restrict__ Xb, int c0, T* a0, T* buf,
+                                               const T* __restrict__ spec, const T* __restrict__ tw,
+                                               int n, int ss, int tid) {
   using C = RegCfg<T, LOGN, H>;
   using PL = RegPlan<LOGN>;
   constexpr int N = C::N, CPW = C::CPW, ROW = C::ROW, W = Tile<T>::W, NT = C::NT;
   constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
-  extern __shared__ unsigned char lds_raw[];
-  T* buf = reinterpret_cast<T*>(lds_raw);
-  const int tid = threadIdx.x;
-  const int g = xcd_remap(blockIdx.x, total_groups);
-  const int b = g / groups_per_rhs;
-  const int c0 = (g % groups_per_rhs) * CPW;
-  T* Xb = X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
-  auto at = [&](int cc, int j) -> size_t { return (size_t)j * W + cc; };
-  // forward pass 0 (radix 16, span 1): straight from memory, pruned input
+  // forward pass 0 (radix 16, span 1) on the loaded column elements
   {
-    constexpr int NB = N / R0;
     int cc, j;
     bsplit<CPW>(tid, cc, j);
-    T a[R0];
+    dft_r<T, R0, false>(a0);
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int e = j + r * NB;
-      a[r] = e < n ? Xb[at(cc, e)] : tmk<T>(0, 0);
-    }
-    dft_r<T, R0, false>(a);
-#pragma unroll
-    for (int r = 0; r < R0; ++r) buf[cc * ROW + lpad(j * R0 + r)] = a[r];
+    for (int r = 0; r < R0; ++r) buf[cc * ROW + lpad(j * R0 + r)] = a0[r];
   }
   __syncthreads();
   reg_pass<T, N, R1, R0, CPW, ROW, NT, false>(buf, tw, tid);
@@ -490,7 +507,137 @@ __global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_cols_reg(T* __rest
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const int e = j + r * NB;
-      if (e < n) Xb[at(cc, e)] = a[r];
+      if (e < n) Xb[(size_t)e * W + cc] = a[r];
+    }
+  }
+}
+
+template <typename T, int LOGN, int H>
+__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_cols_reg(T* __restrict__ X, const T* __restrict__ spec,
+                                                                     const T* __restrict__ tw, int n, int ss,
+                                                                     int groups_per_rhs, int total_groups) {
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
+  const int tid = threadIdx.x;
+  int c0;
+  T* Xb = cols_reg_base<T, LOGN, H>(X, xcd_remap(blockIdx.x, total_groups), groups_per_rhs, n, c0);
+  T a[RegPlan<LOGN>::R0];
+  cols_reg_load<T, LOGN, H>(Xb, a, tid, n);
+  cols_reg_group<T, LOGN, H>(Xb, c0, a, buf, spec, tw, n, ss, tid);
+}
+
+// Column pass as two half-length problems (variants 6, 7).  A column has
+// nonzeros only in its first N/2 entries, so its length-N transform splits
+// into X[2k] = F_{N/2}(x)[k] and X[2k+1] = F_{N/2}(x_j W_N^j)[k]; after the
+// spectrum multiply the kept outputs are y_j = F^-1(Y_even)[j] +
+// W_N^-j F^-1(Y_odd)[j] (unnormalised inverses, j < N/2).  One workgroup
+// (one wave for N <= 2048) per column, half the LDS of the full-length
+// transform, and its barriers involve only that wave, so the waves of a CU
+// run out of step: one loads while another transforms.  The even half's
+// output stays in registers while the odd half runs.
+template <int LOGN> struct EoPlan;
+template <> struct EoPlan<10> { static constexpr int R0 = 8, R1 = 8, R2 = 8; };
+template <> struct EoPlan<11> { static constexpr int R0 = 16, R1 = 16, R2 = 4; };
+template <> struct EoPlan<12> { static constexpr int R0 = 16, R1 = 16, R2 = 8; };
+
+template <typename T, int LOGN>
+struct EoCfg {
+  static constexpr int N = 1 << LOGN, M = N / 2;
+  static constexpr int NT = M / EoPlan<LOGN>::R0;  // one first-pass butterfly per thread
+  static constexpr int ROW = M + M / 16 + 2;
+  static constexpr size_t lds() { return (size_t)ROW * sizeof(T); }
+};
+
+template <typename T, int LOGN, int H2>
+__device__ __forceinline__ void eo_half(const T* __restrict__ Xb, T* a, T* buf, const T* __restrict__ spec,
+                                        const T* __restrict__ tw, int n, int ss, int kxq, int tid) {
+  using C = EoCfg<T, LOGN>;
+  using PL = EoPlan<LOGN>;
+  constexpr int N = C::N, M = C::M, ROW = C::ROW, NT = C::NT, W = Tile<T>::W;
+  constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2, NB0 = M / R0;
+  // forward pass 0 from memory (odd half: times W_N^j, j = tid + r NB0, as
+  // W_N^tid W_N^(r NB0): one per-lane table entry and R0 uniform ones)
+  const T t0 = H2 ? tw[tid] : tmk<T>(1, 0);
+#pragma unroll
+  for (int r = 0; r < R0; ++r) {
+    const int e = tid + r * NB0;
+    T v = e < n ? Xb[(size_t)e * W] : tmk<T>(0, 0);
+    if (H2 && r > 0) v = tmul(v, tw[r * NB0]);
+    if (H2) v = tmul(v, t0);
+    a[r] = v;
+  }
+  dft_r<T, R0, false>(a);
+#pragma unroll
+  for (int r = 0; r < R0; ++r) buf[lpad(tid * R0 + r)] = a[r];
+  __syncthreads();
+  reg_pass<T, M, R1, R0, 1, ROW, NT, false, N>(buf, tw, tid);
+  {  // forward last pass, spectrum at ky = 2 k + H2, inverse first pass
+    constexpr int NB = M / R2, NS = R0 * R1, PER = NB / NT;
+    T b[PER][R2];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + NT * q;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) b[q][r] = buf[lpad(j + r * NB)];
+    }
+    __syncthreads();
+  #pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + NT * q;
+      twiddle_r<T, N, R2, NS, false>(b[q], j, tw);
+      dft_r<T, R2, false>(b[q]);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int ky = 2 * (j + r * NB) + H2;
+        const int kyq = ky <= N / 2 ? ky : N - ky;
+        b[q][r] = tmul(b[q][r], spec[(size_t)kxq * ss + kyq]);
+      }
+      dft_r<T, R2, true>(b[q]);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) buf[lpad(j * R2 + r)] = b[q][r];
+    }
+  }
+  __syncthreads();
+  reg_pass<T, M, R1, R2, 1, ROW, NT, true, N>(buf, tw, tid);
+  {  // inverse last pass: natural order, element tid + r NB0 in a[r]
+    constexpr int NS = R2 * R1;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) a[r] = buf[lpad(tid + r * NB0)];
+    twiddle_r<T, N, R0, NS, true>(a, tid, tw);
+    dft_r<T, R0, true>(a);
+  }
+}
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__((EoCfg<T, LOGN>::NT)) void k_cols_eo(T* __restrict__ X, const T* __restrict__ spec,
+                                                                const T* __restrict__ tw, int n, int ss,
+                                                                int cols_per_rhs, int total) {
+  using C = EoCfg<T, LOGN>;
+  constexpr int N = C::N, W = Tile<T>::W, R0 = EoPlan<LOGN>::R0, NB0 = C::M / R0;
+  extern __shared__ unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int g = xcd_remap(blockIdx.x, total);
+  const int b = g / cols_per_rhs, c = g % cols_per_rhs;
+  T* Xb = X + (size_t)b * n * N + (size_t)(c / W) * n * W + (c % W);
+  const int kxq = c <= N / 2 ? c : N - c;
+  T e[R0], o[R0];
+  eo_half<T, LOGN, 0>(Xb, e, buf, spec, tw, n, ss, kxq, tid);
+  __syncthreads();  // the even half's last reads before the odd half's first writes
+  eo_half<T, LOGN, 1>(Xb, o, buf, spec, tw, n, ss, kxq, tid);
+  T t0 = tw[tid];
+  t0.y = -t0.y;
+#pragma unroll
+  for (int r = 0; r < R0; ++r) {
+    const int j = tid + r * NB0;
+    if (j < n) {
+      T v = tmul(o[r], t0);
+      if (r > 0) {
+        T w = tw[r * NB0];
+        w.y = -w.y;
+        v = tmul(v, w);
+      }
+      Xb[(size_t)j * W] = tadd(e[r], v);
     }
   }
 }
@@ -513,8 +660,9 @@ struct Reg4Cfg {
   static constexpr int fit(int c) {
     return (c * 2 * ROW * (int)sizeof(T) <= 153600 && c * 2 * N / 8 <= MAXT) ? fit(2 * c) : c;
   }
-  static constexpr int CPW = fit(1);
+  static constexpr int CPW = fit(1) < Tile<T>::W ? fit(1) : Tile<T>::W;
   static constexpr int NT = CPW * N / 8;  // one radix-8 butterfly per thread
+  static_assert(CPW <= Tile<T>::W, "a column group stays inside one tile");
   static constexpr size_t lds() { return (size_t)CPW * ROW * sizeof(T); }
 };
 
@@ -861,6 +1009,17 @@ ls_status run_cols_reg(const ApplyView<T, typename CT<T>::R>& av, int batch) {
 }
 
 template <typename T, int LOGN>
+ls_status run_cols_eo(const ApplyView<T, typename CT<T>::R>& av, int batch) {
+  using C = EoCfg<T, LOGN>;
+  constexpr int N = 1 << LOGN;
+  LS_SET_LDS_ONCE((k_cols_eo<T, LOGN>), C::lds());
+  const int total = N * batch;
+  k_cols_eo<T, LOGN><<<total, C::NT, C::lds(), av.stream>>>(av.work, av.spec, av.tw, av.n, av.ss, N, total);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+template <typename T, int LOGN>
 ls_status run_cols_reg4(const ApplyView<T, typename CT<T>::R>& av, int batch) {
   using RC = Reg4Cfg<T, LOGN>;
   constexpr int N = 1 << LOGN;
@@ -905,6 +1064,14 @@ ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, doub
     case 5:
       if constexpr (reg) LS_TRY((run_cols_reg4<T, LOGN>(av, batch)));
       else LS_TRY((run_cols<T, LOGN, 0>(av, batch)));
+      break;
+    case 6:
+      if constexpr (reg) LS_TRY((run_cols_eo<T, LOGN>(av, batch)));
+      else LS_TRY((run_cols<T, LOGN, 0>(av, batch)));
+      break;
+    case 7:
+      if constexpr (reg) LS_TRY((run_cols_reg<T, LOGN, 2>(av, batch)));
+      else LS_TRY((run_cols<T, LOGN, 2>(av, batch)));
       break;
     default:
       if constexpr (reg) LS_TRY((run_cols_reg<T, LOGN, 0>(av, batch)));

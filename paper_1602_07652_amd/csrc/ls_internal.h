@@ -156,6 +156,7 @@ struct ApplyView {
   int n, ss;
   hipStream_t stream;
   int col_variant;  // column-pass tile variant chosen by the autotuner
+  int cus;          // compute units of the device (persistent grids)
 };
 
 // A captured inner-preconditioner application.
@@ -209,16 +210,17 @@ struct ls_plan {
   std::vector<GraphEntry> graphs;
   cplx* solve_buf = nullptr;     // FP64 plans, learned solves: two grid-vector batches
   int col_variant64 = 0, col_variant32 = 0;  // autotuned FFT column-pass variants
-  float tune_ms64[6] = {0, 0, 0, 0, 0, 0}, tune_ms32[6] = {0, 0, 0, 0, 0, 0};
+  float tune_ms64[8] = {}, tune_ms32[8] = {};
+  int cus = 256;                 // compute units of the plan's device
 };
 
 inline ApplyView<cplx, double> view64(ls_plan* p) {
   return ApplyView<cplx, double>{p->m,    p->spec,       p->tw,     p->fft_work,
-                                 p->n,    p->spec_side,  p->stream, p->col_variant64};
+                                 p->n,    p->spec_side,  p->stream, p->col_variant64, p->cus};
 }
 inline ApplyView<fcplx, float> view32(ls_plan* p) {
   return ApplyView<fcplx, float>{p->f32.m, p->f32.spec,   p->f32.tw, p->f32.fft_work,
-                                 p->n,     p->spec_side,  p->stream, p->col_variant32};
+                                 p->n,     p->spec_side,  p->stream, p->col_variant32, p->cus};
 }
 
 // fno.hip: the network as a residual map z = r + s y(m, u_I, r / s) on the
@@ -243,6 +245,7 @@ ls_status fft2_full_forward(ls_plan* p, cplx* c);                // in place, P 
 ls_status spectrum_extract(ls_plan* p, const cplx* c);           // -> p->spec
 ls_status apply_H(ls_plan* p, const cplx* v, cplx* y, int batch, double sign_identity, double scale_conv);
 ls_status apply_H32(ls_plan* p, const fcplx* v, fcplx* y, int batch, double sign_identity, double scale_conv);
+constexpr int kFftVariants = 8;  // FFT column-pass variants (fft.hip)
 ls_status fft_autotune(ls_plan* p);
 // stencil.hip
 ls_status stencils_build(ls_plan* p, const cplx* circ);

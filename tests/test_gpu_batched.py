@@ -107,3 +107,36 @@ def test_fp32_batched_level_steps_match_single_rhs():
         assert e < 1e-4
     pb.close()
     ps.close()
+
+
+@pytest.fixture(scope="module")
+def apply_refs():
+    """Oracle operator applications for the column-pass variant sweep."""
+    out = {}
+    for n, B in [(300, 2), (600, 2), (1024, 1)]:
+        m, _ = li.gaussian_bumps_medium(n, seed=n + 1)
+        omega = 2 * np.pi * n / 10
+        v = li.random_complex((B, n, n), seed=n + 2)
+        W = kernel.kernel_samples(n, 1.0 / n, omega)
+        Gh = kernel.circulant_spectrum(W)
+        ref = np.stack([kernel.apply_H(W, m, v[k], omega, Gh) for k in range(B)])
+        ref32 = np.stack([kernel.apply_H(W, m, v[k].astype(np.complex64).astype(np.complex128), omega, Gh)
+                          for k in range(B)])
+        out[n] = (m, v, ref, ref32)
+    return out
+
+
+@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("n", [300, 600, 1024])
+def test_every_fft_column_variant_matches_oracle(apply_refs, n, variant):
+    """Each column-pass variant, forced (no autotuning), in FP64 and FP32:
+    P = 1024 (n = 300), P = 2048 with a ragged column (n = 600) and with
+    n = P / 2 (n = 1024)."""
+    m, v, ref, ref32 = apply_refs[n]
+    B = v.shape[0]
+    p, _ = make(n, m, slabs=n // 50, max_batch=B, precision=1, autotune=0, fft_variant=variant)
+    e64 = rel(host(p.apply(dev(v))), ref)
+    e32 = rel(host(p.apply_c64(dev(v, torch.complex64))), ref32)
+    banner(f"variant {variant} n={n}: FP64 rel err {e64:.3e}, FP32 {e32:.3e}")
+    assert e64 < 1e-13 and e32 < 5e-6
+    p.close()
