@@ -29,10 +29,7 @@ namespace {
 
 template <typename T>
 struct Tile {
-  // columns per 64-byte run: a 128-byte line holds two consecutive rows of
-  // the same W columns, so the column pass reads whole lines when a workgroup
-  // takes W columns and the row passes when one takes two rows
-  static constexpr int W = 64 / (int)sizeof(T);
+  static constexpr int W = 128 / (int)sizeof(T);  // columns per 128-byte line
 };
 
 template <typename T, bool INV>
@@ -200,6 +197,20 @@ __device__ __forceinline__ int xcd_remap(int id, int total) {
   return (id % 8) * per + id / 8;
 }
 
+// Column group g -> (right-hand side b, group cg).  The S = W / CPW groups
+// that share the 128-byte lines of one tile of W columns are consecutive,
+// then come the other right-hand sides of that tile, then the mirror tile
+// (columns N - kx read the same rows of the quarter spectrum as kx): the run
+// of groups one XCD takes reads each line and each spectrum row into its L2
+// once.  N / W is even.
+__device__ __forceinline__ void col_group(int g, int G, int total, int S, int& b, int& cg) {
+  const int B = total / G, M = G / S;
+  const int P = g / (S * B), rem = g - P * S * B;
+  b = rem / S;
+  const int tile = (P & 1) ? M - 1 - (P >> 1) : (P >> 1);
+  cg = tile * S + (rem - b * S);
+}
+
 // K2: per column c of X: FFT, multiply by the spectrum, IFFT, keep n.
 template <typename T, int LOGN, int V>
 __global__ __launch_bounds__((ColCfg<T, LOGN, V>::NT)) void k_cols_conv(T* __restrict__ X,
@@ -213,8 +224,9 @@ __global__ __launch_bounds__((ColCfg<T, LOGN, V>::NT)) void k_cols_conv(T* __res
   T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   const int g = xcd_remap(blockIdx.x, total_groups);
-  const int b = g / groups_per_rhs;
-  const int c0 = (g % groups_per_rhs) * CPW;
+  int b, cg;
+  col_group(g, groups_per_rhs, total_groups, W / CPW, b, cg);
+  const int c0 = cg * CPW;
   T* Xb = X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
   for (int e = tid; e < CPW * n; e += C::NT) {
     const int j = e / CPW, cc = e % CPW;
@@ -437,10 +449,11 @@ __device__ __forceinline__ void cols_reg_load(const T* __restrict__ Xb, T* a, in
 }
 
 template <typename T, int LOGN, int H>
-__device__ __forceinline__ T* cols_reg_base(T* X, int g, int groups_per_rhs, int n, int& c0) {
+__device__ __forceinline__ T* cols_reg_base(T* X, int g, int groups_per_rhs, int total, int n, int& c0) {
   constexpr int N = 1 << LOGN, CPW = RegCfg<T, LOGN, H>::CPW, W = Tile<T>::W;
-  const int b = g / groups_per_rhs;
-  c0 = (g % groups_per_rhs) * CPW;
+  int b, cg;
+  col_group(g, groups_per_rhs, total, W / CPW, b, cg);
+  c0 = cg * CPW;
   return X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
 }
 
@@ -520,7 +533,7 @@ __global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_cols_reg(T* __rest
   T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   int c0;
-  T* Xb = cols_reg_base<T, LOGN, H>(X, xcd_remap(blockIdx.x, total_groups), groups_per_rhs, n, c0);
+  T* Xb = cols_reg_base<T, LOGN, H>(X, xcd_remap(blockIdx.x, total_groups), groups_per_rhs, total_groups, n, c0);
   T a[RegPlan<LOGN>::R0];
   cols_reg_load<T, LOGN, H>(Xb, a, tid, n);
   cols_reg_group<T, LOGN, H>(Xb, c0, a, buf, spec, tw, n, ss, tid);
@@ -618,7 +631,8 @@ __global__ __launch_bounds__((EoCfg<T, LOGN>::NT)) void k_cols_eo(T* __restrict_
   T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   const int g = xcd_remap(blockIdx.x, total);
-  const int b = g / cols_per_rhs, c = g % cols_per_rhs;
+  int b, c;
+  col_group(g, cols_per_rhs, total, W, b, c);
   T* Xb = X + (size_t)b * n * N + (size_t)(c / W) * n * W + (c % W);
   const int kxq = c <= N / 2 ? c : N - c;
   T e[R0], o[R0];
@@ -678,8 +692,9 @@ __global__ __launch_bounds__((Reg4Cfg<T, LOGN>::NT)) void k_cols_reg4(T* __restr
   T* buf = reinterpret_cast<T*>(lds_raw);
   const int tid = threadIdx.x;
   const int g = xcd_remap(blockIdx.x, total_groups);
-  const int b = g / groups_per_rhs;
-  const int c0 = (g % groups_per_rhs) * CPW;
+  int b, cg;
+  col_group(g, groups_per_rhs, total_groups, W / CPW, b, cg);
+  const int c0 = cg * CPW;
   T* Xb = X + (size_t)b * n * N + (size_t)(c0 / W) * n * W + (c0 % W);
   {  // forward pass 0 (radix R0, span 1) from memory, pruned input
     constexpr int NB = N / R0;
