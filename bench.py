@@ -288,7 +288,12 @@ def main():
                          "batched = only the multi-grid variant; learned = only the learned-form "
                          "variant; apply = only ls_apply of the bench workload at batch 8; "
                          "fno = only the network's training step and inference")
+    ap.add_argument("--fft-variant", type=int, default=None,
+                    help="apply mode: force this FFT column-pass variant (no autotuning) and time the "
+                         "FP32 operator of the same plan too")
     args = ap.parse_args()
+    if args.fft_variant is not None and args.mode != "apply":
+        ap.error("--fft-variant is for --mode apply")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on a "
               f"single MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -325,7 +330,10 @@ def main():
     m_d = torch.from_numpy(cfg["m"]).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, max_batch=8)
+    popts = {}
+    if args.fft_variant is not None:
+        popts = dict(autotune=0, fft_variant=args.fft_variant, precision=1)
+    plan = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, max_batch=8, **popts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"plan created in {setup_s:.2f} s")
@@ -341,8 +349,20 @@ def main():
             plan.apply(vb, out=yb)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.slab_reps
-        print(json.dumps({"mode": "apply", "batch": Bt, "reps": args.slab_reps, "ms": dt * 1e3,
-                          "alg_bytes": apply_bytes(n, Bt)}))
+        out = {"mode": "apply", "batch": Bt, "reps": args.slab_reps, "ms": dt * 1e3,
+               "alg_bytes": apply_bytes(n, Bt)}
+        if args.fft_variant is not None:
+            v32 = vb.to(torch.complex64)
+            y32 = torch.empty_like(v32)
+            for _ in range(2):
+                plan.apply_c64(v32, out=y32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.slab_reps):
+                plan.apply_c64(v32, out=y32)
+            torch.cuda.synchronize()
+            out.update(fft_variant=args.fft_variant, fp32_ms=(time.perf_counter() - t0) / args.slab_reps * 1e3)
+        print(json.dumps(out))
         plan.close()
         return
     if args.mode == "slab":
