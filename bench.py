@@ -150,13 +150,15 @@ def learned_variant(tol, log_fn, weights):
     256^2, 512^2, 1024^2 (omega = 2 pi n / 10, 64 lines per layer), FP32
     operator and slab solves with FP64 refinement, all grids at once.  Arm A:
     ls_solve_multi (plain two-level preconditioner).  Arm B:
-    ls_solve_fno_multi with the trained network as warm start (mode 1).
+    ls_solve_fno_multi with the trained network as warm start, probed on the
+    first wave of each medium (modes LS_FNO_WARM | LS_FNO_PROBE: where that
+    warm start is dropped the network is not evaluated for the other waves).
     Returns a summary of both arms."""
     import numpy as np
     import torch
     import ls_inputs as li
-    from paper_1602_07652_amd import (Plan, Fno, LS_FP32_REFINE, LS_FNO_WARM, solve_multi,
-                                      solve_fno_multi)
+    from paper_1602_07652_amd import (Plan, Fno, LS_FP32_REFINE, LS_FNO_WARM, LS_FNO_PROBE,
+                                      LS_FNO_WARM_SKIPPED, solve_multi, solve_fno_multi)
     from paper_1602_07652_amd.fno_train import load_weights
     dev = torch.device("cuda:0")
     params, meta = load_weights(weights)
@@ -183,7 +185,8 @@ def learned_variant(tol, log_fn, weights):
     arms = {}
     for arm in ("plain", "learned"):
         run = (lambda: solve_multi(plans, fs, tol=tol, outs=us)) if arm == "plain" else \
-              (lambda: solve_fno_multi(plans, nets, uIs, fs, tol=tol, mode=LS_FNO_WARM, outs=us))
+              (lambda: solve_fno_multi(plans, nets, uIs, fs, tol=tol, mode=LS_FNO_WARM | LS_FNO_PROBE,
+                                       outs=us))
         run()                                   # warm-up: graphs, Krylov spaces
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -196,7 +199,9 @@ def learned_variant(tol, log_fn, weights):
                           "outer_its_mean": float(np.mean([i["outer_its"] for i in inf])),
                           "relres_true_max": max(i["relres_true"] for i in inf),
                           "converged": all(i["converged"] for i in inf),
-                          "warm_kept": int(sum(1 for i in inf if i.get("fno_flags", 0) & 1))}
+                          "warm_kept": int(sum(1 for i in inf if i.get("fno_flags", 0) & 1)),
+                          "net_skipped": int(sum(1 for i in inf
+                                                 if i.get("fno_flags", 0) & LS_FNO_WARM_SKIPPED))}
                          for p, inf in zip(plans, infos)],
         }
         log_fn(f"learned-form job, {arm}: {total} solves in {wall:.3f} s = {total / wall:.1f} solves/s; "

@@ -54,14 +54,19 @@ extern "C" {
 #define LS_FNO_PARAMS 4203202
 
 /* Modes of ls_solve_fno (bit set). */
-#define LS_FNO_WARM 1 /* initial guess u0 = FNO(m, u_I, f) */
-#define LS_FNO_PREC 2 /* FNO as the flexible-GMRES preconditioner */
+#define LS_FNO_WARM 1  /* initial guess u0 = FNO(m, u_I, f) */
+#define LS_FNO_PREC 2  /* FNO as the flexible-GMRES preconditioner */
+#define LS_FNO_PROBE 4 /* with LS_FNO_WARM: the first right-hand side of the call is tried alone; if its
+                        * warm start is dropped, the network is not evaluated for the others (same
+                        * medium and grid) and no FNO-preconditioned pass runs */
 
 /* Bits of ls_solve_info.fno_flags. */
 #define LS_FNO_WARM_USED 1      /* the warm start was kept */
 #define LS_FNO_WARM_REJECTED 2  /* the warm start was worse than u0 = 0 (or not finite): dropped */
 #define LS_FNO_PREC_USED 4      /* the FNO-preconditioned pass was kept */
 #define LS_FNO_PREC_FALLBACK 8  /* it stagnated: its correction was dropped, BD finished the solve */
+#define LS_FNO_WARM_SKIPPED 16  /* LS_FNO_PROBE: the probe's warm start was dropped, the network was not
+                                 * evaluated for this right-hand side (u0 = 0) */
 
 typedef struct ls_fno ls_fno;
 
@@ -125,7 +130,7 @@ ls_status ls_bf16_gemm(int M, int N, int K, int batch, const float* A, long long
                        long long sbn, long long sbb, float* C, long long scm, long long scn,
                        long long scb, float alpha, float beta, hipStream_t stream);
 
-/* ls_solve with the network (modes LS_FNO_WARM | LS_FNO_PREC) for the plan's
+/* ls_solve with the network (modes LS_FNO_WARM | LS_FNO_PREC | LS_FNO_PROBE) for the plan's
  * medium and the incident fields uI [batch][n][n] that produced f.  The
  * plain two-level preconditioner stays the fallback: a warm start whose
  * residual is not below ||f|| is dropped; an FNO-preconditioned pass that

@@ -296,7 +296,8 @@ class Plan:
 
     def solve_fno(self, fno, uI, f, tol=1e-8, mode=3, out=None, allow_noconv=False):
         """ls_solve_fno: solve with the network as warm start (mode bit 1)
-        and / or flexible-GMRES preconditioner (bit 2), plain BD fallback."""
+        and / or flexible-GMRES preconditioner (bit 2), plain BD fallback;
+        bit 4 probes the warm start on the first right-hand side first."""
         b = self._batch(f)
         out = torch.empty_like(f) if out is None else out
         N = self.n * self.n * b
@@ -308,8 +309,9 @@ class Plan:
         return out, [i.as_dict() for i in infos]
 
 
-LS_FNO_WARM, LS_FNO_PREC = 1, 2
+LS_FNO_WARM, LS_FNO_PREC, LS_FNO_PROBE = 1, 2, 4
 LS_FNO_WARM_USED, LS_FNO_WARM_REJECTED, LS_FNO_PREC_USED, LS_FNO_PREC_FALLBACK = 1, 2, 4, 8
+LS_FNO_WARM_SKIPPED = 16
 
 
 def fno_param_count() -> int:

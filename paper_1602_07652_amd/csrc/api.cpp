@@ -890,7 +890,8 @@ ls_status ls_solve_multi(ls_plan* const* plans, int count, const double* const* 
 ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f, double* u, int batch,
                        double tol, int mode, ls_solve_info* info) {
   if (!p || !fn || !uI || !f || !u || batch < 1 || f == u || !(tol > 0) || mode < 0 ||
-      mode > (LS_FNO_WARM | LS_FNO_PREC)) {
+      mode > (LS_FNO_WARM | LS_FNO_PREC | LS_FNO_PROBE) ||
+      ((mode & LS_FNO_PROBE) && !(mode & LS_FNO_WARM))) {
     ls_set_error("ls_solve_fno: bad arguments");
     return LS_EINVAL;
   }
@@ -911,6 +912,9 @@ ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f
   cplx* rbuf = p->vtmp + BN;
   const int chunk = p->opt.max_batch;  // the network runs in its own sub-batches
   bool all = true;
+  // LS_FNO_PROBE: the first right-hand side's warm start decides whether the
+  // network is evaluated for the others (same medium, same grid)
+  bool probed = !(mode & LS_FNO_PROBE), net_ok = true;
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int B = std::min(chunk, batch - b0);
     const auto t0 = std::chrono::steady_clock::now();
@@ -921,14 +925,30 @@ ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f
     std::vector<double> nf(B), rel(B, 0.0);
     LS_TRY(vec_norms(p, fb, N, B, nf.data()));
     if (mode & LS_FNO_WARM) {
-      LS_TRY(fno_residual_map<cplx>(fn, n, B, p->m, 0, uIb, fb, ub));  // u0 = f + s y
-      LS_TRY(true_residual(p, fb, ub, rbuf, B, nf, rel));
+      int done = 0;  // right-hand sides whose warm start was evaluated
+      if (!probed) {
+        LS_TRY(fno_residual_map<cplx>(fn, n, 1, p->m, 0, uIb, fb, ub));  // u0 = f + s y
+        std::vector<double> rel1;
+        LS_TRY(true_residual(p, fb, ub, rbuf, 1, nf, rel1));
+        rel[0] = rel1[0];
+        net_ok = nf[0] > 0 && rel[0] < 1.0;
+        probed = true;
+        done = 1;
+      }
+      if (net_ok && done < B) {
+        std::vector<double> nfr(nf.begin() + done, nf.end()), relr;
+        LS_TRY(fno_residual_map<cplx>(fn, n, B - done, p->m, 0, uIb + 2 * done * N, fb + done * N,
+                                      ub + done * N));
+        LS_TRY(true_residual(p, fb + done * N, ub + done * N, rbuf + done * N, B - done, nfr, relr));
+        std::copy(relr.begin(), relr.end(), rel.begin() + done);
+        done = B;
+      }
       for (int i = 0; i < B; ++i) {
-        if (nf[i] > 0 && rel[i] < 1.0) {
+        if (i < done && nf[i] > 0 && rel[i] < 1.0) {
           flags[i] |= LS_FNO_WARM_USED;
           continue;
         }
-        flags[i] |= nf[i] > 0 ? LS_FNO_WARM_REJECTED : 0;
+        if (nf[i] > 0) flags[i] |= i < done ? LS_FNO_WARM_REJECTED : LS_FNO_WARM_SKIPPED;
         LS_TRY(vec_zero(p, ub + i * N, N));
         LS_TRY(vec_copy(p, rbuf + i * N, fb + i * N, N));
         rel[i] = nf[i] > 0 ? 1.0 : 0.0;
@@ -938,7 +958,7 @@ ls_status ls_solve_fno(ls_plan* p, ls_fno* fn, const double* uI, const double* f
       LS_TRY(vec_copy(p, rbuf, fb, N * B));
       for (int i = 0; i < B; ++i) rel[i] = nf[i] > 0 ? 1.0 : 0.0;
     }
-    if (mode & LS_FNO_PREC) {
+    if ((mode & LS_FNO_PREC) && net_ok) {
       // one flexible-GMRES pass preconditioned by the network; kept per
       // right-hand side only if it at least halves the residual
       std::vector<double> scale, back;

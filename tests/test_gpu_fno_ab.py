@@ -132,3 +132,31 @@ def test_ab_beyond_training_size(trained, n):
         banner(f"n={n}: oracle residual of the warm-started solution {res:.2e}")
         assert res < 2e-8
     plan.close()
+
+
+def test_probe_skips_the_network_where_its_warm_start_is_dropped(trained):
+    """LS_FNO_PROBE: at 256^2 (training size) the probe's warm start is kept
+    and every wave gets one; at 1024^2 it is dropped and the other waves
+    start from zero without evaluating the network.  Every solve reaches tol."""
+    from paper_1602_07652_amd import (Plan, LS_FNO_WARM, LS_FNO_PROBE, LS_FNO_WARM_USED,
+                                      LS_FNO_WARM_REJECTED, LS_FNO_WARM_SKIPPED)
+    fno, _, _ = trained
+    for n, B in [(256, 6), (1024, 3)]:
+        m, omega, _ = _case(n, 5300 + n)
+        uI = np.stack([li.plane_wave(n, omega, 2 * np.pi * k / B) for k in range(B)])
+        plan = Plan(n, 1.0 / n, omega, dev(m, torch.float64), slabs=n // 64, max_batch=B, precision=1)
+        uId = dev(uI)
+        f = plan.rhs_from_incident(uId)
+        u, infos = plan.solve_fno(fno, uId, f, tol=1e-8, mode=LS_FNO_WARM | LS_FNO_PROBE)
+        flags = [i["fno_flags"] for i in infos]
+        banner(f"probe n={n}: flags {flags}, outer its {[i['outer_its'] for i in infos]}")
+        assert all(i["converged"] == 1 and i["relres_true"] <= 1e-8 for i in infos)
+        if flags[0] & LS_FNO_WARM_USED:
+            assert all(fl & (LS_FNO_WARM_USED | LS_FNO_WARM_REJECTED) for fl in flags)
+            assert not any(fl & LS_FNO_WARM_SKIPPED for fl in flags)
+        else:
+            assert flags[0] & LS_FNO_WARM_REJECTED
+            assert all(fl == LS_FNO_WARM_SKIPPED for fl in flags[1:])
+        if n == 256:
+            assert flags[0] & LS_FNO_WARM_USED
+        plan.close()
