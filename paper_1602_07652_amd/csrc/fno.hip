@@ -26,6 +26,12 @@ constexpr int kIn = 5, kOut = 2;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// GELU (erf form) and its derivative
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float x) {
+  return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
 // ------------------------------------------------------------------ GEMM
 struct GemmP {
   int M, N, K;
@@ -40,6 +46,7 @@ struct GemmP {
   float alpha, beta;
   const float* bias_m;  // added to row m (split 0 only)
   int atomic;           // split K: accumulate with atomic adds
+  float* C2;            // if set: GELU of the result, same layout as C (C may then be null)
 };
 
 // Tile BM x BN x 32, 256 threads = 4 waves in a WM x WN grid; each wave
@@ -130,7 +137,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmP g) {
     }
   }
   // D layout: lane holds rows 4*(lane/16) + 0..3 of column lane % 16
-  float* __restrict__ C = g.C + b * g.scb;
+  float* __restrict__ C = g.C ? g.C + b * g.scb : nullptr;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -142,6 +149,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmP g) {
         if (m >= g.M || n >= g.N) continue;
         float v = g.alpha * acc[i][j][t];
         if (g.bias_m && blockIdx.z == 0) v += g.bias_m[m];
+        const long long co = b * g.scb + m * g.scm + n * g.scn;
+        if (g.C2) {  // single split, beta = 0
+          if (g.C) g.C[co] = v;
+          g.C2[co] = gelu_f(v);
+          continue;
+        }
         float* c = C + m * g.scm + n * g.scn;
         if (g.atomic)
           atomicAdd(c, v);
@@ -200,7 +213,11 @@ ls_status gemm(GemmP g, int batch, hipStream_t st) {
     LS_HIP(hipGetLastError());
     return LS_OK;
   }
-  if (tiles < 512 && g.K >= 1024) {
+  if (g.C2 && g.beta != 0.f) {
+    ls_set_error("bf16 GEMM: a GELU output needs beta = 0");
+    return LS_EINVAL;
+  }
+  if (tiles < 512 && g.K >= 1024 && !g.C2) {
     splits = (int)std::min<long long>((1024 + tiles - 1) / tiles, g.K / 512);
     if (splits < 1) splits = 1;
   }
@@ -240,20 +257,77 @@ GemmP gp(int M, int N, int K, const float* A, long long sam, long long sak, long
 }
 
 // ----------------------------------------------------------- elementwise
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_d(float x) {
-  return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
-}
-
-__global__ void k_gelu(const float* __restrict__ z, float* __restrict__ v, size_t cnt) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (size_t)gridDim.x * blockDim.x)
-    v[i] = gelu_f(z[i]);
-}
 
 // g *= GELU'(z)
 __global__ void k_gelu_back(float* __restrict__ g, const float* __restrict__ z, size_t cnt) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (size_t)gridDim.x * blockDim.x)
     g[i] *= gelu_d(z[i]);
+}
+
+// Output of Fourier layer l for one row j of one sample s, as one K = 64
+// product on matrix cores:
+//   z[s][o][j n + i] = sum_x' U[s][o][j][x'] Gx[x'][i] + sum_c W[o][c] v[s][c][j n + i] + b[o]
+// (the inverse DFT along x of the mixed modes plus the pointwise map), then
+// z is stored when requested and GELU(z) written as the next layer's input.
+// A workgroup takes 32 outputs x kLBN pixels of the row; wave w owns
+// pixels [32 w, 32 w + 32) as 2 x 2 tiles of 16 x 16 (16x16x32 bf16 MFMA).
+constexpr int kLBN = 128;
+__global__ __launch_bounds__(256) void k_layer_out(const float* __restrict__ U, const float* __restrict__ Gx,
+                                                   const float* __restrict__ Wt, const float* __restrict__ bias,
+                                                   const float* __restrict__ v, float* __restrict__ z,
+                                                   float* __restrict__ vn, int n) {
+  constexpr int K = 64, LDK = 72;
+  __shared__ __attribute__((aligned(16))) __bf16 As[kW * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[kLBN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * kLBN, j = blockIdx.y, s = blockIdx.z;
+  const long long P = (long long)n * n;
+  for (int e = tid; e < kW * K; e += 256) {
+    const int o = e / K, k = e % K;
+    const float a = k < 32 ? U[(((long long)s * kW + o) * n + j) * 32 + k] : Wt[o * kW + (k - 32)];
+    As[o * LDK + k] = (__bf16)a;
+  }
+  for (int e = tid; e < K * kLBN; e += 256) {
+    const int k = e / kLBN, ii = e % kLBN, i = i0 + ii;  // pixels fastest: coalesced
+    float b = 0.f;
+    if (i < n)
+      b = k < 32 ? Gx[(long long)k * n + i] : v[((long long)s * kW + (k - 32)) * P + (long long)j * n + i];
+    Bs[ii * LDK + k] = (__bf16)b;
+  }
+  __syncthreads();
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < K; ks += 32) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[(a * 16 + r16) * LDK + ks + kq]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bs[(wave * 32 + c * 16 + r16) * LDK + ks + kq]);
+        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[a][c], 0, 0, 0);
+      }
+    }
+  }
+  // D layout: lane holds rows 4 (lane / 16) + t of column lane % 16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int o = a * 16 + (lane >> 4) * 4 + t;
+        const int i = i0 + wave * 32 + c * 16 + (lane & 15);
+        if (i >= n) continue;
+        const float val = acc[a][c][t] + bias[o];
+        const long long idx = ((long long)s * kW + o) * P + (long long)j * n + i;
+        if (z) z[idx] = val;
+        if (vn) vn[idx] = gelu_f(val);
+      }
 }
 
 // DFT tables for grid side n (angles in FP64, stored FP32):
@@ -660,25 +734,22 @@ ls_status forward(ls_fno* f, int n, int S, const float* x, float* y, bool keep) 
     LS_HIP(hipGetLastError());
     // U[s,o] = Ai Bst[s,o]
     LS_TRY(gemm(gp(n, 32, 64, tb->Ai, 64, 1, 0, f->Bst, 32, 1, 64 * 32, f->U, 32, 1, (long long)n * 32), S * kW, st));
-    // z[(s,o,j)][i] = sum_x' U[(s,o,j)][x'] Gx[x'][i]
-    LS_TRY(gemm(gp(S * kW * n, n, 32, f->U, 32, 1, 0, tb->Gx, n, 1, 0, zl, n, 1, 0), 1, st));
-    // z += W v + b
-    LS_TRY(gemm(gp(kW, (int)P, kW, par(f, lb(l, 2)), kW, 1, 0, vin, P, 1, kW * P, zl, P, 1, kW * P, 1.f, 1.f,
-                   par(f, lb(l, 3))), S, st));
-    if (l < kL - 1) {
-      float* vn = keep ? f->v[l + 1] : f->v[(l + 1) % 2];
-      const size_t cnt = (size_t)S * kW * P;
-      k_gelu<<<grid_for(cnt), 256, 0, st>>>(zl, vn, cnt);
-      LS_HIP(hipGetLastError());
-      vin = vn;
-    }
+    // z = U Gx + W v + b and the next input GELU(z) in one pass; z itself is
+    // kept for backward and as the last layer's output
+    const bool last = l == kL - 1;
+    float* vn = last ? nullptr : (keep ? f->v[l + 1] : f->v[(l + 1) % 2]);
+    k_layer_out<<<dim3((n + kLBN - 1) / kLBN, n, S), 256, 0, st>>>(f->U, tb->Gx, par(f, lb(l, 2)), par(f, lb(l, 3)),
+                                                                   vin, (keep || last) ? zl : nullptr, vn, n);
+    LS_HIP(hipGetLastError());
+    if (!last) vin = vn;
   }
   const float* v4 = zl;
-  LS_TRY(gemm(gp(kH, (int)P, kW, par(f, P_PROJ1_W), kW, 1, 0, v4, P, 1, kW * P, f->hpre, P, 1, kH * P, 1.f, 0.f,
-                 par(f, P_PROJ1_B)), S, st));
-  const size_t hc = (size_t)S * kH * P;
-  k_gelu<<<grid_for(hc), 256, 0, st>>>(f->hpre, f->hid, hc);
-  LS_HIP(hipGetLastError());
+  {  // hidden layer: hpre = P1 v4 + b1 (kept for backward), hid = GELU(hpre) in the same pass
+    GemmP q = gp(kH, (int)P, kW, par(f, P_PROJ1_W), kW, 1, 0, v4, P, 1, kW * P, keep ? f->hpre : nullptr, P, 1,
+                 kH * P, 1.f, 0.f, par(f, P_PROJ1_B));
+    q.C2 = f->hid;
+    LS_TRY(gemm(q, S, st));
+  }
   LS_TRY(gemm(gp(kOut, (int)P, kH, par(f, P_PROJ2_W), kH, 1, 0, f->hid, P, 1, kH * P, y, P, 1, kOut * P, 1.f, 0.f,
                  par(f, P_PROJ2_B)), S, st));
   if (keep) {
