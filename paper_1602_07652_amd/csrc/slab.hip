@@ -617,7 +617,11 @@ constexpr int kMB = 32;
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr int mq4(int q) { return (q + 3) & ~3; }
-inline size_t bstep_mfma_lds(int q) { return (size_t)2 * 3 * mq4(q) * (kMB + 1) * sizeof(float); }
+// panels staged per mode: 3 (backward), 2 (forward) or 1
+template <int MODE>
+__host__ __device__ constexpr int bstep_panels() { return MODE == BSTEP_BWD ? 3 : (MODE == BSTEP_FWD ? 2 : 1); }
+template <int MODE>
+inline size_t bstep_mfma_lds(int q) { return (size_t)2 * bstep_panels<MODE>() * mq4(q) * (kMB + 1) * sizeof(float); }
 
 template <int MODE>
 __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_t xs_b, int B,
@@ -627,8 +631,8 @@ __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_
   constexpr int U = 8, LB = kMB + 1;  // K steps in flight; padded panel row
   extern __shared__ unsigned char lds_raw[];
   const int q4 = mq4(q);
-  float* xr = reinterpret_cast<float*>(lds_raw);  // [3][q4][LB]
-  float* xi = xr + 3 * q4 * LB;
+  float* xr = reinterpret_cast<float*>(lds_raw);  // [panels][q4][LB]
+  float* xi = xr + bstep_panels<MODE>() * q4 * LB;
   const int lid = bstep_remap(blockIdx.x, total);
   const int blk = lid / tiles;
   const int b0 = (lid % tiles) * kMB;
@@ -857,10 +861,10 @@ static void bstep(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C* a1
     const int tiles = (B + kMB - 1) / kMB;
     // (block, tile) pairs >= 256 measured best against 64 and 128 thresholds
     if (B >= 16 && (long)nb * tiles >= 256) {
-      static const hipError_t once = set_lds(k_bstep_mfma<MODE>, bstep_mfma_lds(kMaxQ));
+      static const hipError_t once = set_lds(k_bstep_mfma<MODE>, bstep_mfma_lds<MODE>(kMaxQ));
       (void)once;
       const int total = nb * tiles;
-      k_bstep_mfma<MODE><<<total, 64 * ((q + 15) / 16), bstep_mfma_lds(q), p->stream>>>(
+      k_bstep_mfma<MODE><<<total, 64 * ((q + 15) / 16), bstep_mfma_lds<MODE>(q), p->stream>>>(
           x, xs_b, B, a0, a1, a2, coef, p->n, q, nl, shift, tiles, total);
       return;
     }
