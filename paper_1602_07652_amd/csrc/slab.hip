@@ -739,20 +739,34 @@ __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_
 
 template <typename C>
 __global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restrict__ coef, int n,
-                              int q) {
+                              int q, int B, int RB) {
+  // x_k -= L_k x_{k-1} + U_k x_{k+1} for the even blocks k of level 0, RB
+  // right-hand sides per thread: the stencil coefficients are loaded once
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 2 * blockIdx.y;
   if (r >= q) return;
-  C* xb = x + (size_t)blockIdx.z * xs_b;
+  const int b0 = blockIdx.z * RB, b1 = min(B, b0 + RB);
   const C* cf = coef + ((size_t)k * q + r) * 9;
-  C acc = xb[(size_t)k * q + r];
-  for (int dZ = -1; dZ <= 1; ++dZ) {
-    const int rr = r + dZ;
-    if (rr < 0 || rr >= q) continue;
-    if (k >= 1) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 0], xb[(size_t)(k - 1) * q + rr]));
-    if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr]));
+  C cl[3], cu[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int rr = r + d - 1;
+    const bool in = rr >= 0 && rr < q;
+    cl[d] = (in && k >= 1) ? cf[d * 3 + 0] : tmk<C>(0, 0);
+    cu[d] = (in && k + 1 < n) ? cf[d * 3 + 2] : tmk<C>(0, 0);
   }
-  xb[(size_t)k * q + r] = acc;
+  for (int b = b0; b < b1; ++b) {
+    C* xb = x + (size_t)b * xs_b;
+    C acc = xb[(size_t)k * q + r];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int rr = r + d - 1;
+      if (rr < 0 || rr >= q) continue;
+      if (k >= 1) acc = tsub(acc, tmul(cl[d], xb[(size_t)(k - 1) * q + rr]));
+      if (k + 1 < n) acc = tsub(acc, tmul(cu[d], xb[(size_t)(k + 1) * q + rr]));
+    }
+    xb[(size_t)k * q + r] = acc;
+  }
 }
 
 // ------------------------------------------------------- sweep helpers
@@ -1282,7 +1296,9 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
   const SlabLevel& L0 = s.levels[0];
   bstep<C, BSTEP_ODD0>(p, x, xs_b, B, fac + L0.off_dinv, nullptr, nullptr, coef, q, L0.nl, 0,
                        L0.nl / 2);
-  k_fwd0_even_b<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, B), 128, 0, p->stream>>>(x, xs_b, coef, n, q);
+  constexpr int RB = 8;  // right-hand sides per thread
+  k_fwd0_even_b<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, (B + RB - 1) / RB), 128, 0, p->stream>>>(
+      x, xs_b, coef, n, q, B, RB);
   for (int l = 1; l < nlev - 1; ++l) {
     const SlabLevel& L = s.levels[l];
     bstep<C, BSTEP_FWD>(p, x, xs_b, B, fac + L.off_pm, fac + L.off_pp, nullptr, coef, q, L.nl, l,
