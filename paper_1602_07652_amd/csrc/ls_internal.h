@@ -119,6 +119,7 @@ struct Slab {
   int top_n;
   cplx* top;
   fcplx* top32;
+  fcplx* top32T;  // FP32 plans with max_batch >= 16: column-major copy [top_n][top_n]
 };
 
 // Contiguous set of grid vectors used as a Krylov basis.
@@ -192,6 +193,7 @@ struct ls_plan {
   fcplx* slab_work32 = nullptr;  // FP32 plans: the two slab scratch vectors
   fcplx* slab_work32b = nullptr;
   fcplx* slab_elim32 = nullptr;
+  fcplx* top_part32 = nullptr;   // batched top operator: per-slice partial products
   fcplx* vtmp32 = nullptr;       // FP32 plans: grid vectors [3][n*n]
 
   // Krylov workspace (grid vectors), grown on demand

@@ -398,6 +398,7 @@ __global__ void k_odd0_lu(const C* __restrict__ y, C* __restrict__ t, const C* _
 constexpr int kTopBlocks = 16;
 constexpr int kTopK = 24;                 // ceil(kTopBlocks * kMaxQ / 64)
 constexpr int kTopMax = kTopBlocks * kMaxQ;
+constexpr int kTopBatchMin = 16;  // right-hand sides from which batched solves use the top operator
 
 template <typename C>
 __global__ __launch_bounds__(256) void k_top(const C* __restrict__ top, const C* __restrict__ t,
@@ -737,6 +738,93 @@ __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_
     }
 }
 
+// The top operator for many right-hand sides (FP32, matrix cores):
+// Y = Top X on the Nt unknowns of the top level, X and Y in place at the
+// level's rows (j << shift) of every right-hand side.  Top is read column-
+// major (topT[k][o]) so that the 16 rows one K step feeds are one 128-byte
+// segment.  A workgroup of 4 waves takes 64 rows (16 per wave) x 32
+// right-hand sides x one K slice of kTopKL; the panel of X is staged in LDS
+// once for the 4 waves.  The slices' partial products go to
+// part[slice][b][o] and k_top_reduce adds them in slice order
+// (deterministic).
+constexpr int kTopKL = 128;  // K per slice
+constexpr int kTopKC = 64;   // K rows staged in LDS at a time
+constexpr int kTopSlices = (kTopMax + kTopKL - 1) / kTopKL;
+
+__global__ __launch_bounds__(256) void k_top_mfma(const fcplx* __restrict__ topT, const fcplx* __restrict__ x,
+                                                  size_t xs_b, int B, int Nt, int q, int shift,
+                                                  fcplx* __restrict__ part) {
+  constexpr int LB = kMB + 1;
+  __shared__ float xr[kTopKC * LB], xi[kTopKC * LB];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int o0 = blockIdx.x * 64 + 16 * w, b0 = blockIdx.y * kMB, sl = blockIdx.z;
+  const int kb = sl * kTopKL, ke = min(Nt, kb + kTopKL);
+  const int nbt = min(kMB, B - b0);
+  const int ra = o0 + (l & 15), kk = l >> 4;
+  f32x4_t dre0 = {0, 0, 0, 0}, dim0 = {0, 0, 0, 0}, dre1 = {0, 0, 0, 0}, dim1 = {0, 0, 0, 0};
+  for (int c0 = kb; c0 < ke; c0 += kTopKC) {
+    const int cn = min(kTopKC, ke - c0);
+    // this chunk's factor elements first: all 16 K steps in flight
+    fcplx a[kTopKC / 4];
+#pragma unroll
+    for (int u = 0; u < kTopKC / 4; ++u) {
+      const int kr = 4 * u + kk;
+      a[u] = (kr < cn && ra < Nt) ? topT[(size_t)(c0 + kr) * Nt + ra] : tmk<fcplx>(0, 0);
+    }
+    __syncthreads();  // the previous chunk's panel is consumed
+    {
+      const int kr = tid & (kTopKC - 1), bq = tid / kTopKC;  // row kr, right-hand sides 8 bq .. 8 bq + 7
+      const bool kin = kr < cn;
+      const int k = c0 + kr, j = kin ? k / q : 0;
+      const size_t off = ((size_t)j << shift) * q + (kin ? k - j * q : 0);
+#pragma unroll
+      for (int e = 0; e < kMB / 4; ++e) {
+        const int bb = bq * (kMB / 4) + e;
+        const fcplx v = (kin && bb < nbt) ? x[(size_t)(b0 + bb) * xs_b + off] : tmk<fcplx>(0, 0);
+        xr[kr * LB + bb] = v.x;
+        xi[kr * LB + bb] = v.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kTopKC / 4; ++u) {
+      if (4 * u >= cn) break;
+      const int o = (4 * u + kk) * LB + (l & 15);
+      const float br0 = xr[o], bi0 = xi[o], br1 = xr[o + 16], bi1 = xi[o + 16];
+      const float ar = a[u].x, ai = a[u].y;
+      dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br0, dre0, 0, 0, 0);
+      dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi0, dre0, 0, 0, 0);
+      dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi0, dim0, 0, 0, 0);
+      dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br0, dim0, 0, 0, 0);
+      dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br1, dre1, 0, 0, 0);
+      dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi1, dre1, 0, 0, 0);
+      dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi1, dim1, 0, 0, 0);
+      dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br1, dim1, 0, 0, 0);
+    }
+  }
+  // D layout: lane l holds rows 4 (l / 16) + i of column l % 16
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = o0 + 4 * (l >> 4) + i, bb = 16 * ct + (l & 15);
+      if (o >= Nt || bb >= nbt) continue;
+      part[((size_t)sl * B + b0 + bb) * Nt + o] = tmk<fcplx>(ct ? dre1[i] : dre0[i], ct ? dim1[i] : dim0[i]);
+    }
+}
+
+// x_b at the top level's rows = sum over slices of part[slice][b][o]
+__global__ void k_top_reduce(const fcplx* __restrict__ part, int slices, int Nt, int B, fcplx* __restrict__ x,
+                             size_t xs_b, int q, int shift) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)Nt * B) return;
+  const int b = (int)(e / Nt), o = (int)(e % Nt);
+  fcplx sum = tmk<fcplx>(0, 0);
+  for (int sl = 0; sl < slices; ++sl) sum = tadd(sum, part[((size_t)sl * B + b) * Nt + o]);
+  const int j = o / q;
+  x[(size_t)b * xs_b + ((size_t)j << shift) * q + (o - j * q)] = sum;
+}
+
 template <typename C>
 __global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restrict__ coef, int n,
                               int q, int B, int RB) {
@@ -935,6 +1023,13 @@ static ls_status build_top(ls_plan* p, Slab& s, const cplx* fac, cplx* work, siz
   if (p->fp32) {
     LS_TRY(plan_alloc(p, (void**)&s.top32, bytes * sizeof(fcplx)));
     k_transpose_to<fcplx><<<blocks, 256, 0, p->stream>>>(work, s.top32, Nt);
+    if (p->opt.max_batch >= kTopBatchMin) {  // column-major copy for many right-hand sides
+      LS_TRY(plan_alloc(p, (void**)&s.top32T, bytes * sizeof(fcplx)));
+      k_down_copy<<<(unsigned)((bytes + 255) / 256), 256, 0, p->stream>>>(work, s.top32T, bytes);
+      if (!p->top_part32)
+        LS_TRY(plan_alloc(p, (void**)&p->top_part32,
+                          (size_t)kTopSlices * kTopMax * p->opt.max_batch * sizeof(fcplx)));
+    }
   } else {
     LS_TRY(plan_alloc(p, (void**)&s.top, bytes * sizeof(cplx)));
     k_transpose_to<cplx><<<blocks, 256, 0, p->stream>>>(work, s.top, Nt);
@@ -1294,19 +1389,38 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
+  // levels from the top level up as one dense operator (FP32, many right-hand sides)
+  int top_l = nlev - 1;
+  const fcplx* topT = nullptr;
+  if constexpr (std::is_same<C, fcplx>::value) {
+    if (B >= kTopBatchMin && s.top_level >= 1 && s.top32T && p->top_part32) {
+      top_l = s.top_level;
+      topT = s.top32T;
+    }
+  }
   bstep<C, BSTEP_ODD0>(p, x, xs_b, B, fac + L0.off_dinv, nullptr, nullptr, coef, q, L0.nl, 0,
                        L0.nl / 2);
   constexpr int RB = 8;  // right-hand sides per thread
   k_fwd0_even_b<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, (B + RB - 1) / RB), 128, 0, p->stream>>>(
       x, xs_b, coef, n, q, B, RB);
-  for (int l = 1; l < nlev - 1; ++l) {
+  for (int l = 1; l < top_l; ++l) {
     const SlabLevel& L = s.levels[l];
     bstep<C, BSTEP_FWD>(p, x, xs_b, B, fac + L.off_pm, fac + L.off_pp, nullptr, coef, q, L.nl, l,
                         (L.nl + 1) / 2);
   }
-  bstep<C, BSTEP_LAST>(p, x, xs_b, B, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, coef,
-                       q, 1, 0, 1);
-  for (int l = nlev - 2; l >= 1; --l) {
+  if constexpr (std::is_same<C, fcplx>::value) {
+    if (topT) {
+      const int Nt = s.top_n, slices = (Nt + kTopKL - 1) / kTopKL;
+      k_top_mfma<<<dim3((Nt + 63) / 64, (B + kMB - 1) / kMB, slices), 256, 0, p->stream>>>(
+          topT, x, xs_b, B, Nt, q, top_l, p->top_part32);
+      k_top_reduce<<<(unsigned)(((size_t)Nt * B + 255) / 256), 256, 0, p->stream>>>(p->top_part32, slices, Nt, B,
+                                                                                     x, xs_b, q, top_l);
+    }
+  }
+  if (top_l == nlev - 1)
+    bstep<C, BSTEP_LAST>(p, x, xs_b, B, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, coef,
+                         q, 1, 0, 1);
+  for (int l = top_l - 1; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
     bstep<C, BSTEP_BWD>(p, x, xs_b, B, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu,
                         coef, q, L.nl, l, L.nl / 2);
