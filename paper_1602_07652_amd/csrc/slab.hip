@@ -858,10 +858,54 @@ __global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restric
 }
 
 // ------------------------------------------------------- sweep helpers
-// dst[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere.
+// Trace sources on two lines of one slab (eq. pde_GRF_real): the term
+// sgn * sum_dX coef[i][rt][(dZ+1)*3 + dX+1] * src(i+dX) added to rhs[i][rt],
+// src(i) = s[i*qs + rs] (+ s2[i*q2 + r2] when s2 is set).
+struct Inject {
+  int rt, dZ;
+  double sgn;
+  int qs, rs;
+};
+
+template <typename T>
+__device__ __forceinline__ T inject_term(const T* __restrict__ coef, int n, int q, int i, const Inject& J,
+                                         const T* __restrict__ src, const T* __restrict__ s2, int q2, int r2) {
+  const T* cf = coef + ((size_t)i * q + J.rt) * 9 + (J.dZ + 1) * 3;
+  T acc = tmk<T>(0, 0);
+  for (int dX = -1; dX <= 1; ++dX) {
+    const int ii = i + dX;
+    if (ii < 0 || ii >= n) continue;
+    T sv = src[(size_t)ii * J.qs + J.rs];
+    if (s2) sv = tadd(sv, s2[(size_t)ii * q2 + r2]);
+    acc = tfma(cf[dX + 1], sv, acc);
+  }
+  return tmk<T>(acc.x * J.sgn, acc.y * J.sgn);
+}
+
+// The two trace sources alone: rhs[i][A.rt] and rhs[i][B.rt] of a layer
+// (row stride qr) from src (row stride qs, batch stride n qs) and s2 on
+// line B (many right-hand sides run this as its own launch).
+template <typename T>
+__global__ void k_inject(T* __restrict__ rhs, int qr, const T* __restrict__ coef, int n, Inject A, Inject Bj,
+                         const T* __restrict__ src, int qs, const T* __restrict__ s2, int q2, int r2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T* rb = rhs + (size_t)blockIdx.y * n * qr;
+  const T* sb = src + (size_t)blockIdx.y * n * qs;
+  const T* s2b = s2 ? s2 + (size_t)blockIdx.y * n * q2 : nullptr;
+  T* o = rb + (size_t)i * qr + A.rt;
+  *o = tadd(*o, inject_term(coef, n, qr, i, A, sb, (const T*)nullptr, 0, 0));
+  o = rb + (size_t)i * qr + Bj.rt;
+  *o = tadd(*o, inject_term(coef, n, qr, i, Bj, sb, s2b, q2, r2));
+}
+
+// dst[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere; with
+// sA set, the downward sweep's two trace sources from sA (the solution of
+// the layer above) are added on lines A.rt and B.rt.
 template <typename T>
 __global__ void k_gather(const T* __restrict__ g, T* __restrict__ dst, int n, int q, int z0,
-                         int a, int b, int orient) {
+                         int a, int b, int orient, const T* __restrict__ coef, Inject A, Inject Bj,
+                         const T* __restrict__ sA) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * q) return;
   g += (size_t)blockIdx.y * n * n;
@@ -871,63 +915,42 @@ __global__ void k_gather(const T* __restrict__ g, T* __restrict__ dst, int n, in
   const int Z = z0 + r;
   T v = tmk<T>(0, 0);
   if (Z >= a && Z <= b) v = (orient == 0) ? g[(size_t)Z * n + i] : g[(size_t)i * n + Z];
+  if (sA) {
+    const T* s = sA + (size_t)blockIdx.y * n * A.qs;
+    if (r == A.rt) v = tadd(v, inject_term(coef, n, q, i, A, s, (const T*)nullptr, 0, 0));
+    if (r == Bj.rt) v = tadd(v, inject_term(coef, n, q, i, Bj, s, (const T*)nullptr, 0, 0));
+  }
   dst[(size_t)i * q + r] = v;
 }
 
-// out(i, Z) (+)= src[i][Z - z0] for Z in [a, b].
+// out(i, Z) (+)= src[i][Z - z0] for Z in [a, b] (the solution of one layer
+// into the grid), and, with rhs set, the upward sweep's two trace sources
+// of the next layer added to its right-hand side rhs (lines A.rt, B.rt;
+// sources sA = the scattered solution, plus s2 on line B).
 template <typename T>
 __global__ void k_scatter(const T* __restrict__ src, T* __restrict__ out, int n, int q, int z0,
-                          int a, int b, int orient, int accumulate) {
+                          int a, int b, int orient, int accumulate, T* __restrict__ rhs, int qr,
+                          const T* __restrict__ coef, Inject A, Inject Bj, const T* __restrict__ s2, int q2,
+                          int r2) {
   const int rows = b - a + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * rows) return;
-  src += (size_t)blockIdx.y * n * q;
-  out += (size_t)blockIdx.y * n * n;
-  int i, Z;
-  if (orient == 0) { Z = a + t / n; i = t % n; } else { i = t / rows; Z = a + t % rows; }
-  const T v = src[(size_t)i * q + (Z - z0)];
-  const size_t o = (orient == 0) ? (size_t)Z * n + i : (size_t)i * n + Z;
-  out[o] = accumulate ? tadd(out[o], v) : v;
-}
-
-// GRF sources on two lines of one slab (eq. pde_GRF_real):
-// rhs[i][rt_j] += sgn_j * sum_dX coef[i][rt_j][(dZ_j+1)*3 + dX+1] * src_j(i+dX),
-// src_j(i) = s1_j[i*q1_j + r1_j] (+ s2[i*q2 + r2] for the second line).
-template <typename T>
-__global__ void k_inject2(T* __restrict__ rhs, const T* __restrict__ coef, int n, int q,
-                          int rtA, int dZA, double sgnA, const T* __restrict__ sA, int qA, int rA,
-                          int rtB, int dZB, double sgnB, const T* __restrict__ sB, int qB, int rB,
-                          const T* __restrict__ s2, int q2, int r2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  // right-hand side blockIdx.y: every slab array has stride n * (its q)
-  rhs += (size_t)blockIdx.y * n * q;
-  sA += (size_t)blockIdx.y * n * qA;
-  sB += (size_t)blockIdx.y * n * qB;
-  if (s2) s2 += (size_t)blockIdx.y * n * q2;
-  {
-    const T* cf = coef + ((size_t)i * q + rtA) * 9 + (dZA + 1) * 3;
-    T acc = tmk<T>(0, 0);
-    for (int dX = -1; dX <= 1; ++dX) {
-      const int ii = i + dX;
-      if (ii < 0 || ii >= n) continue;
-      acc = tfma(cf[dX + 1], sA[(size_t)ii * qA + rA], acc);
-    }
-    T* o = rhs + (size_t)i * q + rtA;
-    *o = tadd(*o, tmk<T>(acc.x * sgnA, acc.y * sgnA));
+  if (t < n * rows) {
+    const T* sb = src + (size_t)blockIdx.y * n * q;
+    T* ob = out + (size_t)blockIdx.y * n * n;
+    int i, Z;
+    if (orient == 0) { Z = a + t / n; i = t % n; } else { i = t / rows; Z = a + t % rows; }
+    const T v = sb[(size_t)i * q + (Z - z0)];
+    const size_t o = (orient == 0) ? (size_t)Z * n + i : (size_t)i * n + Z;
+    ob[o] = accumulate ? tadd(ob[o], v) : v;
   }
-  {
-    const T* cf = coef + ((size_t)i * q + rtB) * 9 + (dZB + 1) * 3;
-    T acc = tmk<T>(0, 0);
-    for (int dX = -1; dX <= 1; ++dX) {
-      const int ii = i + dX;
-      if (ii < 0 || ii >= n) continue;
-      T sv = sB[(size_t)ii * qB + rB];
-      if (s2) sv = tadd(sv, s2[(size_t)ii * q2 + r2]);
-      acc = tfma(cf[dX + 1], sv, acc);
-    }
-    T* o = rhs + (size_t)i * q + rtB;
-    *o = tadd(*o, tmk<T>(acc.x * sgnB, acc.y * sgnB));
+  if (rhs && t < n) {
+    T* rb = rhs + (size_t)blockIdx.y * n * qr;
+    const T* sa = src + (size_t)blockIdx.y * n * q;
+    const T* s2b = s2 + (size_t)blockIdx.y * n * q2;
+    T* o = rb + (size_t)t * qr + A.rt;
+    *o = tadd(*o, inject_term(coef, n, qr, t, A, sa, (const T*)nullptr, 0, 0));
+    o = rb + (size_t)t * qr + Bj.rt;
+    *o = tadd(*o, inject_term(coef, n, qr, t, Bj, sa, s2b, q2, r2));
   }
 }
 
@@ -1516,20 +1539,59 @@ static ls_status solve_t(ls_plan* p, Slab& s, const T* g, T* y, int B) {
 ls_status slab_solve(ls_plan* p, Slab& s, const cplx* g, cplx* y, int B) { return solve_t<cplx>(p, s, g, y, B); }
 ls_status slab_solve(ls_plan* p, Slab& s, const fcplx* g, fcplx* y, int B) { return solve_t<fcplx>(p, s, g, y, B); }
 
+// g^l gathered from g; with `up` set, plus the downward sweep's trace
+// sources from the solution w of the layer above:
+//   g^l += -delta_b C^l_{b,b+1} w^{l+1}(b+1) + delta_{b+1} C^l_{b+1,b} w^{l+1}(b)
 template <typename T>
-static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B) {
+static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B, Slab* up) {
   const int n = p->n, tot = n * s.q;
-  k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b,
-                                                                  s.orient);
+  Inject A{}, Bj{};
+  const T* sA = nullptr;
+  if (up) {
+    A = Inject{s.b - s.z0, +1, -1.0, up->q, s.b + 1 - up->z0};
+    Bj = Inject{s.b + 1 - s.z0, -1, +1.0, up->q, s.b - up->z0};
+    sA = SB<T>::w(*up);
+  }
+  // one right-hand side: the sources in the gather launch; many: a launch of their own
+  const bool fuse = B == 1;
+  k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b, s.orient,
+                                                                  SB<T>::coef(s), A, Bj, fuse ? sA : nullptr);
+  if (sA && !fuse)
+    k_inject<T><<<dim3((n + 255) / 256, B), 256, 0, p->stream>>>(dst, s.q, SB<T>::coef(s), n, A, Bj, sA, up->q,
+                                                                  (const T*)nullptr, 0, 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
+// The layer rows of src (solution of layer s) into out; with `next` set,
+// plus the upward sweep's trace sources for the next layer's right-hand
+// side (v0 = src(a'-1), v1 = src(a') + w^{l'}(a') with a' the next layer's
+// first line):
+//   g^{l'} += -delta_a C_{a,a-1} v0 + delta_{a-1} C_{a-1,a} v1
 template <typename T>
-static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool acc, int B) {
-  const int n = p->n, tot = n * (s.b - s.a + 1);
-  k_scatter<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(src, out, n, s.q, s.z0, s.a, s.b,
-                                                                   s.orient, acc ? 1 : 0);
+static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool acc, int B, Slab* next) {
+  const bool fuse = B == 1;  // one right-hand side: the sources in the scatter launch
+  const int n = p->n, tot = std::max(n * (s.b - s.a + 1), (next && fuse) ? n : 0);
+  Inject A{}, Bj{};
+  T* rhs = nullptr;
+  const T* s2 = nullptr;
+  int qr = 0, q2 = 0, r2 = 0;
+  if (next) {
+    Slab& nx = *next;
+    A = Inject{nx.a - nx.z0, -1, -1.0, s.q, nx.a - 1 - s.z0};
+    Bj = Inject{nx.a - 1 - nx.z0, +1, +1.0, s.q, nx.a - s.z0};
+    rhs = SB<T>::g(nx);
+    qr = nx.q;
+    s2 = SB<T>::w(nx);
+    q2 = nx.q;
+    r2 = nx.a - nx.z0;
+  }
+  k_scatter<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(
+      src, out, n, s.q, s.z0, s.a, s.b, s.orient, acc ? 1 : 0, fuse ? rhs : nullptr, qr,
+      next ? SB<T>::coef(*next) : nullptr, A, Bj, s2, q2, r2);
+  if (next && !fuse)
+    k_inject<T><<<dim3((n + 255) / 256, B), 256, 0, p->stream>>>(rhs, qr, SB<T>::coef(*next), n, A, Bj, src, s.q,
+                                                                  s2, q2, r2);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -1541,25 +1603,15 @@ template <typename T>
 static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumulate, int B) {
   std::vector<Slab>& S = p->slabs[orient];
   const int L = (int)S.size();
-  const int n = p->n;
-  const dim3 grid((n + 255) / 256, B);
-  // downward sweep: l = L-1 .. 0
+  // downward sweep: l = L-1 .. 0 (gather with the trace sources of w^{l+1})
   for (int l = L - 1; l >= 0; --l) {
     Slab& s = S[l];
-    LS_TRY(gather<T>(p, s, g, SB<T>::g(s), B));
-    if (l != L - 1) {
-      Slab& up = S[l + 1];
-      // g^l += -delta_b C^l_{b,b+1} w^{l+1}(b+1) + delta_{b+1} C^l_{b+1,b} w^{l+1}(b)
-      k_inject2<T><<<grid, 256, 0, p->stream>>>(
-          SB<T>::g(s), SB<T>::coef(s), n, s.q,
-          s.b - s.z0, +1, -1.0, SB<T>::w(up), up.q, s.b + 1 - up.z0,
-          s.b + 1 - s.z0, -1, +1.0, SB<T>::w(up), up.q, s.b - up.z0, nullptr, 0, 0);
-      LS_HIP(hipGetLastError());
-    }
+    LS_TRY(gather<T>(p, s, g, SB<T>::g(s), B, l != L - 1 ? &S[l + 1] : nullptr));
     LS_TRY(solve_t<T>(p, s, SB<T>::g(s), SB<T>::w(s), B));
   }
-  // upward sweep: l = 0 .. L-1
-  const T* vprev = nullptr;
+  // upward sweep: l = 0 .. L-1; scattering v^{l-1} also adds its trace
+  // sources to g^l
+  T* vprev = nullptr;
   for (int l = 0; l < L; ++l) {
     Slab& s = S[l];
     T* vcur;
@@ -1567,17 +1619,10 @@ static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumula
       vcur = SB<T>::w(s);  // g^0 is unchanged: v^0 = w^0
     } else {
       vcur = SB<T>::work(p, vprev == SB<T>::work(p, 0) ? 1 : 0);
-      const Slab& dn = S[l - 1];
-      // g^l += -delta_a C^l_{a,a-1} v0 + delta_{a-1} C^l_{a-1,a} v1 with
-      // v0 = v^{l-1}(a-1), v1 = v^{l-1}(a) + w^l(a)
-      k_inject2<T><<<grid, 256, 0, p->stream>>>(
-          SB<T>::g(s), SB<T>::coef(s), n, s.q,
-          s.a - s.z0, -1, -1.0, vprev, dn.q, s.a - 1 - dn.z0,
-          s.a - 1 - s.z0, +1, +1.0, vprev, dn.q, s.a - dn.z0, SB<T>::w(s), s.q, s.a - s.z0);
-      LS_HIP(hipGetLastError());
+      LS_TRY(scatter<T>(p, S[l - 1], vprev, v, accumulate, B, &s));
       LS_TRY(solve_t<T>(p, s, SB<T>::g(s), vcur, B));
     }
-    LS_TRY(scatter<T>(p, s, vcur, v, accumulate, B));
+    if (l == L - 1) LS_TRY(scatter<T>(p, s, vcur, v, accumulate, B, nullptr));
     vprev = vcur;
   }
   return LS_OK;
