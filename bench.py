@@ -206,13 +206,34 @@ def learned_variant(tol, log_fn, weights):
         }
         log_fn(f"learned-form job, {arm}: {total} solves in {wall:.3f} s = {total / wall:.1f} solves/s; "
                f"{arms[arm]['per_grid']}")
+    # the training size alone (64 waves at 256^2): where the network is in distribution
+    p0, n0 = plans[0], nets[0]
+    small = {}
+    for arm in ("plain", "learned"):
+        run = (lambda: p0.solve(fs[0], tol=tol, out=us[0])) if arm == "plain" else \
+              (lambda: p0.solve_fno(n0, uIs[0], fs[0], tol=tol, mode=LS_FNO_WARM | LS_FNO_PROBE, out=us[0]))
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        small[arm] = {"wall_s": wall, "solves_per_s": B / wall,
+                      "outer_its_mean": float(np.mean([i["outer_its"] for i in inf])),
+                      "relres_true_max": max(i["relres_true"] for i in inf),
+                      "converged": all(i["converged"] for i in inf)}
+        log_fn(f"learned-form job at 256^2 only, {arm}: {B} solves in {wall:.3f} s = {B / wall:.1f} solves/s; "
+               f"{small[arm]}")
     for x in plans + nets:
         x.close()
     return {"workload": "64 plane waves x {256^2, 512^2, 1024^2} GRF media (held-out seeds 5000-5002), "
                         "FP32+FP64 refinement, one stream per grid",
             "solves": total, "weights_val_loss": meta["history"][-1]["val"],
             "plain": arms["plain"], "learned": arms["learned"],
-            "speedup": arms["plain"]["wall_s"] / arms["learned"]["wall_s"]}
+            "speedup": arms["plain"]["wall_s"] / arms["learned"]["wall_s"],
+            "training_size_only": {"workload": "64 plane waves, 256^2 GRF medium seed 5000, FP32+FP64 refinement",
+                                   "plain": small["plain"], "learned": small["learned"],
+                                   "speedup": small["plain"]["wall_s"] / small["learned"]["wall_s"]}}
 
 
 def fno_flops(n, S):
