@@ -1175,11 +1175,28 @@ ls_status spectrum_extract(ls_plan* p, const cplx* c) {
 }
 
 template <typename T, typename R>
-ls_status apply_H_t(const ApplyView<T, R>& av, int logP, const T* v, T* y, int batch, double a,
-                    double b) {
+ls_status apply_H_one(const ApplyView<T, R>& av, int logP, const T* v, T* y, int batch, double a, double b) {
 #define CALL_APPLY(L) run_apply<T, R, L>(av, v, y, batch, a, b)
   LS_DISPATCH_LOGP(logP, CALL_APPLY)
 #undef CALL_APPLY
+}
+
+// The batch runs in chunks whose n x P intermediate is at most 96 MB: it is
+// written by the row pass and read back by the column and inverse row passes
+// while still in the 256 MB Infinity Cache (measured at 1024^2, batch 8,
+// FP64: 0.486 ms in one piece, 0.444 ms in chunks of 3; 64 and 128 MB caps
+// 0.452 / 0.453 ms).
+constexpr size_t kApplyChunkBytes = (size_t)96 << 20;
+
+template <typename T, typename R>
+ls_status apply_H_t(const ApplyView<T, R>& av, int logP, const T* v, T* y, int batch, double a,
+                    double b) {
+  const size_t inter = (size_t)av.n * ((size_t)1 << logP) * sizeof(T);
+  const int chunk = std::max(1, (int)(kApplyChunkBytes / inter));
+  const size_t N = (size_t)av.n * av.n;
+  for (int b0 = 0; b0 < batch; b0 += chunk)
+    LS_TRY((apply_H_one<T, R>(av, logP, v + b0 * N, y + b0 * N, std::min(chunk, batch - b0), a, b)));
+  return LS_OK;
 }
 
 // y = a v + b (omega^2 G (m v)); a = 1, b = 1 gives H v; a = 0, b = -1 gives
