@@ -15,8 +15,9 @@ reused).  Prints one JSON line.  Also reports:
   * the FFT matvec (ls_apply) achieved HBM GB/s on a batch of 8;
   * cpu_baseline: one full solve of the same workload by the FP64 CPU
     oracle on the host cores (see cpu_baseline());
-  * variants: the batched FP32 multi-grid form (64 waves x 3 grids) and the
-    learned form next to its plain twin on held-out media.
+  * variants: the same workload in FP32 with FP64 refinement, the batched
+    FP32 multi-grid form (64 waves x 3 grids) and the learned form next to
+    its plain twin on held-out media.
 """
 from __future__ import annotations
 
@@ -460,6 +461,24 @@ def main():
     log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic")
 
     plan.close()
+    # the same workload with FP32 operator and slab solves and FP64 refinement
+    from paper_1602_07652_amd import LS_FP32_REFINE
+    t0 = time.perf_counter()
+    p32 = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, precision=LS_FP32_REFINE)
+    torch.cuda.synchronize()
+    setup32 = time.perf_counter() - t0
+    p32.solve(f, tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos32 = [p32.solve(f, tol=args.tol, out=u)[1][0] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t0
+    p32.close()
+    fp32_single = {"workload": "the plain workload with FP32 operator and slab solves, FP64 refinement",
+                   "solves_per_s": args.steps / el32, "ms_per_solve": 1e3 * el32 / args.steps,
+                   "outer_its": float(np.mean([i["outer_its"] for i in infos32])),
+                   "relres_true": max(i["relres_true"] for i in infos32), "setup_s": setup32}
+    log(f"FP32 + refinement, one right-hand side: {fp32_single}")
     batched = learned = None
     if not args.no_batched:
         batched = batched_variant(args.tol, log)
@@ -508,7 +527,8 @@ def main():
             "ms_per_launch": slab_ms,
         },
         "cpu_baseline": cpu,
-        "variants": {"batched_fp32_multigrid": batched, "learned_fp32_multigrid": learned},
+        "variants": {"fp32_refine_single": fp32_single, "batched_fp32_multigrid": batched,
+                     "learned_fp32_multigrid": learned},
     }
     print(json.dumps(rec), flush=True)
 
