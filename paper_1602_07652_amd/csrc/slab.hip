@@ -533,58 +533,90 @@ __global__ __launch_bounds__(NT) void k_bstep(C* __restrict__ x, size_t xs_b, in
   } else {  // ODD0, BWD0 (level 0)
     k = 2 * blk + 1; row[0] = k; M[0] = m0 + blk * qq; T = 1;
   }
-  // stage panels: element e -> (t, bb, c), c fastest (coalesced)
+  // Thread (r, g) = (tid % q, tid / q): row r of the factor columns g,
+  // g + G, ... (G = NT / q groups), and column r of the panel pairs
+  // (panel t, right-hand side bb) = slot g, g + G, ... when staging.
+  const int G = NT / q;
+  const int r = tid % q, g = tid / q;
+  const bool act = g < G;
   const int per_t = q * nbt;
-  for (int e = tid; e < T * per_t; e += NT) {
-    const int t = e / per_t, rem = e - t * per_t;
-    const int bb = rem / q, c = rem - bb * q;
-    const C* xb = x + (size_t)(b0 + bb) * xs_b;
-    C v;
-    if (MODE == BSTEP_BWD0) {  // L_k x_{k-1} + U_k x_{k+1} from the stencil coefficients
+  // factor chunk (t, c0): columns c0 + u G of M_t, U loads in flight; the
+  // first chunk's loads go out before the staging
+  C cur[U];
+  int ft = 0, fc = g;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int c = fc + u * G;
+    cur[u] = act && T > 0 && c < q ? M[0][(size_t)c * q + r] : tmk<C>(0, 0);
+  }
+  if (MODE == BSTEP_BWD0) {  // L_k x_{k-1} + U_k x_{k+1} from the stencil coefficients
+    for (int e = tid; e < per_t; e += NT) {
+      const int bb = e / q, c = e - bb * q;
+      const C* xb = x + (size_t)(b0 + bb) * xs_b;
       const C* cf = coef + ((size_t)k * q + c) * 9;
-      v = tmk<C>(0, 0);
+      C v = tmk<C>(0, 0);
       for (int dZ = -1; dZ <= 1; ++dZ) {
         const int rr = c + dZ;
         if (rr < 0 || rr >= q) continue;
         v = tfma(cf[(dZ + 1) * 3 + 0], xb[(size_t)(k - 1) * q + rr], v);
         if (k + 1 < n) v = tfma(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr], v);
       }
-    } else {
-      v = xb[(size_t)row[t] * q + c];
-      if (neg[t]) v = tneg(v);
+      xs[(size_t)c * XS + bb] = v;
     }
-    xs[((size_t)t * kMaxQ + c) * XS + bb] = v;
-  }
-  for (int e = tid; e < T * q * (BT - nbt); e += NT) {  // unused right-hand-side slots
-    const int tc = e / (BT - nbt);
-    xs[(size_t)((tc / q) * kMaxQ + tc % q) * XS + nbt + e % (BT - nbt)] = tmk<C>(0, 0);
+    for (int e = tid; e < q * (BT - nbt); e += NT)  // unused right-hand-side slots
+      xs[(size_t)(e / (BT - nbt)) * XS + nbt + e % (BT - nbt)] = tmk<C>(0, 0);
+  } else {
+    // pairs pr = t BT + bb (zero for bb >= nbt); at most EPT per thread since
+    // G >= NT / kMaxQ; every load issued before the stores
+    constexpr int EPT = (3 * BT + NT / kMaxQ - 1) / (NT / kMaxQ);
+    C sv[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int pr = g + i * G, t = pr / BT, bb = pr % BT;
+      sv[i] = tmk<C>(0, 0);
+      if (act && t < T && bb < nbt) {
+        const int rw = t == 0 ? row[0] : (t == 1 ? row[1] : row[2]);
+        sv[i] = x[(size_t)(b0 + bb) * xs_b + (size_t)rw * q + r];
+        if ((t == 0 ? neg[0] : (t == 1 ? neg[1] : neg[2]))) sv[i] = tneg(sv[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int pr = g + i * G, t = pr / BT, bb = pr % BT;
+      if (act && t < T) xs[((size_t)t * kMaxQ + r) * XS + bb] = sv[i];
+    }
   }
   __syncthreads();
-  const int G = NT / q;
-  const int r = tid % q, g = tid / q;
-  const bool act = g < G;
   C acc[BT];
 #pragma unroll
   for (int j = 0; j < BT; ++j) acc[j] = tmk<C>(0, 0);
   if (act) {
-    for (int t = 0; t < T; ++t) {
-      const C* Mt = M[t] + r;
-      const C* Xt = xs + (size_t)t * kMaxQ * XS;
-      for (int c0 = g; c0 < q; c0 += U * G) {
-        C mv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int c = c0 + u * G;
-          mv[u] = c < q ? Mt[(size_t)c * q] : tmk<C>(0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int c = min(c0 + u * G, q - 1);  // mv is zero past the end
-          const C* xr = Xt + (size_t)c * XS;
-#pragma unroll
-          for (int j = 0; j < BT; ++j) acc[j] = tfma(mv[u], xr[j], acc[j]);
-        }
+    while (ft < T) {
+      // the next chunk's loads go out before this chunk's products
+      int nt = ft, nc = fc + U * G;
+      if (nc >= q) {
+        nt = ft + 1;
+        nc = g;
       }
+      C nxt[U];
+      const C* Mn = nt == 1 ? M[1] : (nt == 2 ? M[2] : M[0]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = nc + u * G;
+        nxt[u] = nt < T && c < q ? Mn[(size_t)c * q + r] : tmk<C>(0, 0);
+      }
+      const C* Xt = xs + (size_t)ft * kMaxQ * XS;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = min(fc + u * G, q - 1);  // cur is zero past the end
+        const C* xr = Xt + (size_t)c * XS;
+#pragma unroll
+        for (int j = 0; j < BT; ++j) acc[j] = tfma(cur[u], xr[j], acc[j]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+      ft = nt;
+      fc = nc;
     }
   }
   __syncthreads();  // panels consumed; reuse LDS for the partial sums
@@ -594,15 +626,16 @@ __global__ __launch_bounds__(NT) void k_bstep(C* __restrict__ x, size_t xs_b, in
   }
   __syncthreads();
   const size_t okq = (size_t)(MODE == BSTEP_FWD || MODE == BSTEP_BWD ? (k << shift) : k) * q;
-  for (int e = tid; e < per_t; e += NT) {
-    const int bb = e / q, rr = e - bb * q;
-    C sum = tmk<C>(0, 0);
-    for (int gg = 0; gg < G; ++gg) sum = tadd(sum, xs[(size_t)(gg * q + rr) * XS + bb]);
-    C* o = x + (size_t)(b0 + bb) * xs_b + okq + rr;
-    if (MODE == BSTEP_FWD || MODE == BSTEP_BWD0)
-      *o = tsub(*o, sum);
-    else
-      *o = sum;
+  if (act) {
+    for (int bb = g; bb < nbt; bb += G) {
+      C sum = tmk<C>(0, 0);
+      for (int gg = 0; gg < G; ++gg) sum = tadd(sum, xs[(size_t)(gg * q + r) * XS + bb]);
+      C* o = x + (size_t)(b0 + bb) * xs_b + okq + r;
+      if (MODE == BSTEP_FWD || MODE == BSTEP_BWD0)
+        *o = tsub(*o, sum);
+      else
+        *o = sum;
+    }
   }
 }
 
@@ -623,6 +656,16 @@ template <int MODE>
 __host__ __device__ constexpr int bstep_panels() { return MODE == BSTEP_BWD ? 3 : (MODE == BSTEP_FWD ? 2 : 1); }
 template <int MODE>
 inline size_t bstep_mfma_lds(int q) { return (size_t)2 * bstep_panels<MODE>() * mq4(q) * (kMB + 1) * sizeof(float); }
+
+// Factor element of K step s for lane (row ra, column kk of the step):
+// panel t = s / KS, column 4 (s % KS) + kk of M_t; zero past the end.
+__device__ __forceinline__ fcplx bstep_fac(const fcplx* M0, const fcplx* M1, const fcplx* M2, int s, int S,
+                                           int KS, int kk, int q, bool rin, int ra) {
+  const int t = s >= 2 * KS ? 2 : (s >= KS ? 1 : 0);
+  const int c = 4 * (s - t * KS) + kk;
+  const fcplx* Mt = t == 0 ? M0 : (t == 1 ? M1 : M2);
+  return (s < S && c < q && rin) ? Mt[(size_t)c * q + ra] : tmk<fcplx>(0, 0);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_t xs_b, int B,
@@ -664,62 +707,131 @@ __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_
   } else {  // ODD0, BWD0
     k = 2 * blk + 1; rw0 = k; M0 = m0 + blk * qq; T = 1;
   }
-  // panels: element e -> (t, bb, c), c fastest; zero past q and past nbt
-  for (int e = tid; e < T * kMB * q4; e += NT) {
-    const int t = e / (kMB * q4), rem = e - t * kMB * q4;
-    const int bb = rem / q4, c = rem - bb * q4;
-    fcplx v = tmk<fcplx>(0, 0);
-    if (bb < nbt && c < q) {
-      const fcplx* xb = x + (size_t)(b0 + bb) * xs_b;
-      if (MODE == BSTEP_BWD0) {
-        const fcplx* cf = coef + ((size_t)k * q + c) * 9;
-        for (int dZ = -1; dZ <= 1; ++dZ) {
-          const int rr = c + dZ;
-          if (rr < 0 || rr >= q) continue;
-          v = tfma(cf[(dZ + 1) * 3 + 0], xb[(size_t)(k - 1) * q + rr], v);
-          if (k + 1 < n) v = tfma(cf[(dZ + 1) * 3 + 2], xb[(size_t)(k + 1) * q + rr], v);
-        }
-      } else {
-        v = xb[(size_t)(t == 0 ? rw0 : (t == 1 ? rw1 : rw2)) * q + c];
-        if (MODE == BSTEP_BWD && t > 0) v = tneg(v);
-      }
-    }
-    xr[(t * q4 + c) * LB + bb] = v.x;
-    xi[(t * q4 + c) * LB + bb] = v.y;
-  }
-  __syncthreads();
   const int w = tid >> 6, l = tid & 63;
   const int ra = 16 * w + (l & 15);  // factor row this lane feeds
   const int kk = l >> 4;             // column within the K step
-  f32x4_t dre0 = {0, 0, 0, 0}, dim0 = {0, 0, 0, 0}, dre1 = {0, 0, 0, 0}, dim1 = {0, 0, 0, 0};
-  for (int t = 0; t < T; ++t) {
-    const fcplx* Mt = (t == 0 ? M0 : (t == 1 ? M1 : M2)) + ra;
-    const float* pr = xr + (size_t)t * q4 * LB + (l & 15);
-    const float* pi = xi + (size_t)t * q4 * LB + (l & 15);
-    for (int c0 = 0; c0 < q4; c0 += 4 * U) {
-      fcplx cur[U];
+  // K steps flattened over the panels: step s is panel t = s / KS, factor
+  // column c = 4 (s % KS) + kk, LDS panel row t q4 + c = 4 s + kk
+  const int KS = q4 >> 2, S = T * KS;
+  const bool rin = ra < q;
+  // the first U steps' factor elements are in flight during the staging
+  fcplx cur[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + 4 * u + kk;
-        cur[u] = (c < q && ra < q) ? Mt[(size_t)c * q] : tmk<fcplx>(0, 0);
+  for (int u = 0; u < U; ++u) cur[u] = bstep_fac(M0, M1, M2, u, S, KS, kk, q, rin, ra);
+  // panels: thread (c, slot) = (tid % q4, tid / q4) stages column c of the
+  // (panel, right-hand side) pairs slot, slot + SL, ... (SL = NT / q4 >= 4
+  // since NT = 64 ceil(q / 16) and q4 <= 16 ceil(q / 16), so at most 8 pairs
+  // per thread and panel); zero past q and past nbt
+  const int c = tid % q4, slot = tid / q4, SL = NT / q4;
+  const bool cact = slot < SL;
+  constexpr int EPT = 8 * bstep_panels<MODE>();
+  if constexpr (MODE == BSTEP_BWD0) {
+    // one panel: L_k x_{k-1} + U_k x_{k+1} from the stencil coefficients.
+    // Rows k - 1 and k + 1 of the pairs are loaded at once and pass through
+    // the panel one after the other; each thread keeps its column's six
+    // coefficients in registers and its sums until the panel is free.
+    const bool hp = k + 1 < n;
+    fcplx cl[3], cu[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int rr = c + d - 1;
+      const bool ok = cact && c < q && rr >= 0 && rr < q;
+      const fcplx* cf = coef + ((size_t)k * q + (ok ? c : 0)) * 9;
+      cl[d] = ok ? cf[d * 3 + 0] : tmk<fcplx>(0, 0);
+      cu[d] = ok && hp ? cf[d * 3 + 2] : tmk<fcplx>(0, 0);
+    }
+    fcplx xm[EPT], xp[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int bb = slot + i * SL;
+      const bool ld = cact && bb < nbt && c < q;
+      const fcplx* xb = x + (size_t)(b0 + (ld ? bb : 0)) * xs_b + c;
+      xm[i] = ld ? xb[(size_t)(k - 1) * q] : tmk<fcplx>(0, 0);
+      xp[i] = ld && hp ? xb[(size_t)(k + 1) * q] : tmk<fcplx>(0, 0);
+    }
+    fcplx v[EPT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) __syncthreads();  // the first row's sums are formed
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int bb = slot + i * SL;
+        if (cact && bb < kMB) {
+          xr[c * LB + bb] = h ? xp[i].x : xm[i].x;
+          xi[c * LB + bb] = h ? xp[i].y : xm[i].y;
+        }
       }
+      __syncthreads();
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + 4 * u;
-        if (c >= q4) break;
-        const int o = (c + kk) * LB;
-        const float br0 = pr[o], bi0 = pi[o], br1 = pr[o + 16], bi1 = pi[o + 16];
-        const float ar = cur[u].x, ai = cur[u].y;
-        dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br0, dre0, 0, 0, 0);
-        dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi0, dre0, 0, 0, 0);
-        dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi0, dim0, 0, 0, 0);
-        dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br0, dim0, 0, 0, 0);
-        dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br1, dre1, 0, 0, 0);
-        dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi1, dre1, 0, 0, 0);
-        dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi1, dim1, 0, 0, 0);
-        dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br1, dim1, 0, 0, 0);
+      for (int i = 0; i < EPT; ++i) {
+        const int bb = slot + i * SL;
+        if (!h) v[i] = tmk<fcplx>(0, 0);
+        if (cact && bb < kMB) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int o = min(max(c + d - 1, 0), q4 - 1) * LB + bb;
+            v[i] = tfma(h ? cu[d] : cl[d], tmk<fcplx>(xr[o], xi[o]), v[i]);
+          }
+        }
       }
     }
+    __syncthreads();  // the second row's sums are formed
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int bb = slot + i * SL;
+      if (cact && bb < kMB) {
+        xr[c * LB + bb] = v[i].x;
+        xi[c * LB + bb] = v[i].y;
+      }
+    }
+  } else {
+    // every load issued before the stores
+    fcplx sv[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int pr = slot + i * SL, t = pr / kMB, bb = pr % kMB;
+      sv[i] = tmk<fcplx>(0, 0);
+      if (cact && t < T && bb < nbt && c < q) {
+        sv[i] = x[(size_t)(b0 + bb) * xs_b + (size_t)(t == 0 ? rw0 : (t == 1 ? rw1 : rw2)) * q + c];
+        if (MODE == BSTEP_BWD && t > 0) sv[i] = tneg(sv[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int pr = slot + i * SL, t = pr / kMB, bb = pr % kMB;
+      if (cact && t < T) {
+        xr[(t * q4 + c) * LB + bb] = sv[i].x;
+        xi[(t * q4 + c) * LB + bb] = sv[i].y;
+      }
+    }
+  }
+  __syncthreads();
+  f32x4_t dre0 = {0, 0, 0, 0}, dim0 = {0, 0, 0, 0}, dre1 = {0, 0, 0, 0}, dim1 = {0, 0, 0, 0};
+  const float* pr = xr + (l & 15);
+  const float* pi = xi + (l & 15);
+  for (int s0 = 0; s0 < S; s0 += U) {
+    // the next U steps' loads go out before this group's products
+    fcplx nxt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) nxt[u] = bstep_fac(M0, M1, M2, s0 + U + u, S, KS, kk, q, rin, ra);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int st = s0 + u;
+      if (st >= S) break;
+      const int o = (4 * st + kk) * LB;
+      const float br0 = pr[o], bi0 = pi[o], br1 = pr[o + 16], bi1 = pi[o + 16];
+      const float ar = cur[u].x, ai = cur[u].y;
+      dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br0, dre0, 0, 0, 0);
+      dre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi0, dre0, 0, 0, 0);
+      dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi0, dim0, 0, 0, 0);
+      dim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br0, dim0, 0, 0, 0);
+      dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br1, dre1, 0, 0, 0);
+      dre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi1, dre1, 0, 0, 0);
+      dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi1, dim1, 0, 0, 0);
+      dim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br1, dim1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
   }
   // D layout: lane l holds rows 4 (l / 16) + i of column l % 16
   const size_t okq = (size_t)(MODE == BSTEP_FWD || MODE == BSTEP_BWD ? (k << shift) : k) * q;
