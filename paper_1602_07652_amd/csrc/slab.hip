@@ -1729,10 +1729,15 @@ static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumula
     T* vcur;
     if (l == 0) {
       vcur = SB<T>::w(s);  // g^0 is unchanged: v^0 = w^0
-    } else {
+    } else if (B == 1) {
       vcur = SB<T>::work(p, vprev == SB<T>::work(p, 0) ? 1 : 0);
       LS_TRY(scatter<T>(p, S[l - 1], vprev, v, accumulate, B, &s));
       LS_TRY(solve_t<T>(p, s, SB<T>::g(s), vcur, B));
+    } else {
+      // g^l is not needed after this solve: the batched steps run in place
+      vcur = SB<T>::g(s);
+      LS_TRY(scatter<T>(p, S[l - 1], vprev, v, accumulate, B, &s));
+      LS_TRY(solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), vcur, (size_t)p->n * s.q, B));
     }
     if (l == L - 1) LS_TRY(scatter<T>(p, s, vcur, v, accumulate, B, nullptr));
     vprev = vcur;
