@@ -114,11 +114,17 @@ ls_status fgmres(ls_plan* p, Op op, Prec prec, const T* b, T* x, int B, double t
     LS_TRY(op(Zj, w, B));
     h1.resize((size_t)B * (j + 1));
     h2.resize((size_t)B * (j + 1));
-    LS_TRY(vec_multidot(p, KV.base, j + 1, stride, w, N, B, h1.data()));
-    LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, stride, h1.data(), N, B));
-    LS_TRY(vec_multidot(p, KV.base, j + 1, stride, w, N, B, h2.data()));
-    LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, stride, h2.data(), N, B));
-    LS_TRY(vec_norms(p, w, N, B, hn.data()));
+    if (j + 1 <= 8) {  // fused on the device, one transfer
+      LS_TRY(vec_cgs2(p, KV.base, j + 1, stride, w, N, B, h1.data(), h2.data(), hn.data()));
+      for (int i = 0; i < B; ++i)  // NaN stays NaN: a poisoned vector must not look converged
+        hn[i] = std::isnan(hn[i]) ? hn[i] : std::sqrt(std::fmax(hn[i], 0.0));
+    } else {
+      LS_TRY(vec_multidot(p, KV.base, j + 1, stride, w, N, B, h1.data()));
+      LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, stride, h1.data(), N, B));
+      LS_TRY(vec_multidot(p, KV.base, j + 1, stride, w, N, B, h2.data()));
+      LS_TRY(vec_multiaxpy(p, w, KV.base, j + 1, stride, h2.data(), N, B));
+      LS_TRY(vec_norms(p, w, N, B, hn.data()));
+    }
     jlast = j + 1;
     for (int i = 0; i < B; ++i) {
       if (!active[i]) continue;

@@ -5,6 +5,7 @@
 // Vectors are complex FP64 or FP32; a set of k vectors has a fixed stride.
 #include "ls_internal.h"
 
+#include <algorithm>
 #include <vector>
 
 namespace {
@@ -39,7 +40,9 @@ __global__ __launch_bounds__(kDotThreads) void k_multidot(const T* __restrict__ 
       if (i < k) acc[i] = cfmaconj(up(V[i * stride + t]), wv, acc[i]);
   }
   __shared__ cplx red[kDotThreads];
-  for (int i = 0; i < k; ++i) {
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) {  // constant indices keep acc in registers
+    if (i >= k) break;
     red[threadIdx.x] = acc[i];
     __syncthreads();
     for (int s = kDotThreads / 2; s > 0; s >>= 1) {
@@ -83,6 +86,62 @@ __global__ void k_multiaxpy(T* __restrict__ y, const T* __restrict__ y0, const T
   T acc = y0 ? y0[off] : tmk<T>(0, 0);
   for (int i = 0; i < k; ++i) acc = tfma(tmk<T>(sign * c[i].x, sign * c[i].y), V[i * stride + off], acc);
   y[off] = acc;
+}
+
+// One Gram-Schmidt update fused with the next inner product, for k <=
+// kGroup basis vectors: w[b] -= sum_i c[b][i] V_i[b] (c on the device, the
+// update in the precision of T exactly as k_multiaxpy forms it), then the
+// partial sums of conj(V_i[b]) w[b] (NORM: of |w[b]|^2) exactly as
+// k_multidot forms them from the updated w, on the same grid.
+template <typename T, bool NORM>
+__global__ __launch_bounds__(kDotThreads) void k_update_dot(const T* __restrict__ V, int k, size_t stride,
+                                                            T* __restrict__ w, size_t N,
+                                                            const cplx* __restrict__ c, int ldc,
+                                                            cplx* __restrict__ partial) {
+  V += (size_t)blockIdx.y * N;
+  w += (size_t)blockIdx.y * N;
+  c += (size_t)blockIdx.y * ldc;
+  partial += (size_t)blockIdx.y * gridDim.x * kGroup;
+  T cf[kGroup];
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) cf[i] = i < k ? tmk<T>(-c[i].x, -c[i].y) : tmk<T>(0, 0);
+  constexpr int NA = NORM ? 1 : kGroup;
+  cplx acc[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) acc[i] = cmk(0, 0);
+  for (size_t t = (size_t)blockIdx.x * kDotThreads + threadIdx.x; t < N;
+       t += (size_t)gridDim.x * kDotThreads) {
+    T vi[kGroup];
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) vi[i] = i < k ? V[i * stride + t] : tmk<T>(0, 0);
+    T a = w[t];
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i)
+      if (i < k) a = tfma(cf[i], vi[i], a);
+    w[t] = a;
+    const cplx wv = up(a);
+    if (NORM) {
+      acc[0] = cfmaconj(wv, wv, acc[0]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+        if (i < k) acc[i] = cfmaconj(up(vi[i]), wv, acc[i]);
+    }
+  }
+  __shared__ cplx red[kDotThreads];
+  const int nk = NORM ? 1 : k;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    if (i >= nk) break;
+    red[threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kGroup + i] = red[0];
+    __syncthreads();
+  }
 }
 
 // y[b] = s[b] * x[b]
@@ -204,6 +263,40 @@ ls_status scale_b_t(ls_plan* p, T* y, const T* x, const double* s_host, size_t N
   return LS_OK;
 }
 
+// Classical Gram-Schmidt with one re-orthogonalisation of w against the k
+// vectors V_i (k <= kGroup): h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2,
+// nrm2 = |w|^2, with each update fused into the next inner product and the
+// coefficients kept on the device; one transfer to the host at the end.
+// Every value is the one the unfused sequence of multidot / multiaxpy /
+// norm calls gives.
+template <typename T>
+ls_status cgs2_t(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, int B, cplx* h1_host,
+                 cplx* h2_host, double* nrm2_host) {
+  LS_TRY(ensure_red(p));
+  if (k < 1 || k > kGroup || B > p->opt.max_batch) {
+    ls_set_error("fused Gram-Schmidt step: 1..8 basis vectors");
+    return LS_EUNSUPPORTED;
+  }
+  const int nblk = (int)std::min<size_t>(kDotBlocks, (N + kDotThreads - 1) / kDotThreads);
+  cplx* h1 = p->dotbuf;
+  cplx* h2 = h1 + (size_t)k * B;
+  cplx* nr = h2 + (size_t)k * B;
+  k_multidot<T><<<dim3(nblk, B), kDotThreads, 0, p->stream>>>(V, k, stride, w, N, p->red);
+  k_finish_dot<<<dim3(k, B), 256, 0, p->stream>>>(p->red, nblk, h1, k);
+  k_update_dot<T, false><<<dim3(nblk, B), kDotThreads, 0, p->stream>>>(V, k, stride, w, N, h1, k, p->red);
+  k_finish_dot<<<dim3(k, B), 256, 0, p->stream>>>(p->red, nblk, h2, k);
+  k_update_dot<T, true><<<dim3(nblk, B), kDotThreads, 0, p->stream>>>(V, k, stride, w, N, h2, k, p->red);
+  k_finish_dot<<<dim3(1, B), 256, 0, p->stream>>>(p->red, nblk, nr, 1);
+  LS_HIP(hipGetLastError());
+  std::vector<cplx> hb((size_t)(2 * k + 1) * B);
+  LS_HIP(hipMemcpyAsync(hb.data(), h1, sizeof(cplx) * hb.size(), hipMemcpyDeviceToHost, p->stream));
+  LS_HIP(hipStreamSynchronize(p->stream));
+  std::copy(hb.begin(), hb.begin() + (size_t)k * B, h1_host);
+  std::copy(hb.begin() + (size_t)k * B, hb.begin() + (size_t)2 * k * B, h2_host);
+  for (int b = 0; b < B; ++b) nrm2_host[b] = hb[(size_t)2 * k * B + b].x;
+  return LS_OK;
+}
+
 }  // namespace
 
 #define LS_BLAS_INSTANCES(T)                                                                     \
@@ -225,6 +318,10 @@ ls_status scale_b_t(ls_plan* p, T* y, const T* x, const double* s_host, size_t N
     for (int b = 0; b < B; ++b) /* NaN stays NaN: a poisoned vector must not look converged */     \
       out_host[b] = std::isnan(d[b].x) ? d[b].x : sqrt(fmax(d[b].x, 0.0));                         \
     return LS_OK;                                                                                  \
+  }                                                                                                \
+  ls_status vec_cgs2(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, int B,         \
+                     cplx* h1_host, cplx* h2_host, double* nrm2_host) {                            \
+    return cgs2_t<T>(p, V, k, stride, w, N, B, h1_host, h2_host, nrm2_host);                       \
   }                                                                                                \
   ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host) {                        \
     return vec_norms(p, w, N, 1, out_host);                                                        \

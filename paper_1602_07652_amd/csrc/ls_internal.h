@@ -280,6 +280,9 @@ ls_status bidirectional_apply(ls_plan* p, const fcplx* g, fcplx* v, int B = 1);
   ls_status vec_lincomb(ls_plan* p, T* x, const T* Z, int k, size_t stride,                       \
                         const cplx* coef_host, size_t N, int B);                                   \
   ls_status vec_norms(ls_plan* p, const T* w, size_t N, int B, double* out_host);                 \
+  /* classical Gram-Schmidt with one re-orthogonalisation, 1 <= k <= 8 */                         \
+  ls_status vec_cgs2(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, int B,         \
+                     cplx* h1_host, cplx* h2_host, double* nrm2_host);                             \
   ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host);                         \
   ls_status vec_scale_b(ls_plan* p, T* y, const T* x, const double* s_host, size_t N, int B);     \
   ls_status vec_scale_copy(ls_plan* p, T* y, const T* x, double s, size_t N);                     \
