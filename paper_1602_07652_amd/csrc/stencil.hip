@@ -181,39 +181,74 @@ __global__ void k_stencil_solve(const cplx* __restrict__ gram, const cplx* __res
 __device__ __forceinline__ int axis_type(int i, int n) { return i == 0 ? 0 : (i == n - 1 ? 2 : 1); }
 
 // y = A r (mode 0), y = C v (mode 1), y = g - C v (mode 2); T = double2
-// or float2 (tables and arithmetic in that precision).
-template <typename T, typename R, int MODE>
-__global__ void k_stencil(const T* __restrict__ in, const T* __restrict__ g, T* __restrict__ out,
-                          const T* __restrict__ tables, const R* __restrict__ m, int n, R omega2) {
+// or float2 (tables and arithmetic in that precision).  Thread i takes
+// column i of RW consecutive rows: a window of three rows of in (and m) at
+// columns i - 1, i, i + 1 rolls down the rows, so each input is loaded
+// three times (neighbouring lanes, mostly cache hits) instead of nine; the
+// interior point type's coefficients are loaded once (uniform addresses),
+// the boundary types' per point.  Values outside the grid enter as zeros,
+// which leaves every sum as the tap-by-tap sum over the grid points.
+template <typename T, typename R, int MODE, int RW>
+__global__ __launch_bounds__(128) void k_stencil(const T* __restrict__ in, const T* __restrict__ g,
+                                                 T* __restrict__ out, const T* __restrict__ tables,
+                                                 const R* __restrict__ m, int n, R omega2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
+  const int j0 = blockIdx.y * RW;
   const size_t base = (size_t)blockIdx.z * n * n;
   if (i >= n) return;
-  const int t = axis_type(j, n) * 3 + axis_type(i, n);
-  const T* al = tables + t * 9;
-  const T* be = tables + 81 + t * 9;
-  T acc = tmk<T>(0, 0);
+  const int ti = axis_type(i, n);
+  T ai[9], bi[9];
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int jj = j + dz;
-    if (jj < 0 || jj >= n) continue;
+  for (int s = 0; s < 9; ++s) {
+    ai[s] = tables[4 * 9 + s];
+    bi[s] = tables[81 + 4 * 9 + s];
+  }
+  T v[3][3];
+  R mw[3][3];
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int ii = i + dx;
-      if (ii < 0 || ii >= n) continue;
-      const int s = (dz + 1) * 3 + dx + 1;
-      const size_t idx = (size_t)jj * n + ii;
-      T c = al[s];
-      if (MODE != 0) {
-        const R f = omega2 * m[idx];
-        c.x = fma(be[s].x, f, c.x);
-        c.y = fma(be[s].y, f, c.y);
-      }
-      acc = tfma(c, in[base + idx], acc);
+  for (int w = 0; w < 2; ++w) {  // rows j0 - 1 and j0
+    const int jj = j0 - 1 + w;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int ii = i + d - 1;
+      const bool ok = jj >= 0 && jj < n && ii >= 0 && ii < n;
+      const size_t idx = ok ? (size_t)jj * n + ii : 0;
+      v[w + 1][d] = ok ? in[base + idx] : tmk<T>(0, 0);
+      mw[w + 1][d] = (MODE != 0 && ok) ? m[idx] : (R)0;
     }
   }
-  const size_t o = base + (size_t)j * n + i;
-  out[o] = (MODE == 2) ? tsub(g[o], acc) : acc;
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int j = j0 + r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {  // roll the window down one row
+      v[0][d] = v[1][d];
+      v[1][d] = v[2][d];
+      mw[0][d] = mw[1][d];
+      mw[1][d] = mw[2][d];
+      const int jj = j + 1, ii = i + d - 1;
+      const bool ok = jj < n && ii >= 0 && ii < n;
+      const size_t idx = ok ? (size_t)jj * n + ii : 0;
+      v[2][d] = ok ? in[base + idx] : tmk<T>(0, 0);
+      mw[2][d] = (MODE != 0 && ok) ? m[idx] : (R)0;
+    }
+    if (j >= n) break;
+    const int t = axis_type(j, n) * 3 + ti;
+    T acc = tmk<T>(0, 0);
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+      T c = t == 4 ? ai[s] : tables[t * 9 + s];
+      if (MODE != 0) {
+        const T b = t == 4 ? bi[s] : tables[81 + t * 9 + s];
+        const R f = omega2 * mw[s / 3][s % 3];
+        c.x = fma(b.x, f, c.x);
+        c.y = fma(b.y, f, c.y);
+      }
+      acc = tfma(c, v[s / 3][s % 3], acc);
+    }
+    const size_t o = base + (size_t)j * n + i;
+    out[o] = (MODE == 2) ? tsub(g[o], acc) : acc;
+  }
 }
 
 __global__ void k_to_f32(const cplx* __restrict__ a, fcplx* __restrict__ b, int cnt) {
@@ -252,14 +287,15 @@ template <typename T, typename R>
 static ls_status launch_stencil(ls_plan* p, const T* tables, const R* m, int mode, const T* in,
                                 const T* g, T* out, int batch) {
   const int n = p->n;
-  dim3 grid((n + 127) / 128, n, batch);
+  constexpr int RW = 8;  // rows per thread
+  dim3 grid((n + 127) / 128, (n + RW - 1) / RW, batch);
   const R w2 = (R)(p->omega * p->omega);
   if (mode == 0)
-    k_stencil<T, R, 0><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
+    k_stencil<T, R, 0, RW><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
   else if (mode == 1)
-    k_stencil<T, R, 1><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
+    k_stencil<T, R, 1, RW><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
   else
-    k_stencil<T, R, 2><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
+    k_stencil<T, R, 2, RW><<<grid, 128, 0, p->stream>>>(in, g, out, tables, m, n, w2);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
