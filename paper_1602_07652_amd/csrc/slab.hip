@@ -1066,6 +1066,60 @@ __global__ void k_scatter(const T* __restrict__ src, T* __restrict__ out, int n,
   }
 }
 
+// Horizontal slabs (grid rows are the slab's short axis), many right-hand
+// sides, no trace sources: the same copies as k_gather / k_scatter through
+// a 64 (i) x 32 (r) LDS tile, so that both the grid rows (i fastest) and the
+// slab rows (r fastest) are read and written in runs.
+constexpr int kTI = 64, kTR = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_h(const T* __restrict__ g, T* __restrict__ dst, int n, int q,
+                                                  int z0, int a, int b) {
+  __shared__ T tile[kTR][kTI + 1];
+  const int i0 = blockIdx.x * kTI, r0 = blockIdx.y * kTR;
+  g += (size_t)blockIdx.z * n * n;
+  dst += (size_t)blockIdx.z * n * q;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kTI * kTR / 256; ++e) {  // grid row Z = z0 + r, i fastest
+    const int ii = tid % kTI, rr = tid / kTI + e * (256 / kTI);
+    const int i = i0 + ii, Z = z0 + r0 + rr;
+    tile[rr][ii] = (i < n && r0 + rr < q && Z >= a && Z <= b) ? g[(size_t)Z * n + i] : tmk<T>(0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kTI * kTR / 256; ++e) {  // slab row i, r fastest
+    const int rr = tid % kTR, ii = tid / kTR + e * (256 / kTR);
+    const int i = i0 + ii, r = r0 + rr;
+    if (i < n && r < q) dst[(size_t)i * q + r] = tile[rr][ii];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_h(const T* __restrict__ src, T* __restrict__ out, int n, int q,
+                                                   int z0, int a, int b, int accumulate) {
+  __shared__ T tile[kTR][kTI + 1];
+  const int i0 = blockIdx.x * kTI, Z0 = a + blockIdx.y * kTR;
+  src += (size_t)blockIdx.z * n * q;
+  out += (size_t)blockIdx.z * n * n;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kTI * kTR / 256; ++e) {  // slab row i, Z fastest
+    const int rr = tid % kTR, ii = tid / kTR + e * (256 / kTR);
+    const int i = i0 + ii, Z = Z0 + rr;
+    if (i < n && Z <= b) tile[rr][ii] = src[(size_t)i * q + (Z - z0)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kTI * kTR / 256; ++e) {  // grid row Z, i fastest
+    const int ii = tid % kTI, rr = tid / kTI + e * (256 / kTI);
+    const int i = i0 + ii, Z = Z0 + rr;
+    if (i < n && Z <= b) {
+      const size_t o = (size_t)Z * n + i;
+      out[o] = accumulate ? tadd(out[o], tile[rr][ii]) : tile[rr][ii];
+    }
+  }
+}
+
 __global__ void k_down_copy(const cplx* __restrict__ a, fcplx* __restrict__ b, size_t cnt) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
@@ -1666,8 +1720,12 @@ static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B, Sl
   }
   // one right-hand side: the sources in the gather launch; many: a launch of their own
   const bool fuse = B == 1;
-  k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b, s.orient,
-                                                                  SB<T>::coef(s), A, Bj, fuse ? sA : nullptr);
+  if (!fuse && s.orient == 0)
+    k_gather_h<T><<<dim3((n + kTI - 1) / kTI, (s.q + kTR - 1) / kTR, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0,
+                                                                                          s.a, s.b);
+  else
+    k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b, s.orient,
+                                                                    SB<T>::coef(s), A, Bj, fuse ? sA : nullptr);
   if (sA && !fuse)
     k_inject<T><<<dim3((n + 255) / 256, B), 256, 0, p->stream>>>(dst, s.q, SB<T>::coef(s), n, A, Bj, sA, up->q,
                                                                   (const T*)nullptr, 0, 0);
@@ -1698,9 +1756,13 @@ static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool a
     q2 = nx.q;
     r2 = nx.a - nx.z0;
   }
-  k_scatter<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(
-      src, out, n, s.q, s.z0, s.a, s.b, s.orient, acc ? 1 : 0, fuse ? rhs : nullptr, qr,
-      next ? SB<T>::coef(*next) : nullptr, A, Bj, s2, q2, r2);
+  if (!fuse && s.orient == 0)
+    k_scatter_h<T><<<dim3((n + kTI - 1) / kTI, (s.b - s.a + kTR) / kTR, B), 256, 0, p->stream>>>(
+        src, out, n, s.q, s.z0, s.a, s.b, acc ? 1 : 0);
+  else
+    k_scatter<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(
+        src, out, n, s.q, s.z0, s.a, s.b, s.orient, acc ? 1 : 0, fuse ? rhs : nullptr, qr,
+        next ? SB<T>::coef(*next) : nullptr, A, Bj, s2, q2, r2);
   if (next && !fuse)
     k_inject<T><<<dim3((n + 255) / 256, B), 256, 0, p->stream>>>(rhs, qr, SB<T>::coef(*next), n, A, Bj, src, s.q,
                                                                   s2, q2, r2);
