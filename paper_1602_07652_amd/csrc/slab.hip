@@ -937,35 +937,52 @@ __global__ void k_top_reduce(const fcplx* __restrict__ part, int slices, int Nt,
   x[(size_t)b * xs_b + ((size_t)j << shift) * q + (o - j * q)] = sum;
 }
 
-template <typename C>
+template <typename C, int RB>
 __global__ void k_fwd0_even_b(C* __restrict__ x, size_t xs_b, const C* __restrict__ coef, int n,
-                              int q, int B, int RB) {
+                              int q, int B) {
   // x_k -= L_k x_{k-1} + U_k x_{k+1} for the even blocks k of level 0, RB
-  // right-hand sides per thread: the stencil coefficients are loaded once
+  // right-hand sides per thread: the stencil coefficients are loaded once,
+  // and every right-hand side's inputs are loaded before the first store
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 2 * blockIdx.y;
   if (r >= q) return;
-  const int b0 = blockIdx.z * RB, b1 = min(B, b0 + RB);
+  const int b0 = blockIdx.z * RB;
   const C* cf = coef + ((size_t)k * q + r) * 9;
+  const bool lo = k >= 1, hi = k + 1 < n;
   C cl[3], cu[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int rr = r + d - 1;
     const bool in = rr >= 0 && rr < q;
-    cl[d] = (in && k >= 1) ? cf[d * 3 + 0] : tmk<C>(0, 0);
-    cu[d] = (in && k + 1 < n) ? cf[d * 3 + 2] : tmk<C>(0, 0);
+    cl[d] = (in && lo) ? cf[d * 3 + 0] : tmk<C>(0, 0);
+    cu[d] = (in && hi) ? cf[d * 3 + 2] : tmk<C>(0, 0);
   }
-  for (int b = b0; b < b1; ++b) {
-    C* xb = x + (size_t)b * xs_b;
-    C acc = xb[(size_t)k * q + r];
+  C xk[RB], xm[RB][3], xp[RB][3];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const bool ok = b0 + j < B;
+    const C* xb = x + (size_t)(ok ? b0 + j : 0) * xs_b;
+    xk[j] = ok ? xb[(size_t)k * q + r] : tmk<C>(0, 0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int rr = r + d - 1;
+      const bool in = ok && rr >= 0 && rr < q;
+      xm[j][d] = (in && lo) ? xb[(size_t)(k - 1) * q + rr] : tmk<C>(0, 0);
+      xp[j][d] = (in && hi) ? xb[(size_t)(k + 1) * q + rr] : tmk<C>(0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    if (b0 + j >= B) break;
+    C acc = xk[j];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int rr = r + d - 1;
       if (rr < 0 || rr >= q) continue;
-      if (k >= 1) acc = tsub(acc, tmul(cl[d], xb[(size_t)(k - 1) * q + rr]));
-      if (k + 1 < n) acc = tsub(acc, tmul(cu[d], xb[(size_t)(k + 1) * q + rr]));
+      if (lo) acc = tsub(acc, tmul(cl[d], xm[j][d]));
+      if (hi) acc = tsub(acc, tmul(cu[d], xp[j][d]));
     }
-    xb[(size_t)k * q + r] = acc;
+    x[(size_t)(b0 + j) * xs_b + (size_t)k * q + r] = acc;
   }
 }
 
@@ -1005,10 +1022,14 @@ __global__ void k_inject(T* __restrict__ rhs, int qr, const T* __restrict__ coef
   T* rb = rhs + (size_t)blockIdx.y * n * qr;
   const T* sb = src + (size_t)blockIdx.y * n * qs;
   const T* s2b = s2 ? s2 + (size_t)blockIdx.y * n * q2 : nullptr;
-  T* o = rb + (size_t)i * qr + A.rt;
-  *o = tadd(*o, inject_term(coef, n, qr, i, A, sb, (const T*)nullptr, 0, 0));
-  o = rb + (size_t)i * qr + Bj.rt;
-  *o = tadd(*o, inject_term(coef, n, qr, i, Bj, sb, s2b, q2, r2));
+  // both lines' loads before either store
+  T* oa = rb + (size_t)i * qr + A.rt;
+  T* ob = rb + (size_t)i * qr + Bj.rt;
+  const T ta = inject_term(coef, n, qr, i, A, sb, (const T*)nullptr, 0, 0);
+  const T tb = inject_term(coef, n, qr, i, Bj, sb, s2b, q2, r2);
+  const T va = *oa, vb = *ob;
+  *oa = tadd(va, ta);
+  *ob = tadd(vb, tb);
 }
 
 // dst[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere; with
@@ -1589,9 +1610,9 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
   }
   bstep<C, BSTEP_ODD0>(p, x, xs_b, B, fac + L0.off_dinv, nullptr, nullptr, coef, q, L0.nl, 0,
                        L0.nl / 2);
-  constexpr int RB = 8;  // right-hand sides per thread
-  k_fwd0_even_b<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, (B + RB - 1) / RB), 128, 0, p->stream>>>(
-      x, xs_b, coef, n, q, B, RB);
+  constexpr int RB = sizeof(C) == 8 ? 4 : 2;  // right-hand sides per thread (no spills)
+  k_fwd0_even_b<C, RB><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, (B + RB - 1) / RB), 128, 0, p->stream>>>(
+      x, xs_b, coef, n, q, B);
   for (int l = 1; l < top_l; ++l) {
     const SlabLevel& L = s.levels[l];
     bstep<C, BSTEP_FWD>(p, x, xs_b, B, fac + L.off_pm, fac + L.off_pp, nullptr, coef, q, L.nl, l,
