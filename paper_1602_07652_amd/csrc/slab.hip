@@ -482,7 +482,7 @@ enum { BSTEP_FWD = 0, BSTEP_BWD = 1, BSTEP_LAST = 2, BSTEP_ODD0 = 3, BSTEP_BWD0 
 template <typename C, int BT, int NT>
 struct BShape {
   static constexpr int XS = BT + 16 / (int)sizeof(C);  // padded panel row (complex entries)
-  static constexpr int U = 8;                           // factor loads in flight per thread
+  static constexpr int U = 4;                           // factor loads in flight per thread
   static constexpr int ROWS = (3 * kMaxQ > NT) ? 3 * kMaxQ : NT;
   static constexpr size_t lds() { return (size_t)ROWS * XS * sizeof(C); }
 };
