@@ -672,7 +672,7 @@ __global__ __launch_bounds__(384) void k_bstep_mfma(fcplx* __restrict__ x, size_
                                                     const fcplx* __restrict__ m0, const fcplx* __restrict__ m1,
                                                     const fcplx* __restrict__ m2, const fcplx* __restrict__ coef,
                                                     int n, int q, int nl, int shift, int tiles, int total) {
-  constexpr int U = 8, LB = kMB + 1;  // K steps in flight; padded panel row
+  constexpr int U = 4, LB = kMB + 1;  // K steps in flight; padded panel row
   extern __shared__ unsigned char lds_raw[];
   const int q4 = mq4(q);
   float* xr = reinterpret_cast<float*>(lds_raw);  // [panels][q4][LB]
