@@ -262,7 +262,7 @@ enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4 };
 template <int MODE>
 struct RCols {
   static constexpr int T = MODE == R_BWD ? 3 : (MODE == R_FWD ? 2 : 1);
-  static constexpr int N = 8 * T;
+  static constexpr int N = 7 * T;
 };
 
 // Row tiles per block for extended thickness q: the fewest with at most
@@ -282,7 +282,7 @@ inline int row_splits(int q, int t, int ncol) {
 //   R_BWD   level l, k odd:  y_k = Dinv_k t_k - (Dinv L)_k y_{k-1} - (Dinv U)_k y_{k+1}
 //   R_BWD0  level 0, k odd:  y_k -= Dinv_k t_k, t_k = L_k y_{k-1} + U_k y_{k+1} (k_odd0_lu)
 template <typename C, int MODE>
-__global__ __launch_bounds__(256) void k_rstep(const C* __restrict__ g, C* __restrict__ t, C* __restrict__ y,
+__global__ __launch_bounds__(256, 4) void k_rstep(const C* __restrict__ g, C* __restrict__ t, C* __restrict__ y,
                                               const C* __restrict__ m0, const C* __restrict__ m1,
                                               const C* __restrict__ m2, const C* __restrict__ coef, int n,
                                               int q, int nl, int shift, int RS) {
