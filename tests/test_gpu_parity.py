@@ -180,6 +180,29 @@ def test_solve_c1_matches_dense_solution():
     assert info[0]["outer_its"] <= 6
     p.close()
 
+def test_long_arnoldi_runs_match_dense_solutions():
+    """Unpreconditioned inner GMRES (LS_PREC_NONE) runs well past 8 Arnoldi
+    steps, so every solve goes through both Gram-Schmidt forms: the fused
+    device form (up to 8 basis vectors) and the multi-dot / multi-axpy one
+    beyond.  Three right-hand sides at once; each must reach the dense
+    solution of H u = f (Section 2) to the accuracy its residual allows."""
+    n, fq = 48, 6.0
+    m = li.gaussian_disk_medium(n)
+    p, omega = make_plan(n, fq, m, slabs=3, ext=10, precond=2, max_batch=3)
+    uI = np.stack([li.plane_wave(n, omega, th) for th in (0.0, 1.0, 2.5)])
+    f = p.rhs_from_incident(dev(uI))
+    u, infos = p.solve(f, tol=1e-9)
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    uh = host(u)
+    for b, info in enumerate(infos):
+        f_ref = kernel.rhs_from_incident(W, m, uI[b], omega)
+        e = rel(uh[b], solver.dense_solve(W, m, omega, f_ref))
+        banner(f"long Arnoldi, wave {b}: {info}, rel err vs dense {e:.3e}")
+        assert info["converged"] == 1 and info["relres_true"] < 1e-9
+        assert info["inner_its_total"] > 8 * info["outer_its"]
+        assert e < 1e-6
+    p.close()
+
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batched_solve_equals_single_solves(precision):
