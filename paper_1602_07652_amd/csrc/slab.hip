@@ -1013,10 +1013,12 @@ __device__ __forceinline__ T inject_term(const T* __restrict__ coef, int n, int 
 
 // The two trace sources alone: rhs[i][A.rt] and rhs[i][B.rt] of a layer
 // (row stride qr) from src (row stride qs, batch stride n qs) and s2 on
-// line B (many right-hand sides run this as its own launch).
+// line B (many right-hand sides run this as its own launch); rhs2, when
+// set, is a second copy of rhs that receives the same sums.
 template <typename T>
 __global__ void k_inject(T* __restrict__ rhs, int qr, const T* __restrict__ coef, int n, Inject A, Inject Bj,
-                         const T* __restrict__ src, int qs, const T* __restrict__ s2, int q2, int r2) {
+                         const T* __restrict__ src, int qs, const T* __restrict__ s2, int q2, int r2,
+                         T* __restrict__ rhs2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T* rb = rhs + (size_t)blockIdx.y * n * qr;
@@ -1027,9 +1029,14 @@ __global__ void k_inject(T* __restrict__ rhs, int qr, const T* __restrict__ coef
   T* ob = rb + (size_t)i * qr + Bj.rt;
   const T ta = inject_term(coef, n, qr, i, A, sb, (const T*)nullptr, 0, 0);
   const T tb = inject_term(coef, n, qr, i, Bj, sb, s2b, q2, r2);
-  const T va = *oa, vb = *ob;
-  *oa = tadd(va, ta);
-  *ob = tadd(vb, tb);
+  const T va = tadd(*oa, ta), vb = tadd(*ob, tb);
+  *oa = va;
+  *ob = vb;
+  if (rhs2) {
+    T* r2b = rhs2 + (size_t)blockIdx.y * n * qr + (size_t)i * qr;
+    r2b[A.rt] = va;
+    r2b[Bj.rt] = vb;
+  }
 }
 
 // dst[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere; with
@@ -1038,7 +1045,7 @@ __global__ void k_inject(T* __restrict__ rhs, int qr, const T* __restrict__ coef
 template <typename T>
 __global__ void k_gather(const T* __restrict__ g, T* __restrict__ dst, int n, int q, int z0,
                          int a, int b, int orient, const T* __restrict__ coef, Inject A, Inject Bj,
-                         const T* __restrict__ sA) {
+                         const T* __restrict__ sA, T* __restrict__ dst2) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * q) return;
   g += (size_t)blockIdx.y * n * n;
@@ -1054,6 +1061,7 @@ __global__ void k_gather(const T* __restrict__ g, T* __restrict__ dst, int n, in
     if (r == Bj.rt) v = tadd(v, inject_term(coef, n, q, i, Bj, s, (const T*)nullptr, 0, 0));
   }
   dst[(size_t)i * q + r] = v;
+  if (dst2) dst2[(size_t)blockIdx.y * n * q + (size_t)i * q + r] = v;
 }
 
 // out(i, Z) (+)= src[i][Z - z0] for Z in [a, b] (the solution of one layer
@@ -1094,7 +1102,7 @@ __global__ void k_scatter(const T* __restrict__ src, T* __restrict__ out, int n,
 constexpr int kTI = 64, kTR = 32;
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_h(const T* __restrict__ g, T* __restrict__ dst, int n, int q,
-                                                  int z0, int a, int b) {
+                                                  int z0, int a, int b, T* __restrict__ dst2) {
   __shared__ T tile[kTR][kTI + 1];
   const int i0 = blockIdx.x * kTI, r0 = blockIdx.y * kTR;
   g += (size_t)blockIdx.z * n * n;
@@ -1111,7 +1119,10 @@ __global__ __launch_bounds__(256) void k_gather_h(const T* __restrict__ g, T* __
   for (int e = 0; e < kTI * kTR / 256; ++e) {  // slab row i, r fastest
     const int rr = tid % kTR, ii = tid / kTR + e * (256 / kTR);
     const int i = i0 + ii, r = r0 + rr;
-    if (i < n && r < q) dst[(size_t)i * q + r] = tile[rr][ii];
+    if (i < n && r < q) {
+      dst[(size_t)i * q + r] = tile[rr][ii];
+      if (dst2) dst2[(size_t)blockIdx.z * n * q + (size_t)i * q + r] = tile[rr][ii];
+    }
   }
 }
 
@@ -1730,7 +1741,7 @@ ls_status slab_solve(ls_plan* p, Slab& s, const fcplx* g, fcplx* y, int B) { ret
 // sources from the solution w of the layer above:
 //   g^l += -delta_b C^l_{b,b+1} w^{l+1}(b+1) + delta_{b+1} C^l_{b+1,b} w^{l+1}(b)
 template <typename T>
-static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B, Slab* up) {
+static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B, Slab* up, T* dst2 = nullptr) {
   const int n = p->n, tot = n * s.q;
   Inject A{}, Bj{};
   const T* sA = nullptr;
@@ -1743,13 +1754,14 @@ static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B, Sl
   const bool fuse = B == 1;
   if (!fuse && s.orient == 0)
     k_gather_h<T><<<dim3((n + kTI - 1) / kTI, (s.q + kTR - 1) / kTR, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0,
-                                                                                          s.a, s.b);
+                                                                                          s.a, s.b, dst2);
   else
     k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b, s.orient,
-                                                                    SB<T>::coef(s), A, Bj, fuse ? sA : nullptr);
+                                                                    SB<T>::coef(s), A, Bj, fuse ? sA : nullptr,
+                                                                    dst2);
   if (sA && !fuse)
     k_inject<T><<<dim3((n + 255) / 256, B), 256, 0, p->stream>>>(dst, s.q, SB<T>::coef(s), n, A, Bj, sA, up->q,
-                                                                  (const T*)nullptr, 0, 0);
+                                                                  (const T*)nullptr, 0, 0, dst2);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -1786,7 +1798,7 @@ static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool a
         next ? SB<T>::coef(*next) : nullptr, A, Bj, s2, q2, r2);
   if (next && !fuse)
     k_inject<T><<<dim3((n + 255) / 256, B), 256, 0, p->stream>>>(rhs, qr, SB<T>::coef(*next), n, A, Bj, src, s.q,
-                                                                  s2, q2, r2);
+                                                                  s2, q2, r2, (T*)nullptr);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -1801,8 +1813,15 @@ static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumula
   // downward sweep: l = L-1 .. 0 (gather with the trace sources of w^{l+1})
   for (int l = L - 1; l >= 0; --l) {
     Slab& s = S[l];
-    LS_TRY(gather<T>(p, s, g, SB<T>::g(s), B, l != L - 1 ? &S[l + 1] : nullptr));
-    LS_TRY(solve_t<T>(p, s, SB<T>::g(s), SB<T>::w(s), B));
+    if (B == 1) {
+      LS_TRY(gather<T>(p, s, g, SB<T>::g(s), B, l != L - 1 ? &S[l + 1] : nullptr));
+      LS_TRY(solve_t<T>(p, s, SB<T>::g(s), SB<T>::w(s), B));
+    } else {
+      // g^l is kept for the upward sweep; the batched steps run in place on
+      // a second copy that the gather writes alongside it
+      LS_TRY(gather<T>(p, s, g, SB<T>::g(s), B, l != L - 1 ? &S[l + 1] : nullptr, SB<T>::w(s)));
+      LS_TRY(solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), SB<T>::w(s), (size_t)p->n * s.q, B));
+    }
   }
   // upward sweep: l = 0 .. L-1; scattering v^{l-1} also adds its trace
   // sources to g^l
