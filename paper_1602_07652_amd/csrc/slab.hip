@@ -1152,6 +1152,86 @@ __global__ __launch_bounds__(256) void k_scatter_h(const T* __restrict__ src, T*
   }
 }
 
+// The same copies for one right-hand side, through narrower 16 (i) x 32 (r)
+// tiles (enough workgroups for a single grid vector), with the trace
+// sources folded in: the gather adds the downward sweep's sources to its
+// tile before writing it out; the scatter's first row of tiles adds the
+// upward sweep's sources of the next layer to that layer's right-hand side.
+constexpr int kTI1 = 16;
+template <typename T>
+__global__ __launch_bounds__(128) void k_gather_h1(const T* __restrict__ g, T* __restrict__ dst, int n, int q,
+                                                   int z0, int a, int b, const T* __restrict__ coef, Inject A,
+                                                   Inject Bj, const T* __restrict__ sA) {
+  __shared__ T tile[kTR][kTI1 + 1];
+  const int i0 = blockIdx.x * kTI1, r0 = blockIdx.y * kTR;
+  const int tid = threadIdx.x;
+  // trace sources of this tile's columns: thread j < 16 line A, 16 <= j < 32 line B
+  T inj = tmk<T>(0, 0);
+  int injr = -1;
+  if (sA && tid < 2 * kTI1) {
+    const Inject& J = tid < kTI1 ? A : Bj;
+    const int ii = tid % kTI1, i = i0 + ii;
+    if (i < n && J.rt >= r0 && J.rt < r0 + kTR && J.rt < q) {
+      inj = inject_term(coef, n, q, i, J, sA, (const T*)nullptr, 0, 0);
+      injr = J.rt - r0;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kTI1 * kTR / 128; ++e) {  // grid row Z = z0 + r, i fastest
+    const int ii = tid % kTI1, rr = tid / kTI1 + e * (128 / kTI1);
+    const int i = i0 + ii, Z = z0 + r0 + rr;
+    tile[rr][ii] = (i < n && r0 + rr < q && Z >= a && Z <= b) ? g[(size_t)Z * n + i] : tmk<T>(0, 0);
+  }
+  __syncthreads();
+  if (injr >= 0) tile[injr][tid % kTI1] = tadd(tile[injr][tid % kTI1], inj);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kTI1 * kTR / 128; ++e) {  // slab row i, r fastest
+    const int rr = tid % kTR, ii = tid / kTR + e * (128 / kTR);
+    const int i = i0 + ii, r = r0 + rr;
+    if (i < n && r < q) dst[(size_t)i * q + r] = tile[rr][ii];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(128) void k_scatter_h1(const T* __restrict__ src, T* __restrict__ out, int n, int q,
+                                                    int z0, int a, int b, int accumulate, T* __restrict__ rhs,
+                                                    int qr, const T* __restrict__ coef, Inject A, Inject Bj,
+                                                    const T* __restrict__ s2, int q2, int r2) {
+  __shared__ T tile[kTR][kTI1 + 1];
+  const int i0 = blockIdx.x * kTI1, Z0 = a + blockIdx.y * kTR;
+  const int tid = threadIdx.x;
+  const int t = i0 + tid;
+  const bool inj = rhs && blockIdx.y == 0 && tid < kTI1 && t < n;
+  T ta = tmk<T>(0, 0), tb = tmk<T>(0, 0), va = tmk<T>(0, 0), vb = tmk<T>(0, 0);
+  if (inj) {  // the next layer's two trace sources, loads issued with the tile's
+    ta = inject_term(coef, n, qr, t, A, src, (const T*)nullptr, 0, 0);
+    tb = inject_term(coef, n, qr, t, Bj, src, s2, q2, r2);
+    va = rhs[(size_t)t * qr + A.rt];
+    vb = rhs[(size_t)t * qr + Bj.rt];
+  }
+#pragma unroll
+  for (int e = 0; e < kTI1 * kTR / 128; ++e) {  // slab row i, Z fastest
+    const int rr = tid % kTR, ii = tid / kTR + e * (128 / kTR);
+    const int i = i0 + ii, Z = Z0 + rr;
+    if (i < n && Z <= b) tile[rr][ii] = src[(size_t)i * q + (Z - z0)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kTI1 * kTR / 128; ++e) {  // grid row Z, i fastest
+    const int ii = tid % kTI1, rr = tid / kTI1 + e * (128 / kTI1);
+    const int i = i0 + ii, Z = Z0 + rr;
+    if (i < n && Z <= b) {
+      const size_t o = (size_t)Z * n + i;
+      out[o] = accumulate ? tadd(out[o], tile[rr][ii]) : tile[rr][ii];
+    }
+  }
+  if (inj) {
+    rhs[(size_t)t * qr + A.rt] = tadd(va, ta);
+    rhs[(size_t)t * qr + Bj.rt] = tadd(vb, tb);
+  }
+}
+
 __global__ void k_down_copy(const cplx* __restrict__ a, fcplx* __restrict__ b, size_t cnt) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
@@ -1755,6 +1835,9 @@ static ls_status gather(ls_plan* p, const Slab& s, const T* g, T* dst, int B, Sl
   if (!fuse && s.orient == 0)
     k_gather_h<T><<<dim3((n + kTI - 1) / kTI, (s.q + kTR - 1) / kTR, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0,
                                                                                           s.a, s.b, dst2);
+  else if (fuse && s.orient == 0 && !dst2)
+    k_gather_h1<T><<<dim3((n + kTI1 - 1) / kTI1, (s.q + kTR - 1) / kTR), 128, 0, p->stream>>>(
+        g, dst, n, s.q, s.z0, s.a, s.b, SB<T>::coef(s), A, Bj, sA);
   else
     k_gather<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(g, dst, n, s.q, s.z0, s.a, s.b, s.orient,
                                                                     SB<T>::coef(s), A, Bj, fuse ? sA : nullptr,
@@ -1792,6 +1875,10 @@ static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool a
   if (!fuse && s.orient == 0)
     k_scatter_h<T><<<dim3((n + kTI - 1) / kTI, (s.b - s.a + kTR) / kTR, B), 256, 0, p->stream>>>(
         src, out, n, s.q, s.z0, s.a, s.b, acc ? 1 : 0);
+  else if (fuse && s.orient == 0)
+    k_scatter_h1<T><<<dim3((n + kTI1 - 1) / kTI1, (s.b - s.a + kTR) / kTR), 128, 0, p->stream>>>(
+        src, out, n, s.q, s.z0, s.a, s.b, acc ? 1 : 0, rhs, qr, next ? SB<T>::coef(*next) : nullptr, A, Bj, s2, q2,
+        r2);
   else
     k_scatter<T><<<dim3((tot + 255) / 256, B), 256, 0, p->stream>>>(
         src, out, n, s.q, s.z0, s.a, s.b, s.orient, acc ? 1 : 0, fuse ? rhs : nullptr, qr,
