@@ -412,9 +412,19 @@ __global__ __launch_bounds__(256) void k_top(const C* __restrict__ top, const C*
     const int b = lane + 64 * k;
     mv[k] = (o < Nt && b < Nt) ? top[(size_t)o * Nt + b] : tmk<C>(0, 0);
   }
-  for (int e = threadIdx.x; e < Nt; e += 256) {
+  // the inputs: every load issued before the first LDS store
+  constexpr int TE = (kTopMax + 255) / 256;
+  C tin[TE];
+#pragma unroll
+  for (int u = 0; u < TE; ++u) {
+    const int e = threadIdx.x + 256 * u;
     const int j = e / q, r = e - j * q;
-    tv[e] = t[((size_t)j << shift) * q + r];
+    tin[u] = e < Nt ? t[((size_t)j << shift) * q + r] : tmk<C>(0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < TE; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    if (e < Nt) tv[e] = tin[u];
   }
   __syncthreads();
   C acc = tmk<C>(0, 0);
