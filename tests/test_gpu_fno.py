@@ -193,7 +193,7 @@ def _solve_problem(n=64, seed=5000, batch=2):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_fno_converges_and_reports(net, precision):
     """With an untrained network the solver still reaches tol (the oracle's
-    residual judges), whatever the flags say about the network's passes."""
+    residual decides), whatever the flags say about the network's passes."""
     from paper_1602_07652_amd import Plan
     n = 64
     _, flat = _params(seed=17, last_scale=1.0)

@@ -1,7 +1,7 @@
 """What the trained network gains over the method without it (A/B), with the
 weights trained by paper_1602_07652_amd.fno_train on 2000 solves at 256^2
 (Gaussian-random-field media, seeds 1000-2999).  Test media use seeds
-5000+ (never seen in training).  The FP64 oracle judges every solution's
+5000+ (never seen in training).  The FP64 oracle checks every solution's
 residual; iteration counts and wall times are printed for both arms."""
 import os
 import time

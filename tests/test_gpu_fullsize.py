@@ -1,4 +1,4 @@
-"""Full-size workloads judged by the FP64 oracle's residual (a property that
+"""Full-size workloads checked by the FP64 oracle's residual (a property that
 holds at any size): the plain 1024^2 solve as bench.py times it, and the
 64-wave batched FP32 + refinement solve at 1024^2 on sampled waves."""
 import numpy as np
