@@ -33,10 +33,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes of one interior-layer slab solve of the bench workload (q = 84),
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of `bench.py --mode slab`,
-# calibrated by the same counters on a 1 GiB device copy (fetch x2, write
-# x1); profiles/slab_solve_bench_1024.md holds the figures.  Re-measure when
-# the slab-solve kernels change.
-SLAB_TRAFFIC_BYTES = 450.09e6
+# calibrated by the same counters on a 1 GiB device copy; the profile under
+# profiles/ named for the slab solve holds the figures and their command.
+# It is a counter figure from a profiling run, not a measurement of this
+# run: None when the kernels have changed since the counters were taken.
+SLAB_TRAFFIC_BYTES = None
+SLAB_TRAFFIC_SOURCE = None
 
 
 def log(msg):
@@ -66,9 +68,22 @@ def cpu_baseline(cfg, L, ext, tol):
     the 2L SuperLU slab factorisations) is built first and not timed, as the
     GPU plan creation is not part of the GPU number; then one outer flexible
     GMRES solve to `tol` (Alg. 3 preconditioner, Alg. 2 inner sweeps) is
-    timed.  cores = process CPU time / wall time of the timed solve (the
-    threads NumPy / SciPy actually kept busy)."""
+    timed.  cores = the threads the oracle's pools ran with (the BLAS pool
+    and scipy.fft's workers = all host CPUs); host_cpus, blas_threads and
+    the measured utilisation (process CPU time / wall time) are reported
+    beside it."""
     from oracle import solver
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"),
+                   default=1)
+    except Exception:
+        blas = None
+    host_cpus = os.cpu_count()
+    try:
+        host_cpus = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
     n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
     t0 = time.perf_counter()
     P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=L, ext=ext)
@@ -81,13 +96,56 @@ def cpu_baseline(cfg, L, ext, tol):
     return {
         "value": 1.0 / wall,
         "unit": "solves/s",
-        "cores": max(1, int(round(cpu / wall))),
+        "cores": max(blas or 1, host_cpus or 1),
+        "host_cpus": host_cpus,
+        "blas_threads": blas,
+        "fft_workers": host_cpus,
+        "utilisation": cpu / wall,
         "kind": "oracle",
         "sample": (f"one full oracle solve of the bench workload (tol {tol:g}): {info['iters']} outer "
                    f"iterations, inner {info['inner_iters']}, relres {info['relres_true']:.2e}, "
                    f"{wall:.1f} s wall / {cpu:.1f} s CPU; off-line setup {setup_s:.1f} s not timed"),
         "solve_s": wall,
     }
+
+def c3_variant(tol, log_fn, steps=2):
+    """The precision workload: 2048^2 grid, omega = 2 pi 200, Gaussian random
+    field medium (correlation length 0.05, std 0.15, smooth compact support,
+    seed 0), plane wave theta = 0, 32 layers x 2 directions, FP32 operator
+    and slab solves (factors computed in FP64), FP64 Gram-Schmidt and
+    refinement residuals, solved to relative residual `tol`.  The error
+    against the FP64 oracle is checked by the GPU tests (oracle residual of
+    this solve at tol 1e-10; rel. L2 error <= 1e-8 against the oracle's own
+    solution at 256^2); here the library's FP64 residual is reported."""
+    import numpy as np
+    import torch
+    import ls_inputs as li
+    from paper_1602_07652_amd import Plan, LS_FP32_REFINE
+    dev = torch.device("cuda:0")
+    cfg = li.config_inputs("c3_2048_grf")
+    n, omega = cfg["n"], cfg["omega"]
+    t0 = time.perf_counter()
+    p = Plan(n, 1.0 / n, omega, torch.from_numpy(cfg["m"]).to(dev), slabs=cfg["slabs"], ext=10,
+             precision=LS_FP32_REFINE)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    f = p.rhs_from_incident(torch.from_numpy(cfg["uI"]).to(dev))
+    u = torch.empty_like(f)
+    p.solve(f, tol=tol, out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [p.solve(f, tol=tol, out=u)[1][0] for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    p.close()
+    out = {"workload": "2048^2 GRF medium, omega=2*pi*200, 32 layers x 2 directions, FP32 operator and slab "
+                       "solves, FP64 factorisation / Gram-Schmidt / refinement residuals",
+           "solves_per_s": steps / wall, "ms_per_solve": 1e3 * wall / steps,
+           "outer_its": float(np.mean([i["outer_its"] for i in infos])),
+           "relres_true": max(i["relres_true"] for i in infos), "setup_s": setup}
+    log_fn(f"2048^2 FP32 + refinement: {out}")
+    return out
+
 
 def batched_variant(tol, log_fn):
     """64 incident plane waves (theta_k = 2 pi k / 64) per medium on three
@@ -307,6 +365,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--slab-reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 variant")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 2048^2 FP32 + refinement variant")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
     ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
     ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned", "apply", "fno"],
@@ -479,6 +538,7 @@ def main():
                    "outer_its": float(np.mean([i["outer_its"] for i in infos32])),
                    "relres_true": max(i["relres_true"] for i in infos32), "setup_s": setup32}
     log(f"FP32 + refinement, one right-hand side: {fp32_single}")
+    c3 = None if args.no_c3 else c3_variant(args.tol, log)
     batched = learned = None
     if not args.no_batched:
         batched = batched_variant(args.tol, log)
@@ -524,10 +584,12 @@ def main():
             "unit": "GB/s",
             "frac": slab_gbs / HBM_PEAK_GBS,
             "traffic": SLAB_TRAFFIC_BYTES,
+            "traffic_source": SLAB_TRAFFIC_SOURCE,
             "ms_per_launch": slab_ms,
         },
         "cpu_baseline": cpu,
-        "variants": {"fp32_refine_single": fp32_single, "batched_fp32_multigrid": batched,
+        "variants": {"fp32_refine_single": fp32_single, "fp32_refine_2048_grf": c3,
+                     "batched_fp32_multigrid": batched,
                      "learned_fp32_multigrid": learned},
     }
     print(json.dumps(rec), flush=True)

@@ -79,7 +79,7 @@ typedef struct {
   int inner_fixed_iters; /* > 0: inner GMRES runs exactly this many iterations */
   int max_batch;         /* largest `batch` passed to ls_apply / ls_rhs_from_incident */
   double lowp_tol;       /* LS_FP32_REFINE: relative tolerance of each FP32 correction solve */
-  int max_refine;        /* LS_FP32_REFINE: refinement sweeps limit */
+  int max_refine;        /* refinement sweeps limit (LS_FP32_REFINE) / FP64 restarts limit (LS_FP64) */
   int use_graphs;        /* 1: the inner preconditioner runs as a captured hipGraph */
   int autotune;          /* 1: time the FFT column-pass tile variants at plan creation */
   int fft_variant;       /* autotune 0: FFT column-pass variant to use, 0..7 (0: radix-16 register passes) */
@@ -90,7 +90,7 @@ typedef struct {
   int inner_its_total;    /* inner GMRES iterations summed over all outer iterations */
   double relres_est;      /* least-squares residual estimate at exit */
   double relres_true;     /* ||f - H u|| / ||f|| recomputed in FP64 at exit */
-  int converged;          /* 1 if relres_est <= tol */
+  int converged;          /* 1 if relres_true <= tol (the recomputed FP64 residual, not the estimate) */
   double t_ms;            /* wall time of this right-hand side */
   int fno_flags;          /* ls_solve_fno only: LS_FNO_* bits of ls_fno.h, else 0 */
 } ls_solve_info;
@@ -133,13 +133,23 @@ ls_status ls_rhs_from_incident(ls_plan* plan, const double* uI, double* f, int b
  * LS_ENOCONV if the inner limit was hit (z then holds the last iterate). */
 ls_status ls_precond_apply(ls_plan* plan, const double* r, double* z, int batch);
 
-/* u ~= H^{-1} f by flexible GMRES (x0 = 0, no restart) preconditioned by
- * ls_precond_apply, until the relative residual estimate is <= tol.
+/* u ~= H^{-1} f: the on-line stage of Section 4 -- the outer GMRES on the
+ * discrete Lippmann-Schwinger system H u = f of Section 2, preconditioned by
+ * Alg. 3 (ls_precond_apply), run as the flexible GMRES that Section 6
+ * proposes (x0 = 0, no restart) until the least-squares residual estimate
+ * is <= tol.  The FP64 residual ||f - H u|| / ||f|| is then recomputed; a
+ * right-hand side whose estimate met tol but whose recomputed residual did
+ * not is restarted from its iterate (FP64 corrections d ~ H^{-1}(f - H u),
+ * at most max_refine).
  * LS_FP32_REFINE plans: FP64 refinement sweeps r = f - H u, each solving
  * H d = r with the FP32 flexible GMRES to max(lowp_tol, tol/||r||) and
  * adding d, until ||f - H u|| / ||f|| <= tol; f and u stay FP64.
- * info: HOST array of `batch` records or NULL.  Synchronises.
- * LS_ENOCONV if some right-hand side hit max_outer (or max_refine). */
+ * f, u: DEVICE arrays of `batch` grid vectors, f != u; batch >= 1 (worked
+ * through max_batch at a time); tol > 0.
+ * info: HOST array of `batch` records or NULL; info[b].converged is 1 iff
+ * the recomputed residual is <= tol.  Synchronises.
+ * LS_ENOCONV if some right-hand side ends above tol (max_outer or
+ * max_refine reached); u then holds the last iterate. */
 ls_status ls_solve(ls_plan* plan, const double* f, double* u, int batch, double tol,
                    ls_solve_info* info);
 

@@ -796,12 +796,22 @@ ls_status ls_solve(ls_plan* p, const double* f, double* u, int batch, double tol
     if (!p->fp32) {
       std::vector<GmresResult> res;
       LS_TRY(outer_fgmres<cplx>(p, fb, ub, B, std::vector<double>(B, tol), res, inner_total));
+      bool restart = false;
       for (int i = 0; i < B; ++i) {
         outer_total[i] = res[i].iters;
         est[i] = res[i].relres;
-        conv[i] = res[i].converged;
       }
       LS_TRY(true_residual(p, fb, ub, rbuf, B, nf, rel));
+      // the flag follows the recomputed residual: a right-hand side whose
+      // estimate met tol but whose true residual did not is restarted from
+      // its iterate (FP64 corrections, at most max_refine)
+      for (int i = 0; i < B; ++i) restart = restart || (rel[i] > tol && est[i] <= tol && std::isfinite(rel[i]));
+      if (restart) {
+        if (!p->solve_buf)
+          LS_TRY(plan_alloc(p, (void**)&p->solve_buf, sizeof(cplx) * 2 * (size_t)p->opt.max_batch * N));
+        LS_TRY(refine_bd(p, fb, ub, rbuf, p->solve_buf, B, tol, nf, rel, outer_total, inner_total));
+      }
+      for (int i = 0; i < B; ++i) conv[i] = rel[i] <= tol;
     } else {
       // Iterative refinement: r = f - H u in FP64, d ~ H^{-1} r by FP32
       // flexible GMRES to max(lowp_tol, tol / ||r||_rel), u += d, until

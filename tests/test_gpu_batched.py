@@ -104,8 +104,35 @@ def test_fp32_batched_level_steps_match_single_rhs():
         zs = host(ps.precond_apply(dev(r[k:k + 1])))[0]
         e = rel(zb[k], zs)
         banner(f"fp32 batched vs single rhs k={k} rel diff {e:.3e}")
-        assert e < 1e-4
+        assert e < 3e-5
     pb.close()
+    ps.close()
+
+
+def test_fp32_batched_precond_matches_oracle():
+    """Alg. 3 on an FP32 plan with 64 right-hand sides, against the FP64
+    oracle's Alg. 3 on sampled right-hand sides.  512^2, 8 layers (interior
+    q = 84), one inner GMRES iteration (a fixed map of r): levels 0 and 1 of
+    every slab solve have >= 256 (block, 32-right-hand-side tile) pairs and
+    run on matrix cores (k_bstep_mfma), and the top of each reduction is the
+    FP32 dense operator on matrix cores (k_top_mfma).  The difference is
+    FP32 rounding of the factors and sweeps, u32 times the local condition
+    numbers (the single-right-hand-side FP32 path is within the same bound)."""
+    from oracle import solver
+    n, B, L = 512, 64, 8
+    m, _ = li.gaussian_bumps_medium(n, seed=5)
+    p, omega = make(n, m, slabs=L, ext=10, max_batch=B, precision=1, inner_fixed_iters=1)
+    ps, _ = make(n, m, slabs=L, ext=10, max_batch=1, precision=1, inner_fixed_iters=1)
+    r = li.random_complex((B, n, n), 78)
+    z = host(p.precond_apply(dev(r)))
+    P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=L, ext=10, inner_fixed_iters=1)
+    for k in (0, 21, 42, 63):
+        zr = P.precond_apply(r[k])
+        e = rel(z[k], zr)
+        es = rel(host(ps.precond_apply(dev(r[k:k + 1])))[0], zr)
+        banner(f"fp32 batched precond k={k}: rel err vs oracle {e:.3e} (single-rhs FP32 path {es:.3e})")
+        assert e < 1e-4 and es < 1e-4
+    p.close()
     ps.close()
 
 
@@ -138,5 +165,5 @@ def test_every_fft_column_variant_matches_oracle(apply_refs, n, variant):
     e64 = rel(host(p.apply(dev(v))), ref)
     e32 = rel(host(p.apply_c64(dev(v, torch.complex64))), ref32)
     banner(f"variant {variant} n={n}: FP64 rel err {e64:.3e}, FP32 {e32:.3e}")
-    assert e64 < 1e-13 and e32 < 5e-6
+    assert e64 < 1e-13 and e32 < 1e-6
     p.close()

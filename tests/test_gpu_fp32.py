@@ -35,7 +35,10 @@ def test_fp32_operator(n, batch):
     W = kernel.kernel_samples(n, 1.0 / n, omega)
     e = rel(y, kernel.apply_H(W, m, v.astype(np.complex64).astype(np.complex128), omega))
     banner(f"fp32 apply n={n} rel err {e:.3e}")
-    assert e < 5e-6
+    # FP32 rounding of the inputs is taken out (the reference uses the
+    # rounded v); what is left is the FP32 FFT convolution, ~ u32 log2(P)
+    # ~ 6e-8 * 12 relative: 1e-6 is ~ 15x that
+    assert e < 1e-6
     # the FP64 operator of an FP32 plan stays FP64
     y64 = host(p.apply(dev(v)))
     assert rel(y64, kernel.apply_H(W, m, v, omega)) < 1e-13
@@ -81,16 +84,44 @@ def test_fp32_refined_solve_reaches_fp64_accuracy():
     p.close()
 
 
+def test_fp32_refined_solution_error_vs_oracle_solution():
+    """The precision workload's target on a grid the oracle solves in
+    seconds: a Gaussian-random-field medium (correlation length 0.05, std
+    0.15, smooth compact support) at 256^2, omega = 2 pi 25.6 (10 points per
+    wavelength), 4 layers.  The FP32 + FP64-refinement solution at tol 1e-10
+    against the oracle's own FP64 flexible-GMRES solution at tol 1e-12:
+    relative L2 error <= 1e-8.  Both solve H u = f; the error bound is
+    kappa(H) times the residuals (1e-10 and 1e-12), so the margin to 1e-8
+    covers kappa up to ~100."""
+    n = 256
+    omega = 2 * np.pi * 25.6
+    m = li.gaussian_random_field_medium(n, seed=0)
+    uI = li.plane_wave(n, omega, 0.0)
+    p, _ = plan32(n, 25.6, m, slabs=4, ext=10)
+    f = p.rhs_from_incident(dev(uI))
+    u, info = p.solve(f, tol=1e-10)
+    P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=4, ext=10)
+    u_ref, oinfo = P.solve(P.rhs(uI), tol=1e-12)
+    e = rel(host(u), u_ref)
+    banner(f"fp32+refine 256^2 GRF: {info[0]}; oracle {oinfo['iters']} outer, relres "
+           f"{oinfo['relres_true']:.2e}; rel L2 error vs oracle solution {e:.3e}")
+    assert oinfo["relres_true"] < 1e-11
+    assert info[0]["converged"] == 1 and info[0]["relres_true"] <= 1e-10
+    assert e <= 1e-8
+    p.close()
+
+
 @pytest.mark.parametrize("name", ["c3_2048_grf"])
 def test_fp32_refined_solve_full_size_residual(name):
-    """2048^2 Gaussian-random-field workload: the oracle's FP64 residual of
-    the GPU solution is below the tolerance."""
+    """2048^2 Gaussian-random-field workload at tol 1e-10: the oracle's FP64
+    residual of the GPU solution is at most the tolerance (the library's
+    own FP64 residual and the oracle's agree to rounding)."""
     cfg = li.config_inputs(name)
     n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
     p, _ = plan32(n, omega / (2 * np.pi), m, slabs=cfg["slabs"], ext=10)
     uI = cfg["uI"]
     f = p.rhs_from_incident(dev(uI))
-    u, info = p.solve(f, tol=1e-8)
+    u, info = p.solve(f, tol=1e-10)
     banner(f"fp32+refine {name} info={info[0]}")
     W = kernel.kernel_samples(n, 1.0 / n, omega)
     Gh = kernel.circulant_spectrum(W)
@@ -99,5 +130,6 @@ def test_fp32_refined_solve_full_size_residual(name):
     r = f_ref - kernel.apply_H(W, m, uh, omega, Gh)
     res = np.linalg.norm(r) / np.linalg.norm(f_ref)
     banner(f"oracle FP64 residual of the GPU solution {res:.3e}")
-    assert info[0]["converged"] == 1 and res < 1.5e-8
+    assert info[0]["converged"] == 1 and res <= 1e-10
+    assert abs(res - info[0]["relres_true"]) <= 1e-3 * res
     p.close()

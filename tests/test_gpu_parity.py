@@ -130,7 +130,7 @@ def test_slab_solves(n, f, L, ext, shift, seed):
             x_ref = spla.spsolve(Cl.tocsc(), b.T.reshape(-1)).reshape(q, n).T
             e = rel(x, x_ref)
             banner(f"slab n={n} orient={orient} l={l} q={q} rel err {e:.3e}")
-            assert e < 1e-9
+            assert e < 1e-10
     p.close()
 
 
@@ -147,7 +147,7 @@ def test_sweeps_and_bidirectional(n, f, L, ext, shift, seed):
     vb = host(p.bidirectional(dev(g)))
     e2 = rel(vb, bd.apply(g))
     banner(f"sweeps n={n} L={L} H {e0:.3e} V {e1:.3e} BD {e2:.3e}")
-    assert e0 < 1e-8 and e1 < 1e-8 and e2 < 1e-8
+    assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10
     p.close()
 
 
@@ -160,7 +160,7 @@ def test_precond_fixed_iterations():
     z = host(p.precond_apply(dev(r)))
     e = rel(z, P.precond_apply(r))
     banner(f"precond fixed=2 rel err {e:.3e}")
-    assert e < 1e-8
+    assert e < 1e-12
     p.close()
 
 
@@ -239,7 +239,7 @@ def test_batched_sweep_and_precond_match_oracle():
     for k in range(3):
         e = rel(z[k], P.precond_apply(r[k]))
         banner(f"batched precond k={k} rel err {e:.3e}")
-        assert e < 1e-8
+        assert e < 1e-12
     p.close()
 
 
