@@ -217,6 +217,21 @@ ls_status ls_apply_c64(ls_plan* plan, const float* v, float* Hv, int batch);
  * ls_sweep, ls_bidirectional and ls_precond_apply. */
 ls_status ls_slab_solve(ls_plan* plan, int orient, int slab, const double* b, double* x);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * slab solve as ls_slab_solve, same arguments, layout and results (the same
+ * kernels), but the call allocates nothing.  Its scratch -- the eliminated
+ * right-hand sides, plus the FP32 copies of b and x on LS_FP32_REFINE plans
+ * or the copy of b when b == x -- lives in one static device array of
+ * ls_noalloc_scratch_bytes() bytes (6 MiB, enough for every slab a plan can
+ * have: n * q <= 2048 * 96) that each GPU holds until the process ends; its
+ * device address is taken once per device by ls_plan_create.  Every call on
+ * one GPU shares that array, so calls that overlap on one GPU (other
+ * streams, other host threads) race: serialise them.  A slab larger than
+ * the array gives LS_EINVAL; the plan's own scratch is not touched. */
+ls_status ls_slab_solve_noalloc(ls_plan* plan, int orient, int slab, const double* b, double* x);
+size_t ls_noalloc_scratch_bytes(void);
+
 /* v = Preconditioner(g) (Alg. 1) on horizontal (orient 0) or vertical
  * (orient 1) layers; g, v grid vectors, g != v. */
 ls_status ls_sweep(ls_plan* plan, int orient, const double* g, double* v);

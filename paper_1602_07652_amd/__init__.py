@@ -92,6 +92,8 @@ def lib():
         "ls_stencil_C": (_i, [_vp, _vp, _vp, _i]),
         "ls_slab_info": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
         "ls_slab_solve": (_i, [_vp, _i, _i, _vp, _vp]),
+        "ls_slab_solve_noalloc": (_i, [_vp, _i, _i, _vp, _vp]),
+        "ls_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "ls_sweep": (_i, [_vp, _i, _vp, _vp]),
         "ls_bidirectional": (_i, [_vp, _vp, _vp]),
         "ls_solve_multi": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -279,6 +281,16 @@ class Plan:
         q = z1 - z0 + 1
         out = torch.empty_like(b) if out is None else out
         _check("ls_slab_solve", lib().ls_slab_solve(
+            self.handle, orient, slab, _ptr(b, self.n * q, "b"), _ptr(out, self.n * q, "x")))
+        return out
+
+    def slab_solve_noalloc(self, orient, slab, b, out=None):
+        """ls_slab_solve_noalloc: ls_slab_solve with its scratch in the
+        library's static device array (the call allocates nothing)."""
+        a_, b_, z0, z1 = self.slab_info(orient, slab)
+        q = z1 - z0 + 1
+        out = torch.empty_like(b) if out is None else out
+        _check("ls_slab_solve_noalloc", lib().ls_slab_solve_noalloc(
             self.handle, orient, slab, _ptr(b, self.n * q, "b"), _ptr(out, self.n * q, "x")))
         return out
 

@@ -586,6 +586,12 @@ ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const dou
     delete p;
     return LS_EDEVICE;
   }
+  // the allocation-free entry point's static scratch: its device address on
+  // this device, taken once with the device current
+  if (ls_status ss = static_scratch_init(p->device); ss != LS_OK) {
+    delete p;
+    return ss;
+  }
   if (hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
       p->cus < 1)
     p->cus = 256;
@@ -709,6 +715,19 @@ ls_status ls_slab_solve(ls_plan* p, int orient, int slab, const double* b, doubl
   }
   return slab_solve(p, s, bb, xx, 1);
 }
+
+ls_status ls_slab_solve_noalloc(ls_plan* p, int orient, int slab, const double* b, double* x) {
+  if (!p || !b || !x || orient < 0 || orient > 1 || slab < 0 || slab >= p->L ||
+      p->slabs[orient].empty()) {
+    ls_set_error("ls_slab_solve_noalloc: bad arguments");
+    return LS_EINVAL;
+  }
+  DeviceGuard dg(p->device);
+  return slab_solve_noalloc(p, p->slabs[orient][slab], reinterpret_cast<const cplx*>(b),
+                            reinterpret_cast<cplx*>(x));
+}
+
+size_t ls_noalloc_scratch_bytes(void) { return static_scratch_bytes(); }
 
 ls_status ls_sweep(ls_plan* p, int orient, const double* g, double* v) {
   if (!p || !g || !v || g == v || orient < 0 || orient > 1 || p->slabs[orient].empty()) {

@@ -269,6 +269,11 @@ ls_status sweep_apply(ls_plan* p, int orient, const cplx* g, cplx* v, bool accum
 ls_status sweep_apply(ls_plan* p, int orient, const fcplx* g, fcplx* v, bool accumulate, int B = 1);
 ls_status bidirectional_apply(ls_plan* p, const cplx* g, cplx* v, int B = 1);
 ls_status bidirectional_apply(ls_plan* p, const fcplx* g, fcplx* v, int B = 1);
+// allocation-free single-right-hand-side slab solve (scratch in a static
+// device array, set up once per device by static_scratch_init)
+ls_status static_scratch_init(int device);
+size_t static_scratch_bytes();
+ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x);
 // blas.hip (each for T = cplx and T = fcplx; inner products in FP64)
 // Batched forms act on B right-hand sides stored [B][N] (vector i of a
 // Krylov set at V + i*stride, stride >= B*N); coefficient arrays are [B][k].

@@ -37,6 +37,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace {
 
@@ -1963,3 +1964,87 @@ static ls_status bidir_t(ls_plan* p, const T* g, T* v, int B) {
 
 ls_status bidirectional_apply(ls_plan* p, const cplx* g, cplx* v, int B) { return bidir_t<cplx>(p, g, v, B); }
 ls_status bidirectional_apply(ls_plan* p, const fcplx* g, fcplx* v, int B) { return bidir_t<fcplx>(p, g, v, B); }
+
+// ------------------------------------------------- allocation-free slab solve
+// The single-right-hand-side slab solve with its scratch -- the eliminated
+// right-hand sides t, and the copies of b and x an FP32 plan or an in-place
+// call needs -- in a file-scope device array instead of plan memory, for
+// callers that cannot allocate (graph capture, serving loops).  Each GPU
+// holds its own copy of the array for the life of the process; host code
+// never uses the array's name, only the device address taken once per
+// device by static_scratch_init (at plan creation, with the device current).
+// Calls on one GPU share the array: they must not overlap.
+constexpr size_t kScratchBytes = (size_t)6 << 20;  // 2 * n * q * 16 B at n = 2048, q = 96
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+namespace {
+constexpr int kScratchDevices = 64;
+void* g_scratch_dev[kScratchDevices];
+std::mutex g_scratch_mu;
+
+__global__ void k_up_copy(const fcplx* __restrict__ a, cplx* __restrict__ b, size_t cnt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = cmk((double)a[i].x, (double)a[i].y);
+}
+}  // namespace
+
+size_t static_scratch_bytes() { return kScratchBytes; }
+
+ls_status static_scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) {
+    ls_set_error("static scratch: device index out of range");
+    return LS_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return LS_OK;
+  void* ptr = nullptr;
+  LS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) {
+    ls_set_error("static scratch: hipGetSymbolAddress returned a null address");
+    return LS_EDEVICE;
+  }
+  g_scratch_dev[device] = ptr;
+  return LS_OK;
+}
+
+ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (p->device >= 0 && p->device < kScratchDevices) base = g_scratch_dev[p->device];
+  }
+  if (!base) {
+    ls_set_error("ls_slab_solve_noalloc: static scratch of this device not set up");
+    return LS_EDEVICE;
+  }
+  const size_t cnt = (size_t)p->n * s.q;
+  const unsigned blocks = (unsigned)((cnt + 255) / 256);
+  if (p->fp32) {
+    if (3 * cnt * sizeof(fcplx) > kScratchBytes) {
+      ls_set_error("ls_slab_solve_noalloc: slab of " + std::to_string(cnt) + " unknowns exceeds the " +
+                   std::to_string(kScratchBytes) + "-byte static scratch");
+      return LS_EINVAL;
+    }
+    fcplx* gi = reinterpret_cast<fcplx*>(base);
+    fcplx* yo = gi + cnt;
+    fcplx* t = yo + cnt;
+    k_down_copy<<<blocks, 256, 0, p->stream>>>(b, gi, cnt);
+    LS_TRY(solve_rows<fcplx>(p, s, s.fac32, s.coef32, s.top32, gi, t, yo));
+    k_up_copy<<<blocks, 256, 0, p->stream>>>(yo, x, cnt);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+  }
+  const bool inplace = b == x;
+  if ((inplace ? 2 : 1) * cnt * sizeof(cplx) > kScratchBytes) {
+    ls_set_error("ls_slab_solve_noalloc: slab of " + std::to_string(cnt) + " unknowns exceeds the " +
+                 std::to_string(kScratchBytes) + "-byte static scratch");
+    return LS_EINVAL;
+  }
+  cplx* t = reinterpret_cast<cplx*>(base);
+  const cplx* g = b;
+  if (inplace) {
+    cplx* gi = t + cnt;
+    LS_HIP(hipMemcpyAsync(gi, b, cnt * sizeof(cplx), hipMemcpyDeviceToDevice, p->stream));
+    g = gi;
+  }
+  return solve_rows<cplx>(p, s, s.fac, s.coef, s.top, g, t, x);
+}
