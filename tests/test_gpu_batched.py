@@ -131,7 +131,8 @@ def test_fp32_batched_precond_matches_oracle():
         e = rel(z[k], zr)
         es = rel(host(ps.precond_apply(dev(r[k:k + 1])))[0], zr)
         banner(f"fp32 batched precond k={k}: rel err vs oracle {e:.3e} (single-rhs FP32 path {es:.3e})")
-        assert e < 1e-4 and es < 1e-4
+        # measured 3.7e-6 - 4.0e-6 on both paths
+        assert e < 4e-5 and es < 4e-5
     p.close()
     ps.close()
 

@@ -61,12 +61,14 @@ def test_fp32_slabs_and_sweeps():
         x_ref = spla.spsolve(Cl.tocsc(), b.T.reshape(-1)).reshape(q, n).T
         e = rel(x, x_ref)
         banner(f"fp32 slab l={l} rel err {e:.3e}")
-        assert e < 1e-4
+        # u32 = 6e-8 times the slab's condition (measured 2.1e-7 - 2.2e-7)
+        assert e < 3e-6
     bd = slabs.BiDirectional(al, be, m, omega, L, ext)
     g = li.random_complex((n, n), 3)
     e = rel(host(p.bidirectional(dev(g))), bd.apply(g))
     banner(f"fp32 bidirectional rel err {e:.3e}")
-    assert e < 1e-4
+    # Alg. 2 chains 2L - 1 slab solves per direction and a residual (measured 4.2e-6)
+    assert e < 5e-5
     p.close()
 
 

@@ -275,7 +275,8 @@ def test_slab_solve_at_bench_shape(bench_shape, orient, l):
     x_ref = spla.spsolve(Cl.tocsc(), b.T.reshape(-1)).reshape(q, n).T
     e = rel(x, x_ref)
     banner(f"bench-shape slab orient={orient} l={l} q={q} rel err {e:.3e}")
-    assert e < 1e-9
+    # both sides carry ~ eps * cond(C^l) at q = 84 (measured 2.8e-11 - 3.7e-11)
+    assert e < 4e-10
 
 
 def test_zero_right_hand_side_gives_zero():
