@@ -147,6 +147,93 @@ def c3_variant(tol, log_fn, steps=2):
     return out
 
 
+def trend_variant(log_fn, sizes=(256, 512, 1024, 2048), shifts_at=1024, shifts=(0.0, 1.0, 2.0, 4.0),
+                  waves=8):
+    """Section 5.1's comparison of the one-directional (Alg. 1, PT) and the
+    bi-directional (Alg. 2, BD) preconditioners on the sparsified system
+    C v = g alone: GMRES to 1e-6 with either preconditioner, for a focusing
+    (+0.3) and a defocusing (-0.3) smooth Gaussian perturbation (width 0.15),
+    n = 256 ... 2048, omega = 2 pi n / 10 (10 points per wavelength),
+    L = n / 64 layers extended by 10 lines, `waves` incident plane waves
+    theta_k = 2 pi k / waves solved together, g = A f, f = -omega^2 G (m u_I).
+    Then the complex shift of Section 3.3 (omega^2 sigma = shift_c omega in
+    the cut-off region) at one size.  Returns rows of mean / max iterations
+    and ms per right-hand side."""
+    import numpy as np
+    import torch
+    import ls_inputs as li
+    from paper_1602_07652_amd import Plan, LS_PREC_BD, LS_PREC_PT1
+    dev = torch.device("cuda:0")
+    rows = []
+    cases = [(n, sgn, 0.0) for n in sizes for sgn in (1.0, -1.0)]
+    cases += [(shifts_at, sgn, sh) for sh in shifts if sh != 0.0 for sgn in (1.0, -1.0)]
+    for n, sgn, sh in cases:
+        omega = 2 * np.pi * n / 10
+        # the Krylov basis of a 2048^2 run that does not converge is 2 x max_its
+        # grid vectors per wave: fewer waves and iterations there
+        nw, max_its = (waves, 300) if n < 2048 else (2, 250)
+        m = torch.from_numpy(li.smooth_bump_medium(n, 0.3 * sgn)).to(dev)
+        uI = torch.from_numpy(np.stack([li.plane_wave(n, omega, 2 * np.pi * k / nw)
+                                        for k in range(nw)])).to(dev)
+        for name, pc in (("PT", LS_PREC_PT1), ("BD", LS_PREC_BD)):
+            p = Plan(n, 1.0 / n, omega, m, slabs=n // 64, ext=10, shift_c=sh, precond=pc, max_batch=nw)
+            g = p.stencil_A(p.rhs_from_incident(uI))
+            v = torch.empty_like(g)
+            reps = 2 if n < 2048 else 1      # warm-up run (graphs) below 2048^2
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = p.sparse_solve(g, tol=1e-6, max_its=max_its, out=v, allow_noconv=True)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+            its = [i["outer_its"] for i in info]
+            row = {"n": n, "omega": omega, "L": n // 64, "medium": "+" if sgn > 0 else "-", "shift_c": sh,
+                   "precond": name, "its_mean": float(np.mean(its)), "its_max": int(max(its)),
+                   "converged": all(i["converged"] for i in info),
+                   "relres_true_max": max(i["relres_true"] for i in info),
+                   "waves": nw, "max_its": max_its, "ms_per_rhs": 1e3 * wall / nw}
+            rows.append(row)
+            log_fn(f"trend {row}")
+            p.close()
+            del g, v
+        del m, uI
+        torch.cuda.empty_cache()
+    return rows
+
+
+def setup_variant(log_fn, sizes=(256, 512, 1024, 2048)):
+    """The off-line stage (Section 4.1) timed by step, n = 256 ... 2048:
+    8-bump medium (seed 1), omega = 2 pi n / 10, L = n / 64 layers, FP64,
+    one plan per size created twice (the second creation is timed, so code
+    loading is not), then a plan for a second medium of the same (n, h,
+    omega) made with ls_plan_create_like, which copies the spectrum and the
+    stencils instead of recomputing them."""
+    import numpy as np
+    import torch
+    import ls_inputs as li
+    from paper_1602_07652_amd import Plan
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in sizes:
+        omega = 2 * np.pi * n / 10
+        m1 = torch.from_numpy(li.gaussian_bumps_medium(n, seed=1)[0]).to(dev)
+        m2 = torch.from_numpy(li.gaussian_bumps_medium(n, seed=2)[0]).to(dev)
+        kw = dict(slabs=n // 64, ext=10)
+        Plan(n, 1.0 / n, omega, m1, **kw).close()
+        torch.cuda.synchronize()
+        p = Plan(n, 1.0 / n, omega, m1, **kw)
+        full = p.timings()
+        q = Plan(n, 1.0 / n, omega, m2, like=p, **kw)
+        like = q.timings()
+        row = {"n": n, "N": n * n, "full_ms": full, "like_ms": like}
+        rows.append(row)
+        log_fn(f"setup n={n}: full {full['total']:.1f} ms, like {like['total']:.1f} ms; {full}")
+        p.close()
+        q.close()
+        torch.cuda.empty_cache()
+    return rows
+
+
 def batched_variant(tol, log_fn):
     """64 incident plane waves (theta_k = 2 pi k / 64) per medium on three
     media of different size (256^2, 512^2, 1024^2, 8 Gaussian bumps seeds 1-3,
@@ -368,12 +455,15 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 2048^2 FP32 + refinement variant")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
     ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
-    ap.add_argument("--mode", default="full", choices=["full", "slab", "copy", "batched", "learned", "apply", "fno"],
+    ap.add_argument("--mode", default="full",
+                    choices=["full", "slab", "copy", "batched", "learned", "apply", "fno", "trend", "setup"],
                     help="profiling sub-runs: slab = only slab solves of the bench workload's "
                          "interior layer; copy = 1 GiB device copies (counter calibration); "
                          "batched = only the multi-grid variant; learned = only the learned-form "
                          "variant; apply = only ls_apply of the bench workload at batch 8; "
-                         "fno = only the network's training step and inference")
+                         "fno = only the network's training step and inference; trend = PT vs BD "
+                         "iteration counts on the sparsified system; setup = off-line stage timed by "
+                         "step from 256^2 to 2048^2")
     ap.add_argument("--fft-variant", type=int, default=None,
                     help="apply mode: force this FFT column-pass variant (no autotuning) and time the "
                          "FP32 operator of the same plan too")
@@ -401,6 +491,12 @@ def main():
         return
     if args.mode == "batched":
         print(json.dumps({"mode": "batched", "batched": batched_variant(args.tol, log)}))
+        return
+    if args.mode == "trend":
+        print(json.dumps({"mode": "trend", "rows": trend_variant(log)}))
+        return
+    if args.mode == "setup":
+        print(json.dumps({"mode": "setup", "rows": setup_variant(log)}))
         return
     from paper_1602_07652_amd.fno_train import DEFAULT_WEIGHTS
     weights = args.weights or DEFAULT_WEIGHTS

@@ -116,6 +116,28 @@ void ls_options_default(ls_options* opt);
 ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const double* m,
                          const ls_options* opt, void* stream);
 
+/* The off-line stage for another medium on the same grid and frequency:
+ * like ls_plan_create with (n, h, omega) taken from src, but the kernel
+ * samples, the spectrum and the stencils -- which depend only on (n, h,
+ * omega) (Section 2) -- are copied from src instead of recomputed, and
+ * src's autotuned FFT variants are reused (when both plans autotune and
+ * have the same precision).  Only the medium-dependent part runs: slab
+ * assembly and factorisation (Section 4.1, done once per medium).  src must
+ * live on the current device; it is only read and may be destroyed
+ * afterwards.  m, opt, stream as for ls_plan_create. */
+ls_status ls_plan_create_like(ls_plan** out, const ls_plan* src, const double* m, const ls_options* opt,
+                              void* stream);
+
+/* Wall times in ms of the off-line stage of this plan (Section 4.1), by
+ * step: ms[0] kernel samples and circulant embedding, ms[1] stencils,
+ * ms[2] spectrum (2-D FFT and quarter extraction; for ls_plan_create_like
+ * the copies from the source plan), ms[3] slab assembly, ms[4] slab
+ * factorisation, ms[5] top-of-reduction operators, ms[6] FFT autotuning,
+ * ms[7] the whole plan creation.  Steps are timed with the stream drained
+ * between them.  count <= 8 entries are written (more are zeroed).  HOST
+ * array. */
+ls_status ls_plan_timings(const ls_plan* plan, double* ms, int count);
+
 /* Frees the plan (synchronises its stream first).  NULL is accepted. */
 ls_status ls_plan_destroy(ls_plan* plan);
 
@@ -132,6 +154,21 @@ ls_status ls_rhs_from_incident(ls_plan* plan, const double* uI, double* f, int b
  * (or after inner_fixed_iters iterations).  Synchronises.  Returns
  * LS_ENOCONV if the inner limit was hit (z then holds the last iterate). */
 ls_status ls_precond_apply(ls_plan* plan, const double* r, double* z, int batch);
+
+/* v ~= C^{-1} g: the sparsified system alone, solved by GMRES (x0 = 0, no
+ * restart) right-preconditioned by opt.precond -- Alg. 2 (LS_PREC_BD), Alg. 1
+ * one direction (LS_PREC_PT1) or none -- until the least-squares residual
+ * estimate is <= tol or after max_its iterations.  This is the solve whose
+ * iteration counts and times Section 5.1 compares for the one-directional
+ * and bi-directional preconditioners (its Table 2, tol 1e-6).  g, v: DEVICE
+ * arrays of `batch` grid vectors, g != v.  info: HOST array of `batch`
+ * records or NULL: outer_its = iterations, relres_est = the estimate,
+ * relres_true = ||g - C v|| / ||g|| recomputed in FP64, converged = the
+ * estimate met tol.  FP32 plans run the iteration in FP32 (inner products
+ * in FP64).  Synchronises.  LS_ENOCONV if some right-hand side hit max_its
+ * (v then holds the last iterate). */
+ls_status ls_sparse_solve(ls_plan* plan, const double* g, double* v, int batch, double tol, int max_its,
+                          ls_solve_info* info);
 
 /* u ~= H^{-1} f: the on-line stage of Section 4 -- the outer GMRES on the
  * discrete Lippmann-Schwinger system H u = f of Section 2, preconditioned by

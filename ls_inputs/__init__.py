@@ -23,6 +23,7 @@ __all__ = [
     "gaussian_disk_medium",
     "gaussian_bumps_medium",
     "gaussian_random_field_medium",
+    "smooth_bump_medium",
     "disk_medium",
     "plane_wave",
     "random_complex",
@@ -93,6 +94,16 @@ def gaussian_random_field_medium(n: int, seed: int, corr_len=0.05, std=0.15,
     tau = np.clip((r - r_in) / (r_out - r_in), 0.0, 1.0)
     cut = 1.0 - 3.0 * tau**2 + 2.0 * tau**3
     return field * cut
+
+
+def smooth_bump_medium(n: int, amp: float, width: float = 0.15, centre=(0.5, 0.5)):
+    """One smooth Gaussian perturbation amp * exp(-|x - centre|^2 / (2 width^2)):
+    a focusing (amp > 0) or defocusing (amp < 0) medium, the stand-in for the
+    positive and negative smooth perturbations the paper's Section 5.1
+    compares (shown there only as a picture)."""
+    X, Z = grid_coords(n)
+    r2 = (X - centre[0]) ** 2 + (Z - centre[1]) ** 2
+    return amp * np.exp(-r2 / (2.0 * width**2))
 
 
 def disk_medium(n: int, contrast: float, radius: float, centre=(0.5, 0.5)):

@@ -77,11 +77,14 @@ def lib():
         "ls_options_default": (None, [ctypes.POINTER(Options)]),
         "ls_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _vp, ctypes.POINTER(Options), _vp]),
         "ls_plan_destroy": (_i, [_vp]),
+        "ls_plan_create_like": (_i, [ctypes.POINTER(_vp), _vp, _vp, ctypes.POINTER(Options), _vp]),
+        "ls_plan_timings": (_i, [_vp, ctypes.POINTER(_d), _i]),
         "ls_apply": (_i, [_vp, _vp, _vp, _i]),
         "ls_apply_c64": (_i, [_vp, _vp, _vp, _i]),
         "ls_rhs_from_incident": (_i, [_vp, _vp, _vp, _i]),
         "ls_precond_apply": (_i, [_vp, _vp, _vp, _i]),
         "ls_solve": (_i, [_vp, _vp, _vp, _i, _d, ctypes.POINTER(SolveInfo)]),
+        "ls_sparse_solve": (_i, [_vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(SolveInfo)]),
         "ls_status_str": (ctypes.c_char_p, [_i]),
         "ls_last_error": (ctypes.c_char_p, []),
         "ls_plan_dims": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -156,16 +159,25 @@ class Plan:
     arguments set ls_options fields.  The plan uses the current torch stream.
     """
 
-    def __init__(self, n: int, h: float, omega: float, m: torch.Tensor, **opts):
+    def __init__(self, n: int, h: float, omega: float, m: torch.Tensor, like=None, **opts):
+        """like: an existing Plan of the same (n, h, omega) whose spectrum and
+        stencils are reused (ls_plan_create_like)."""
         self.n, self.h, self.omega = int(n), float(h), float(omega)
         self.options = default_options(**opts)
         self._m = m.contiguous()
         self.stream = torch.cuda.current_stream(m.device)
         handle = ctypes.c_void_p()
-        _check("ls_plan_create", lib().ls_plan_create(
-            ctypes.byref(handle), self.n, self.h, self.omega,
-            _ptr(self._m, n * n, "m", torch.float64), ctypes.byref(self.options),
-            ctypes.c_void_p(self.stream.cuda_stream)))
+        if like is not None:
+            if (like.n, like.h, like.omega) != (self.n, self.h, self.omega):
+                raise ValueError("like: the source plan has another (n, h, omega)")
+            _check("ls_plan_create_like", lib().ls_plan_create_like(
+                ctypes.byref(handle), like.handle, _ptr(self._m, n * n, "m", torch.float64),
+                ctypes.byref(self.options), ctypes.c_void_p(self.stream.cuda_stream)))
+        else:
+            _check("ls_plan_create", lib().ls_plan_create(
+                ctypes.byref(handle), self.n, self.h, self.omega,
+                _ptr(self._m, n * n, "m", torch.float64), ctypes.byref(self.options),
+                ctypes.c_void_p(self.stream.cuda_stream)))
         self.handle = handle
         P, L, ss = _i(), _i(), _i()
         _check("ls_plan_dims", lib().ls_plan_dims(handle, ctypes.byref(P), ctypes.byref(L), ctypes.byref(ss)))
@@ -235,6 +247,18 @@ class Plan:
             _check("ls_solve", code)
         return out, [i.as_dict() for i in infos]
 
+    def sparse_solve(self, g, tol=1e-6, max_its=200, out=None, allow_noconv=False):
+        """ls_sparse_solve: GMRES on C v = g with the plan's inner preconditioner."""
+        b = self._batch(g)
+        out = torch.empty_like(g) if out is None else out
+        N = self.n * self.n * b
+        infos = (SolveInfo * b)()
+        code = lib().ls_sparse_solve(self.handle, _ptr(g, N, "g"), _ptr(out, N, "v"), b, float(tol),
+                                     int(max_its), infos)
+        if not (allow_noconv and code == 4):
+            _check("ls_sparse_solve", code)
+        return out, [i.as_dict() for i in infos]
+
     def kernel_samples(self):
         W = 2 * self.n - 1
         out = torch.empty((W, W), dtype=torch.complex128, device=self.device)
@@ -270,6 +294,14 @@ class Plan:
         N = self.n * self.n * b
         _check("ls_stencil_C", lib().ls_stencil_C(self.handle, _ptr(v, N, "v"), _ptr(out, N, "y"), b))
         return out
+
+    STAGES = ("samples", "stencils", "spectrum", "assembly", "factorisation", "top", "autotune", "total")
+
+    def timings(self):
+        """ls_plan_timings: wall ms of the off-line stage by step."""
+        ms = (_d * 8)()
+        _check("ls_plan_timings", lib().ls_plan_timings(self.handle, ms, 8))
+        return dict(zip(self.STAGES, list(ms)))
 
     def slab_info(self, orient, slab):
         lims = (_i * 4)()

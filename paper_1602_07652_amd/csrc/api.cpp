@@ -307,6 +307,11 @@ bool valid_opts(const ls_options& o) {
 
 void ls_set_error(const std::string& msg) { g_last_error = msg; }
 
+double plan_clock_ms(ls_plan* p) {
+  (void)hipStreamSynchronize(p->stream);
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 ls_status plan_alloc(ls_plan* p, void** ptr, size_t bytes) {
   *ptr = nullptr;
   if (bytes == 0) bytes = 16;
@@ -505,8 +510,13 @@ ls_status ls_plan_destroy(ls_plan* p) {
   return LS_OK;
 }
 
-static ls_status create_impl(ls_plan* p, const double* m) {
+// The off-line stage (Section 4.1).  With src, a plan of the same (n, h,
+// omega) -- whose kernel samples, spectrum and stencils do not depend on the
+// medium -- the spectrum and stencil tables are copied from it instead of
+// recomputed, and its autotuned FFT variants are reused.
+static ls_status create_impl(ls_plan* p, const double* m, const ls_plan* src) {
   const int n = p->n;
+  const double t_start = plan_clock_ms(p);
   LS_TRY(plan_alloc(p, (void**)&p->m, sizeof(double) * n * n));
   LS_HIP(hipMemcpyAsync(p->m, m, sizeof(double) * n * n, hipMemcpyDeviceToDevice, p->stream));
   LS_TRY(fft_setup_twiddles(p));
@@ -522,29 +532,68 @@ static ls_status create_impl(ls_plan* p, const double* m) {
     LS_TRY(plan_alloc(p, (void**)&p->f32.fft_work, sizeof(fcplx) * (size_t)p->opt.max_batch * n * p->P));
     LS_TRY(plan_alloc(p, (void**)&p->vtmp32, sizeof(fcplx) * (size_t)3 * n * n * p->opt.max_batch));
   }
-  {
+  if (src) {
+    const size_t ss = (size_t)p->spec_side * p->spec_side;
+    LS_HIP(hipMemcpyAsync(p->spec, src->spec, sizeof(cplx) * ss, hipMemcpyDeviceToDevice, p->stream));
+    LS_HIP(hipMemcpyAsync(p->stencil_d, src->stencil_d, sizeof(cplx) * 324, hipMemcpyDeviceToDevice, p->stream));
+    std::memcpy(p->alpha_h, src->alpha_h, sizeof(p->alpha_h));
+    std::memcpy(p->beta_h, src->beta_h, sizeof(p->beta_h));
+    if (p->fp32) {
+      LS_TRY(stencils_to_f32(p));
+      LS_TRY(spectrum_to_f32(p));
+    }
+    p->stage_ms[2] = plan_clock_ms(p) - t_start;
+  } else {
     cplx* circ = nullptr;
     LS_HIP(hipMalloc(&circ, sizeof(cplx) * (size_t)p->P * p->P));
+    double t0 = plan_clock_ms(p), t1 = t0, t2 = t0;
     ls_status s = launch_circulant(p, circ);
-    if (s == LS_OK) s = stencils_build(p, circ);
+    if (s == LS_OK) {
+      t1 = plan_clock_ms(p);
+      s = stencils_build(p, circ);
+    }
     if (s == LS_OK && p->fp32) s = stencils_to_f32(p);
-    if (s == LS_OK) s = fft2_full_forward(p, circ);
+    if (s == LS_OK) {
+      t2 = plan_clock_ms(p);
+      s = fft2_full_forward(p, circ);
+    }
     if (s == LS_OK) s = spectrum_extract(p, circ);
     if (s == LS_OK && hipStreamSynchronize(p->stream) != hipSuccess) s = LS_EDEVICE;
     (void)hipFree(circ);
     if (s != LS_OK) return s;
+    const double t3 = plan_clock_ms(p);
+    p->stage_ms[0] = t1 - t0;
+    p->stage_ms[1] = t2 - t1;
+    p->stage_ms[2] = t3 - t2;
   }
   LS_TRY(plan_alloc(p, (void**)&p->fft_work, sizeof(cplx) * (size_t)p->opt.max_batch * n * p->P));
   LS_TRY(plan_alloc(p, (void**)&p->vtmp, sizeof(cplx) * (size_t)3 * n * n * p->opt.max_batch));
   if (p->opt.precond != LS_PREC_NONE) LS_TRY(slabs_build(p));
   p->col_variant64 = p->col_variant32 = p->opt.fft_variant;
-  if (p->opt.autotune) LS_TRY(fft_autotune(p));
+  const double t_tune = plan_clock_ms(p);
+  bool tuned = false;
+  if (p->opt.autotune) {
+    if (src && src->opt.autotune && src->fp32 == p->fp32) {
+      p->col_variant64 = src->col_variant64;
+      p->col_variant32 = src->col_variant32;
+      std::memcpy(p->tune_ms64, src->tune_ms64, sizeof(p->tune_ms64));
+      std::memcpy(p->tune_ms32, src->tune_ms32, sizeof(p->tune_ms32));
+    } else {
+      LS_TRY(fft_autotune(p));
+      tuned = true;
+    }
+  }
   LS_HIP(hipStreamSynchronize(p->stream));
+  const double t_end = plan_clock_ms(p);
+  p->stage_ms[6] = tuned ? t_end - t_tune : 0.0;
+  p->stage_ms[7] = t_end - t_start;
   return LS_OK;
 }
 
-ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const double* m,
-                         const ls_options* opt, void* stream) {
+// Validates the arguments and sets up a plan's geometry, device and stream;
+// the off-line stage itself is create_impl.
+static ls_status create_common(ls_plan** out, int n, double h, double omega, const double* m,
+                               const ls_options* opt, void* stream, const ls_plan* src) {
   if (!out || !m) {
     ls_set_error("ls_plan_create: null pointer");
     return LS_EINVAL;
@@ -605,7 +654,7 @@ ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const dou
     }
     p->own_stream = true;
   }
-  ls_status s = create_impl(p, m);
+  ls_status s = create_impl(p, m, src);
   if (s != LS_OK) {
     std::string keep = g_last_error;
     ls_plan_destroy(p);
@@ -613,6 +662,35 @@ ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const dou
     return s;
   }
   *out = p;
+  return LS_OK;
+}
+
+ls_status ls_plan_create(ls_plan** out, int n, double h, double omega, const double* m,
+                         const ls_options* opt, void* stream) {
+  return create_common(out, n, h, omega, m, opt, stream, nullptr);
+}
+
+ls_status ls_plan_create_like(ls_plan** out, const ls_plan* src, const double* m, const ls_options* opt,
+                              void* stream) {
+  if (!src) {
+    ls_set_error("ls_plan_create_like: null source plan");
+    return LS_EINVAL;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != src->device) {
+    ls_set_error("ls_plan_create_like: the source plan lives on another device");
+    return LS_EINVAL;
+  }
+  return create_common(out, src->n, src->h, src->omega, m, opt, stream, src);
+}
+
+ls_status ls_plan_timings(const ls_plan* p, double* ms, int count) {
+  if (!p || !ms || count < 1) {
+    ls_set_error("ls_plan_timings: bad arguments");
+    return LS_EINVAL;
+  }
+  for (int i = 0; i < count && i < 8; ++i) ms[i] = p->stage_ms[i];
+  for (int i = 8; i < count; ++i) ms[i] = 0.0;
   return LS_OK;
 }
 
@@ -762,6 +840,63 @@ ls_status ls_apply_c64(ls_plan* p, const float* v, float* Hv, int batch) {
   }
   DeviceGuard dg(p->device);
   return apply_H32(p, reinterpret_cast<const fcplx*>(v), reinterpret_cast<fcplx*>(Hv), batch, 1.0, 1.0);
+}
+
+ls_status ls_sparse_solve(ls_plan* p, const double* g, double* v, int batch, double tol, int max_its,
+                          ls_solve_info* info) {
+  if (!p || !g || !v || batch < 1 || g == v || !(tol > 0) || max_its < 1) {
+    ls_set_error("ls_sparse_solve: bad arguments");
+    return LS_EINVAL;
+  }
+  DeviceGuard dg(p->device);
+  const size_t N = (size_t)p->n * p->n;
+  bool all = true;
+  for (int b0 = 0; b0 < batch; b0 += p->opt.max_batch) {
+    const int B = std::min(p->opt.max_batch, batch - b0);
+    const auto t0 = std::chrono::steady_clock::now();
+    const cplx* gb = reinterpret_cast<const cplx*>(g) + b0 * N;
+    cplx* vb = reinterpret_cast<cplx*>(v) + b0 * N;
+    std::vector<GmresResult> res;
+    auto run = [&](auto tag, const auto* gi, auto* vo) -> ls_status {
+      using T = decltype(tag);
+      auto op = [&](const T* in, T* out, int nb) { return stencil_apply_C(p, in, out, nb); };
+      auto pr = [&](const T* in, T* out, int nb) { return inner_prec<T>(p, in, out, nb); };
+      return fgmres<T>(p, op, pr, gi, vo, B, tol, max_its, 0, PK<T>::iV(p), PK<T>::iZ(p), res);
+    };
+    if (p->fp32) {
+      LS_TRY(via_f32(p, g + 2 * b0 * N, v + 2 * b0 * N, B,
+                     [&](const fcplx* a, fcplx* o) { return run(fcplx{}, a, o); }));
+    } else {
+      LS_TRY(run(cplx{}, gb, vb));
+    }
+    // the recomputed FP64 residual ||g - C v|| / ||g||
+    cplx* e = p->vtmp + (size_t)p->opt.max_batch * N;
+    std::vector<double> ng(B), ne(B);
+    LS_TRY(vec_norms(p, gb, N, B, ng.data()));
+    LS_TRY(stencil_residual_C(p, gb, vb, e, B));
+    LS_TRY(vec_norms(p, e, N, B, ne.data()));
+    LS_HIP(hipStreamSynchronize(p->stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < B; ++i) {
+      const double rel = ng[i] > 0 ? ne[i] / ng[i] : 0.0;
+      all = all && res[i].converged;
+      if (info) {
+        ls_solve_info& I = info[b0 + i];
+        I.outer_its = res[i].iters;
+        I.inner_its_total = 0;
+        I.relres_est = res[i].relres;
+        I.relres_true = rel;
+        I.converged = res[i].converged ? 1 : 0;
+        I.t_ms = ms / B;
+        I.fno_flags = 0;
+      }
+    }
+  }
+  if (!all) {
+    ls_set_error("ls_sparse_solve: hit max_its before tol");
+    return LS_ENOCONV;
+  }
+  return LS_OK;
 }
 
 ls_status ls_precond_apply(ls_plan* p, const double* r, double* z, int batch) {

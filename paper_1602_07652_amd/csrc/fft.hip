@@ -1164,6 +1164,20 @@ ls_status fft2_full_forward(ls_plan* p, cplx* c) {
 #undef CALL_FULL
 }
 
+__global__ void k_spec_to_f32(const cplx* __restrict__ a, fcplx* __restrict__ b, size_t cnt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+// FP32 copy of the stored FP64 spectrum (the same rounding as extracting it
+// from the transform in FP32).
+ls_status spectrum_to_f32(ls_plan* p) {
+  const size_t cnt = (size_t)p->spec_side * p->spec_side;
+  k_spec_to_f32<<<(unsigned)((cnt + 255) / 256), 256, 0, p->stream>>>(p->spec, p->f32.spec, cnt);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
 ls_status spectrum_extract(ls_plan* p, const cplx* c) {
   const int ss = p->P / 2 + 1;
   const double scale = p->omega * p->omega / ((double)p->P * (double)p->P);

@@ -214,6 +214,10 @@ struct ls_plan {
   int col_variant64 = 0, col_variant32 = 0;  // autotuned FFT column-pass variants
   float tune_ms64[8] = {}, tune_ms32[8] = {};
   int cus = 256;                 // compute units of the plan's device
+  // wall time of the off-line stages (ls_plan_timings): kernel samples and
+  // circulant, stencils, spectrum, slab assembly, slab factorisation, top
+  // operators, FFT autotuning, whole ls_plan_create
+  double stage_ms[8] = {};
 };
 
 inline ApplyView<cplx, double> view64(ls_plan* p) {
@@ -234,6 +238,8 @@ hipStream_t fno_swap_stream(ls_fno* f, hipStream_t s);
 int fno_max_batch(const ls_fno* f);
 int fno_max_n(const ls_fno* f);
 
+// host wall clock in ms after the plan's stream has drained (stage timers)
+double plan_clock_ms(ls_plan* p);
 // device memory helpers (record in plan->allocs)
 ls_status plan_alloc(ls_plan* p, void** ptr, size_t bytes);
 
@@ -245,6 +251,7 @@ ls_status launch_kernel_samples(ls_plan* p, cplx* w);            // (2n-1)^2 sam
 ls_status fft_setup_twiddles(ls_plan* p);
 ls_status fft2_full_forward(ls_plan* p, cplx* c);                // in place, P x P row-major
 ls_status spectrum_extract(ls_plan* p, const cplx* c);           // -> p->spec
+ls_status spectrum_to_f32(ls_plan* p);                            // p->f32.spec from p->spec
 ls_status apply_H(ls_plan* p, const cplx* v, cplx* y, int batch, double sign_identity, double scale_conv);
 ls_status apply_H32(ls_plan* p, const fcplx* v, fcplx* y, int batch, double sign_identity, double scale_conv);
 constexpr int kFftVariants = 8;  // FFT column-pass variants (fft.hip)

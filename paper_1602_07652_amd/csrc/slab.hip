@@ -1643,11 +1643,18 @@ ls_status slabs_build(ls_plan* p) {
         if ((st = plan_alloc(p, (void**)&s.fac, s.fac_elems * sizeof(cplx))) != LS_OK) break;
       }
       const cplx* tables = p->stencil_d + (o == 0 ? 0 : 162);
+      const double t0 = plan_clock_ms(p);
       k_assemble<<<dim3((s.q + 63) / 64, n), 64, 0, p->stream>>>(
           s.coef, tables, p->m, n, s.q, s.z0, s.a, s.b, std::max(ext, 2), o, w2, sigma);
       if (hipGetLastError() != hipSuccess) { ls_set_error("assembly launch failed"); st = LS_EDEVICE; break; }
+      const double t1 = plan_clock_ms(p);
       if ((st = factor_slab(p, s, work, status)) != LS_OK) break;
+      const double t2 = plan_clock_ms(p);
       if ((st = build_top(p, s, s.fac, work, work_elems)) != LS_OK) break;
+      const double t3 = plan_clock_ms(p);
+      p->stage_ms[3] += t1 - t0;
+      p->stage_ms[4] += t2 - t1;
+      p->stage_ms[5] += t3 - t2;
       if (p->fp32) {
         // FP64 factorisation, FP32 storage for the solves
         k_down_copy<<<(unsigned)((s.fac_elems + 255) / 256), 256, 0, p->stream>>>(s.fac, s.fac32,
