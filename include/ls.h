@@ -83,7 +83,25 @@ typedef struct {
   int use_graphs;        /* 1: the inner preconditioner runs as a captured hipGraph */
   int autotune;          /* 1: time the FFT column-pass tile variants at plan creation */
   int fft_variant;       /* autotune 0: FFT column-pass variant to use, 0..7 (0: radix-16 register passes) */
+  int sweep;             /* LS_SWEEP_SEQUENTIAL or LS_SWEEP_DECOUPLED (how Alg. 1 runs, one right-hand side) */
 } ls_options;
+
+/* How one application of Alg. 1 (Section 3.4) runs for one right-hand side
+ * (ls_options.sweep); both are the same linear operator.
+ * LS_SWEEP_SEQUENTIAL: as written, 2L - 1 local solves one after the other,
+ *   each waiting for the traces of its neighbour.
+ * LS_SWEEP_DECOUPLED: every layer's local solve of its own right-hand side
+ *   first (independent), then the traces the sweeps pass between layers by
+ *   two short chains of dense products with precomputed trace-transfer maps
+ *   (each the restriction of a local Green's function to the two lines a
+ *   neighbour reads -- the reduction of the sweep to interface unknowns the
+ *   paper's Section 6 names as future work), then every layer's solve with
+ *   its trace sources added (independent again): 2L local solves with no
+ *   dependence between layers, plus the chains.  Plan creation then also
+ *   builds the maps: 4n local solves per layer, three 2n x 2n maps per layer
+ *   (n = 1024: 64 MB each in FP64).  Batches of several right-hand sides use
+ *   the sequential sweep. */
+enum { LS_SWEEP_SEQUENTIAL = 0, LS_SWEEP_DECOUPLED = 1 };
 
 typedef struct {
   int outer_its;          /* outer flexible-GMRES iterations */
@@ -98,7 +116,7 @@ typedef struct {
 /* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,
  * max_inner 50, shift_c 0, LS_FP64, LS_PREC_BD, inner_fixed_iters 0,
  * max_batch 1, lowp_tol 1e-5, max_refine 10, use_graphs 1, autotune 1,
- * fft_variant 0.
+ * fft_variant 0, sweep LS_SWEEP_SEQUENTIAL.
  * Never fails. */
 void ls_options_default(ls_options* opt);
 
@@ -132,10 +150,10 @@ ls_status ls_plan_create_like(ls_plan** out, const ls_plan* src, const double* m
  * step: ms[0] kernel samples and circulant embedding, ms[1] stencils,
  * ms[2] spectrum (2-D FFT and quarter extraction; for ls_plan_create_like
  * the copies from the source plan), ms[3] slab assembly, ms[4] slab
- * factorisation, ms[5] top-of-reduction operators, ms[6] FFT autotuning,
- * ms[7] the whole plan creation.  Steps are timed with the stream drained
- * between them.  count <= 8 entries are written (more are zeroed).  HOST
- * array. */
+ * factorisation, ms[5] top-of-reduction operators, ms[6] trace-transfer
+ * maps (LS_SWEEP_DECOUPLED), ms[7] FFT autotuning, ms[8] the whole plan
+ * creation.  Steps are timed with the stream drained between them.  count
+ * <= 9 entries are written (more are zeroed).  HOST array. */
 ls_status ls_plan_timings(const ls_plan* plan, double* ms, int count);
 
 /* Frees the plan (synchronises its stream first).  NULL is accepted. */

@@ -25,6 +25,7 @@ __all__ = [
 
 LS_PREC_BD, LS_PREC_PT1, LS_PREC_NONE = 0, 1, 2
 LS_FP64, LS_FP32_REFINE = 0, 1
+LS_SWEEP_SEQUENTIAL, LS_SWEEP_DECOUPLED = 0, 1
 _STATUS = {0: "LS_OK", 1: "LS_EINVAL", 2: "LS_ENOMEM", 3: "LS_EDEVICE", 4: "LS_ENOCONV",
            5: "LS_ESINGULAR", 6: "LS_EUNSUPPORTED"}
 
@@ -43,6 +44,7 @@ class Options(ctypes.Structure):
         ("inner_fixed_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("lowp_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
         ("use_graphs", ctypes.c_int), ("autotune", ctypes.c_int), ("fft_variant", ctypes.c_int),
+        ("sweep", ctypes.c_int),
     ]
 
 
@@ -295,12 +297,13 @@ class Plan:
         _check("ls_stencil_C", lib().ls_stencil_C(self.handle, _ptr(v, N, "v"), _ptr(out, N, "y"), b))
         return out
 
-    STAGES = ("samples", "stencils", "spectrum", "assembly", "factorisation", "top", "autotune", "total")
+    STAGES = ("samples", "stencils", "spectrum", "assembly", "factorisation", "top", "maps", "autotune",
+              "total")
 
     def timings(self):
         """ls_plan_timings: wall ms of the off-line stage by step."""
-        ms = (_d * 8)()
-        _check("ls_plan_timings", lib().ls_plan_timings(self.handle, ms, 8))
+        ms = (_d * 9)()
+        _check("ls_plan_timings", lib().ls_plan_timings(self.handle, ms, 9))
         return dict(zip(self.STAGES, list(ms)))
 
     def slab_info(self, orient, slab):

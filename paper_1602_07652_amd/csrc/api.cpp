@@ -297,6 +297,7 @@ ls_status f32_scratch(ls_plan* p, F32Scratch& s) {
 bool valid_opts(const ls_options& o) {
   if (o.use_graphs < 0 || o.use_graphs > 1 || o.autotune < 0 || o.autotune > 1) return false;
   if (o.fft_variant < 0 || o.fft_variant >= kFftVariants) return false;
+  if (o.sweep != LS_SWEEP_SEQUENTIAL && o.sweep != LS_SWEEP_DECOUPLED) return false;
   return o.ext >= 0 && o.inner_tol > 0 && o.max_outer >= 1 && o.max_inner >= 1 &&
          (o.precision == LS_FP64 || o.precision == LS_FP32_REFINE) && o.precond >= LS_PREC_BD &&
          o.precond <= LS_PREC_NONE && o.inner_fixed_iters >= 0 && o.max_batch >= 1 &&
@@ -482,6 +483,7 @@ void ls_options_default(ls_options* o) {
   o->use_graphs = 1;
   o->autotune = 1;
   o->fft_variant = 0;
+  o->sweep = LS_SWEEP_SEQUENTIAL;
 }
 
 const char* ls_status_str(ls_status s) {
@@ -505,6 +507,11 @@ ls_status ls_plan_destroy(ls_plan* p) {
   (void)hipStreamSynchronize(p->stream);
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   for (void* a : p->allocs) (void)hipFree(a);
+  for (int k = 0; k < ls_plan::kSide; ++k) {
+    if (p->side[k]) (void)hipStreamDestroy(p->side[k]);
+    if (p->side_join[k]) (void)hipEventDestroy(p->side_join[k]);
+  }
+  if (p->side_fork) (void)hipEventDestroy(p->side_fork);
   if (p->own_stream) (void)hipStreamDestroy(p->stream);
   delete p;
   return LS_OK;
@@ -585,8 +592,8 @@ static ls_status create_impl(ls_plan* p, const double* m, const ls_plan* src) {
   }
   LS_HIP(hipStreamSynchronize(p->stream));
   const double t_end = plan_clock_ms(p);
-  p->stage_ms[6] = tuned ? t_end - t_tune : 0.0;
-  p->stage_ms[7] = t_end - t_start;
+  p->stage_ms[7] = tuned ? t_end - t_tune : 0.0;
+  p->stage_ms[8] = t_end - t_start;
   return LS_OK;
 }
 
@@ -689,8 +696,8 @@ ls_status ls_plan_timings(const ls_plan* p, double* ms, int count) {
     ls_set_error("ls_plan_timings: bad arguments");
     return LS_EINVAL;
   }
-  for (int i = 0; i < count && i < 8; ++i) ms[i] = p->stage_ms[i];
-  for (int i = 8; i < count; ++i) ms[i] = 0.0;
+  for (int i = 0; i < count && i < 9; ++i) ms[i] = p->stage_ms[i];
+  for (int i = 9; i < count; ++i) ms[i] = 0.0;
   return LS_OK;
 }
 

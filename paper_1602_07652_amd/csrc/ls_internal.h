@@ -120,6 +120,17 @@ struct Slab {
   cplx* top;
   fcplx* top32;
   fcplx* top32T;  // FP32 plans with max_batch >= 16: column-major copy [top_n][top_n]
+  // Trace-transfer maps of the decoupled sweep (opt.sweep == LS_SWEEP_DECOUPLED),
+  // row-major [2n][2n] in the plan's precision (null where the slab needs none):
+  // mT = R_tau (C^l)^{-1} E, mU = R_sigma (C^l)^{-1} E, mV = R_sigma (C^l)^{-1} F
+  // (E, F: the downward and upward trace-source injections of the layer,
+  // R_tau, R_sigma: the two grid lines its neighbours read).
+  cplx* mT;
+  cplx* mU;
+  cplx* mV;
+  fcplx* mT32;
+  fcplx* mU32;
+  fcplx* mV32;
 };
 
 // Contiguous set of grid vectors used as a Krylov basis.
@@ -195,6 +206,8 @@ struct ls_plan {
   fcplx* slab_elim32 = nullptr;
   fcplx* top_part32 = nullptr;   // batched top operator: per-slice partial products
   fcplx* vtmp32 = nullptr;       // FP32 plans: grid vectors [3][n*n]
+  cplx* traces = nullptr;        // decoupled sweep: tau and sigma traces [2][L][2n]
+  fcplx* traces32 = nullptr;
 
   // Krylov workspace (grid vectors), grown on demand
   KrylovSpace innerV, innerZ, outerV, outerZ;
@@ -216,8 +229,16 @@ struct ls_plan {
   int cus = 256;                 // compute units of the plan's device
   // wall time of the off-line stages (ls_plan_timings): kernel samples and
   // circulant, stencils, spectrum, slab assembly, slab factorisation, top
-  // operators, FFT autotuning, whole ls_plan_create
-  double stage_ms[8] = {};
+  // operators, trace-transfer maps, FFT autotuning, whole ls_plan_create
+  double stage_ms[9] = {};
+  // decoupled sweep: side streams for the independent local solves, their
+  // fork / join events and per-stream scratch (elimination, solution)
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t side_fork = nullptr;
+  hipEvent_t side_join[kSide] = {};
+  void* side_elim[kSide] = {};
+  void* side_work[kSide] = {};
 };
 
 inline ApplyView<cplx, double> view64(ls_plan* p) {

@@ -1106,6 +1106,100 @@ __global__ void k_scatter(const T* __restrict__ src, T* __restrict__ out, int n,
   }
 }
 
+// ------------------------------------------------------ decoupled sweep
+// The trace sources one layer receives, as a map from a trace -- two grid
+// lines of n values, [2][n] -- to the layer's right-hand side: line part p
+// enters slab-frame row rt[p] through the couplings of stencil row dZ[p] of
+// the layer's own matrix, times sgn[p] (the injections of k_gather /
+// k_scatter, Section 3.2 eq. pde_GRF_real).
+struct TraceInj {
+  int rt[2], dZ[2];
+  double sgn[2];
+};
+
+// Right-hand side of the unit trace j0 + b in x_b (b < B; x zeroed before).
+__global__ void k_unit_rhs(cplx* __restrict__ x, const cplx* __restrict__ coef, int n, int q, TraceInj E,
+                           int j0, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int j = j0 + b, p = j / n, i0 = j % n;
+  cplx* xb = x + (size_t)b * n * q;
+  for (int i = max(i0 - 1, 0); i <= min(i0 + 1, n - 1); ++i) {
+    const cplx c = coef[((size_t)i * q + E.rt[p]) * 9 + (E.dZ[p] + 1) * 3 + (i0 - i) + 1];
+    xb[(size_t)i * q + E.rt[p]] = cmk(c.x * E.sgn[p], c.y * E.sgn[p]);
+  }
+}
+
+// Columns j0 .. j0 + B - 1 of a map: M[k][j0 + b] = x_b[k mod n][row(k / n)].
+template <typename M>
+__global__ void k_extract_map(const cplx* __restrict__ x, int n, int q, int r0, int r1, M* __restrict__ map,
+                              int j0, int B) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)B * 2 * n) return;
+  const int b = (int)(t % B), k = (int)(t / B);  // consecutive threads: one map row
+  const int p = k / n, i = k % n;
+  const cplx v = x[(size_t)b * n * q + (size_t)i * q + (p ? r1 : r0)];
+  map[(size_t)k * 2 * n + j0 + b] = tmk<M>(v.x, v.y);
+}
+
+// One step of a trace chain, k < 2n:
+//   out[k] = y[k mod n][row(k / n)] (+ x1[k - n] for k >= n when addJ)
+//            + sum_j M1[k][j] x1[j] + sum_j M2[k][j] x2[j]
+// (M1, M2 may be null).  One wave per output entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trace_step(T* __restrict__ out, const T* __restrict__ y, int n, int q,
+                                                    int r0, int r1, const T* __restrict__ M1,
+                                                    const T* __restrict__ x1, const T* __restrict__ M2,
+                                                    const T* __restrict__ x2, int addJ) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + w, N2 = 2 * n;
+  if (k >= N2) return;
+  T acc = tmk<T>(0, 0);
+  if (M1) {
+    const T* row = M1 + (size_t)k * N2;
+    for (int j = lane; j < N2; j += 64) acc = tfma(row[j], x1[j], acc);
+  }
+  if (M2) {
+    const T* row = M2 + (size_t)k * N2;
+    for (int j = lane; j < N2; j += 64) acc = tfma(row[j], x2[j], acc);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+  }
+  if (lane == 0) {
+    T v = tadd(y[(size_t)(k % n) * q + (k < n ? r0 : r1)], acc);
+    if (addJ && k >= n) v = tadd(v, x1[k - n]);
+    out[k] = v;
+  }
+}
+
+// rhs += A ta (+ Bi tb): the two trace-source injections of one layer
+// (either may be absent: null trace).
+template <typename T>
+__global__ void k_inject_traces(T* __restrict__ rhs, const T* __restrict__ coef, int n, int q, TraceInj A,
+                                const T* __restrict__ ta, TraceInj Bi, const T* __restrict__ tb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int s = 0; s < 2; ++s) {
+    const TraceInj& J = s ? Bi : A;
+    const T* tr = s ? tb : ta;
+    if (!tr) continue;
+    for (int p = 0; p < 2; ++p) {
+      const T* cf = coef + ((size_t)i * q + J.rt[p]) * 9 + (J.dZ[p] + 1) * 3;
+      T acc = tmk<T>(0, 0);
+      for (int dX = -1; dX <= 1; ++dX) {
+        const int ii = i + dX;
+        if (ii < 0 || ii >= n) continue;
+        acc = tfma(cf[dX + 1], tr[(size_t)p * n + ii], acc);
+      }
+      T* o = rhs + (size_t)i * q + J.rt[p];
+      *o = tadd(*o, tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]));
+    }
+  }
+}
+
 // Horizontal slabs (grid rows are the slab's short axis), many right-hand
 // sides, no trace sources: the same copies as k_gather / k_scatter through
 // a 64 (i) x 32 (r) LDS tile, so that both the grid rows (i fastest) and the
@@ -1578,6 +1672,79 @@ ls_status factor_slab(ls_plan* p, Slab& s, cplx* work, int* status) {
 
 }  // namespace
 
+template <typename C>
+static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C* coef, C* x, size_t xs_b, int B);
+
+// Trace sources of layer s: from the layer above (downward sweep: lines b + 1
+// and b of its solution, into rows b and b + 1) and from the layer below
+// (upward sweep: lines a - 1 and a, into rows a and a - 1).
+static TraceInj inj_down(const Slab& s) {
+  return TraceInj{{s.b - s.z0, s.b + 1 - s.z0}, {+1, -1}, {-1.0, +1.0}};
+}
+static TraceInj inj_up(const Slab& s) {
+  return TraceInj{{s.a - s.z0, s.a - 1 - s.z0}, {-1, +1}, {-1.0, +1.0}};
+}
+
+// Trace-transfer maps of layer s (decoupled sweep), from its FP64 factors:
+// (C^l)^{-1} applied to the 2n unit traces of each injection it needs (in
+// batches of solves on `work`), restricted to the two lines each neighbour
+// reads.  Layer l of L needs mT (1 <= l <= L-2), mU (l <= L-2), mV
+// (1 <= l <= L-2).
+static ls_status build_maps(ls_plan* p, Slab& s, const cplx* fac, cplx* work, size_t work_elems) {
+  const int n = p->n, q = s.q, l = s.idx, L = p->L, N2 = 2 * n;
+  const bool needT = l >= 1 && l <= L - 2, needU = l <= L - 2, needV = l >= 1 && l <= L - 2;
+  if (!needU) return LS_OK;
+  const size_t mbytes = (size_t)N2 * N2 * (p->fp32 ? sizeof(fcplx) : sizeof(cplx));
+  void* mT = nullptr;
+  void* mU = nullptr;
+  void* mV = nullptr;
+  if (needT) LS_TRY(plan_alloc(p, &mT, mbytes));
+  LS_TRY(plan_alloc(p, &mU, mbytes));
+  if (needV) LS_TRY(plan_alloc(p, &mV, mbytes));
+  const size_t vec = (size_t)n * q;
+  const int Bc = (int)std::max<size_t>(1, std::min<size_t>(256, work_elems / vec));
+  const int rows_tau[2] = {s.a - s.z0, s.a - 1 - s.z0};
+  const int rows_sig[2] = {s.b - s.z0, s.b + 1 - s.z0};
+  auto extract = [&](void* map, const int* rows, int j0, int B) -> ls_status {
+    const size_t cnt = (size_t)B * N2;
+    const unsigned blocks = (unsigned)((cnt + 255) / 256);
+    if (p->fp32)
+      k_extract_map<fcplx><<<blocks, 256, 0, p->stream>>>(work, n, q, rows[0], rows[1], (fcplx*)map, j0, B);
+    else
+      k_extract_map<cplx><<<blocks, 256, 0, p->stream>>>(work, n, q, rows[0], rows[1], (cplx*)map, j0, B);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+  };
+  for (int which = 0; which < 2; ++which) {  // 0: downward injection E, 1: upward F
+    if (which == 1 && !needV) break;
+    const TraceInj J = which == 0 ? inj_down(s) : inj_up(s);
+    for (int j0 = 0; j0 < N2; j0 += Bc) {
+      const int B = std::min(Bc, N2 - j0);
+      LS_HIP(hipMemsetAsync(work, 0, (size_t)B * vec * sizeof(cplx), p->stream));
+      k_unit_rhs<<<(B + 63) / 64, 64, 0, p->stream>>>(work, s.coef, n, q, J, j0, B);
+      LS_HIP(hipGetLastError());
+      LS_TRY(solve_levels_b<cplx>(p, s, fac, s.coef, work, vec, B));
+      if (which == 0) {
+        if (needT) LS_TRY(extract(mT, rows_tau, j0, B));
+        LS_TRY(extract(mU, rows_sig, j0, B));
+      } else {
+        LS_TRY(extract(mV, rows_sig, j0, B));
+      }
+    }
+  }
+  LS_HIP(hipStreamSynchronize(p->stream));
+  if (p->fp32) {
+    s.mT32 = (fcplx*)mT;
+    s.mU32 = (fcplx*)mU;
+    s.mV32 = (fcplx*)mV;
+  } else {
+    s.mT = (cplx*)mT;
+    s.mU = (cplx*)mU;
+    s.mV = (cplx*)mV;
+  }
+  return LS_OK;
+}
+
 // Layers (Section 3.1): t = n / L lines each, the first n mod L layers one
 // more; extension ext lines each side, clipped to the grid.
 ls_status slabs_build(ls_plan* p) {
@@ -1652,9 +1819,12 @@ ls_status slabs_build(ls_plan* p) {
       const double t2 = plan_clock_ms(p);
       if ((st = build_top(p, s, s.fac, work, work_elems)) != LS_OK) break;
       const double t3 = plan_clock_ms(p);
+      if (p->opt.sweep == LS_SWEEP_DECOUPLED && (st = build_maps(p, s, s.fac, work, work_elems)) != LS_OK) break;
+      const double t4 = plan_clock_ms(p);
       p->stage_ms[3] += t1 - t0;
       p->stage_ms[4] += t2 - t1;
       p->stage_ms[5] += t3 - t2;
+      p->stage_ms[6] += t4 - t3;
       if (p->fp32) {
         // FP64 factorisation, FP32 storage for the solves
         k_down_copy<<<(unsigned)((s.fac_elems + 255) / 256), 256, 0, p->stream>>>(s.fac, s.fac32,
@@ -1681,6 +1851,20 @@ ls_status slabs_build(ls_plan* p) {
   if (bad) {
     ls_set_error("slab factorisation: zero or non-finite pivot");
     return LS_ESINGULAR;
+  }
+  if (p->opt.sweep == LS_SWEEP_DECOUPLED) {
+    const size_t tr = (size_t)2 * L * 2 * n;
+    if (p->fp32) LS_TRY(plan_alloc(p, (void**)&p->traces32, tr * sizeof(fcplx)));
+    else LS_TRY(plan_alloc(p, (void**)&p->traces, tr * sizeof(cplx)));
+    // side streams (default priority) for the independent local solves
+    const size_t esz = p->fp32 ? sizeof(fcplx) : sizeof(cplx);
+    LS_HIP(hipEventCreateWithFlags(&p->side_fork, hipEventDisableTiming));
+    for (int k = 0; k < ls_plan::kSide; ++k) {
+      LS_HIP(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
+      LS_HIP(hipEventCreateWithFlags(&p->side_join[k], hipEventDisableTiming));
+      LS_TRY(plan_alloc(p, &p->side_elim[k], (size_t)n * qmax * esz));
+      LS_TRY(plan_alloc(p, &p->side_work[k], (size_t)n * qmax * esz));
+    }
   }
   const size_t wv = (size_t)n * qmax * p->opt.max_batch;
   const size_t w1 = (size_t)n * qmax;  // single-right-hand-side elimination scratch
@@ -1809,6 +1993,10 @@ struct SB<cplx> {
   static cplx* elim(ls_plan* p) { return p->slab_elim; }
   static const cplx* top(const Slab& s) { return s.top; }
   static cplx* vtmp(ls_plan* p) { return p->vtmp; }
+  static const cplx* mT(const Slab& s) { return s.mT; }
+  static const cplx* mU(const Slab& s) { return s.mU; }
+  static const cplx* mV(const Slab& s) { return s.mV; }
+  static cplx* traces(ls_plan* p) { return p->traces; }
 };
 template <>
 struct SB<fcplx> {
@@ -1820,6 +2008,10 @@ struct SB<fcplx> {
   static fcplx* elim(ls_plan* p) { return p->slab_elim32; }
   static const fcplx* top(const Slab& s) { return s.top32; }
   static fcplx* vtmp(ls_plan* p) { return p->vtmp32; }
+  static const fcplx* mT(const Slab& s) { return s.mT32; }
+  static const fcplx* mU(const Slab& s) { return s.mU32; }
+  static const fcplx* mV(const Slab& s) { return s.mV32; }
+  static fcplx* traces(ls_plan* p) { return p->traces32; }
 };
 
 // y = C_slab^{-1} g for B right-hand sides [B][n][q] (g untouched, y != g).
@@ -1908,6 +2100,101 @@ static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool a
   return LS_OK;
 }
 
+// Alg. 1 for one right-hand side with the layers decoupled (the same linear
+// operator): y^l = (C^l)^{-1} g^l for every layer; the traces the downward
+// sweep passes, tau^l = R_tau w^l = R_tau y^l + mT^l tau^{l+1}, and the
+// upward sweep's, sigma^l = R_sigma v^l + J tau^{l+1} = R_sigma y^l +
+// (mU^l + J) tau^{l+1} + mV^l sigma^{l-1}, by two chains of dense products;
+// then every layer's solve of g^l + E^l tau^{l+1} + F^l sigma^{l-1}, whose
+// layer lines are Alg. 1's output.
+// The independent per-layer work runs on the plan's side streams, layer l on
+// stream l mod kSide (forked from and joined back to the plan's stream by
+// events, so a captured graph records it as parallel branches); while a
+// side stream runs, the plan's stream and single-solve scratch are swapped
+// for that stream's own.
+struct SideSwap {
+  ls_plan* p;
+  hipStream_t st;
+  cplx* e64;
+  cplx* w64;
+  fcplx* e32;
+  fcplx* w32;
+  SideSwap(ls_plan* p_, int k) : p(p_), st(p_->stream), e64(p_->slab_elim), w64(p_->slab_work),
+                                 e32(p_->slab_elim32), w32(p_->slab_work32) {
+    p->stream = p->side[k];
+    if (p->fp32) {
+      p->slab_elim32 = (fcplx*)p->side_elim[k];
+      p->slab_work32 = (fcplx*)p->side_work[k];
+    } else {
+      p->slab_elim = (cplx*)p->side_elim[k];
+      p->slab_work = (cplx*)p->side_work[k];
+    }
+  }
+  ~SideSwap() {
+    p->stream = st;
+    p->slab_elim = e64;
+    p->slab_work = w64;
+    p->slab_elim32 = e32;
+    p->slab_work32 = w32;
+  }
+};
+
+template <class F>
+static ls_status on_side_streams(ls_plan* p, int L, F per_layer) {
+  constexpr int K = ls_plan::kSide;
+  LS_HIP(hipEventRecord(p->side_fork, p->stream));
+  for (int k = 0; k < K && k < L; ++k) LS_HIP(hipStreamWaitEvent(p->side[k], p->side_fork, 0));
+  ls_status st = LS_OK;
+  for (int l = 0; l < L && st == LS_OK; ++l) {
+    SideSwap sw(p, l % K);
+    st = per_layer(l);
+  }
+  for (int k = 0; k < K && k < L; ++k) {
+    LS_HIP(hipEventRecord(p->side_join[k], p->side[k]));
+    LS_HIP(hipStreamWaitEvent(p->stream, p->side_join[k], 0));
+  }
+  return st;
+}
+
+template <typename T>
+static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, bool accumulate) {
+  std::vector<Slab>& S = p->slabs[orient];
+  const int L = (int)S.size(), n = p->n, N2 = 2 * n;
+  T* tau = SB<T>::traces(p);
+  T* sig = tau + (size_t)L * N2;
+  LS_TRY(on_side_streams(p, L, [&](int l) -> ls_status {
+    Slab& s = S[l];
+    LS_TRY(gather<T>(p, s, g, SB<T>::g(s), 1, nullptr));
+    return solve_t<T>(p, s, SB<T>::g(s), SB<T>::w(s), 1);
+  }));
+  const unsigned steps = (unsigned)((N2 + 3) / 4);
+  for (int l = L - 1; l >= 1; --l) {
+    Slab& s = S[l];
+    const bool m = l <= L - 2;
+    k_trace_step<T><<<steps, 256, 0, p->stream>>>(tau + (size_t)l * N2, SB<T>::w(s), n, s.q, s.a - s.z0,
+                                                  s.a - 1 - s.z0, m ? SB<T>::mT(s) : nullptr,
+                                                  m ? tau + (size_t)(l + 1) * N2 : nullptr, nullptr, nullptr, 0);
+  }
+  for (int l = 0; l <= L - 2; ++l) {
+    Slab& s = S[l];
+    k_trace_step<T><<<steps, 256, 0, p->stream>>>(sig + (size_t)l * N2, SB<T>::w(s), n, s.q, s.b - s.z0,
+                                                  s.b + 1 - s.z0, SB<T>::mU(s), tau + (size_t)(l + 1) * N2,
+                                                  l >= 1 ? SB<T>::mV(s) : nullptr,
+                                                  l >= 1 ? sig + (size_t)(l - 1) * N2 : nullptr, 1);
+  }
+  LS_HIP(hipGetLastError());
+  return on_side_streams(p, L, [&](int l) -> ls_status {
+    Slab& s = S[l];
+    k_inject_traces<T><<<(n + 255) / 256, 256, 0, p->stream>>>(
+        SB<T>::g(s), SB<T>::coef(s), n, s.q, inj_down(s), l <= L - 2 ? tau + (size_t)(l + 1) * N2 : nullptr,
+        inj_up(s), l >= 1 ? sig + (size_t)(l - 1) * N2 : nullptr);
+    LS_HIP(hipGetLastError());
+    T* x = SB<T>::work(p, 0);
+    LS_TRY(solve_t<T>(p, s, SB<T>::g(s), x, 1));
+    return scatter<T>(p, s, x, v, accumulate, 1, nullptr);
+  });
+}
+
 // Alg. 1 (Gauss-Seidel polarized traces) on layers of one orientation, for
 // B right-hand sides at once.  v receives the concatenated layer solutions
 // (or has them added).
@@ -1915,6 +2202,8 @@ template <typename T>
 static ls_status sweep_t(ls_plan* p, int orient, const T* g, T* v, bool accumulate, int B) {
   std::vector<Slab>& S = p->slabs[orient];
   const int L = (int)S.size();
+  if (B == 1 && L >= 2 && p->opt.sweep == LS_SWEEP_DECOUPLED && SB<T>::traces(p))
+    return sweep_decoupled_t<T>(p, orient, g, v, accumulate);
   // downward sweep: l = L-1 .. 0 (gather with the trace sources of w^{l+1})
   for (int l = L - 1; l >= 0; --l) {
     Slab& s = S[l];

@@ -151,6 +151,39 @@ def test_sweeps_and_bidirectional(n, f, L, ext, shift, seed):
     p.close()
 
 
+@pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES)
+def test_decoupled_sweep_matches_oracle(n, f, L, ext, shift, seed):
+    """Alg. 1 with the layers decoupled by trace-transfer maps (independent
+    local solves, two chains of dense products for the traces, independent
+    solves again) is the same linear operator as the sequential sweep: both
+    orientations and Alg. 2 against the oracle's sequential sweeps."""
+    from paper_1602_07652_amd import LS_SWEEP_DECOUPLED
+    m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
+    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift, sweep=LS_SWEEP_DECOUPLED)
+    bd = slabs.BiDirectional(al, be, m, omega, L, ext, shift)
+    g = li.random_complex((n, n), 13)
+    e0 = rel(host(p.sweep(0, dev(g))), bd.prec_h(g))
+    e1 = rel(host(p.sweep(1, dev(g))), bd.prec_v(g))
+    e2 = rel(host(p.bidirectional(dev(g))), bd.apply(g))
+    banner(f"decoupled sweeps n={n} L={L} shift={shift}: H {e0:.3e} V {e1:.3e} BD {e2:.3e}")
+    assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10
+    p.close()
+
+
+def test_decoupled_sweep_fp32_plan():
+    from paper_1602_07652_amd import LS_SWEEP_DECOUPLED, LS_FP32_REFINE
+    n, f, L, ext, shift, seed = SLAB_CASES[1]
+    m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
+    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift, sweep=LS_SWEEP_DECOUPLED,
+                     precision=LS_FP32_REFINE)
+    bd = slabs.BiDirectional(al, be, m, omega, L, ext, shift)
+    g = li.random_complex((n, n), 14)
+    e = rel(host(p.bidirectional(dev(g))), bd.apply(g))
+    banner(f"decoupled sweeps FP32 n={n}: BD {e:.3e}")
+    assert e < 5e-5
+    p.close()
+
+
 def test_precond_fixed_iterations():
     n, f, L = 64, 6.0, 4
     m = li.gaussian_disk_medium(n)
@@ -331,6 +364,29 @@ def test_too_thick_layer_is_refused():
         make_plan(n, 20.0, np.zeros((n, n)), slabs=2, ext=10)     # q = 120 > 96
     banner(f"refused: {ei.value}")
     assert "96" in str(ei.value)
+
+
+def test_decoupled_sweep_at_bench_shape(bench_shape):
+    """1024^2, 16 layers: the decoupled sweep against the sequential one of
+    the bench plan, and the full bench solve with it (same iterations, same
+    solution to the tolerance)."""
+    from paper_1602_07652_amd import LS_SWEEP_DECOUPLED
+    n, omega, m, al, be, p = bench_shape
+    pd, _ = make_plan(n, omega / (2 * np.pi), m, slabs=16, ext=10, sweep=LS_SWEEP_DECOUPLED)
+    g = dev(li.random_complex((n, n), 71))
+    for orient in (0, 1):
+        e = rel(host(pd.sweep(orient, g)), host(p.sweep(orient, g)))
+        banner(f"bench-shape decoupled vs sequential sweep orient={orient}: {e:.3e}")
+        assert e < 1e-10
+    cfg = li.config_inputs("c2_1024_bumps")
+    f = p.rhs_from_incident(dev(cfg["uI"]))
+    us, i_s = p.solve(f, tol=1e-8)
+    ud, i_d = pd.solve(f, tol=1e-8)
+    e = rel(host(ud), host(us))
+    banner(f"bench solve sequential {i_s[0]} decoupled {i_d[0]}: {e:.3e}")
+    assert i_d[0]["converged"] == 1 and i_d[0]["outer_its"] == i_s[0]["outer_its"]
+    assert e < 1e-8
+    pd.close()
 
 
 def test_apply_properties_at_bench_shape(bench_shape):
