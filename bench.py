@@ -8,7 +8,12 @@ omega = 2*pi*100 (10.24 points per wavelength), medium = 8 Gaussian bumps
 GMRES to relative residual 1e-8.
 
 One step = one ls_solve of one right-hand side (the on-line stage, plan
-reused).  Prints one JSON line.  Also reports:
+reused), with the decoupled form of the sweeps (LS_SWEEP_DECOUPLED: every
+layer's local solves independent, the traces passed between layers by
+precomputed trace-transfer maps; the same operator as the sequential
+sweep, whose solve rate is reported as a variant).  Plan creation (with the
+maps) is timed separately (config.setup_s).  Prints one JSON line.  Also
+reports:
   * roofline of the dominant kernel chain (the single-right-hand-side
     block-cyclic-reduction slab solve of an interior layer, ~95 % of a
     solve), timed live with HIP events on the plan's stream;
@@ -37,8 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/ named for the slab solve holds the figures and their command.
 # It is a counter figure from a profiling run, not a measurement of this
 # run: None when the kernels have changed since the counters were taken.
-SLAB_TRAFFIC_BYTES = None
-SLAB_TRAFFIC_SOURCE = None
+SLAB_TRAFFIC_BYTES = 450.09e6
+SLAB_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode slab` (5 interior slab solves), "
+                       "scaled by the counters of a 1 GiB device copy; see the slab-solve profile")
 
 
 def log(msg):
@@ -515,10 +521,13 @@ def main():
     popts = {}
     if args.fft_variant is not None:
         popts = dict(autotune=0, fft_variant=args.fft_variant, precision=1)
+    if args.mode == "full":
+        popts["sweep"] = 1    # decoupled sweeps for the timed solve
     plan = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, max_batch=8, **popts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    log(f"plan created in {setup_s:.2f} s")
+    setup_steps = plan.timings()
+    log(f"plan created in {setup_s:.2f} s ({setup_steps})")
     if args.mode == "apply":
         Bt = 8
         vb = torch.randn((Bt, n, n), dtype=torch.complex128, device=dev)
@@ -616,6 +625,23 @@ def main():
     log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic")
 
     plan.close()
+    # the same solve with the sequential sweeps (Alg. 1 as written)
+    t0 = time.perf_counter()
+    pseq = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext)
+    torch.cuda.synchronize()
+    setup_seq = time.perf_counter() - t0
+    pseq.solve(f, tol=args.tol, out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos_seq = [pseq.solve(f, tol=args.tol, out=u)[1][0] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    pseq.close()
+    seq_single = {"workload": "the plain workload with the sequential sweeps (Alg. 1 as written)",
+                  "solves_per_s": args.steps / el_seq, "ms_per_solve": 1e3 * el_seq / args.steps,
+                  "outer_its": float(np.mean([i["outer_its"] for i in infos_seq])),
+                  "relres_true": max(i["relres_true"] for i in infos_seq), "setup_s": setup_seq}
+    log(f"sequential sweeps: {seq_single}")
     # the same workload with FP32 operator and slab solves and FP64 refinement
     from paper_1602_07652_amd import LS_FP32_REFINE
     t0 = time.perf_counter()
@@ -664,7 +690,8 @@ def main():
         "config": {
             "workload": "plain two-level solve, 1024^2 grid, omega=2*pi*100, 8 Gaussian bumps (seed 0), "
                         "one plane wave, 16 layers x 2 directions, ext 10, FP64, BD inner preconditioner",
-            "variant": "plain (FP64, one right-hand side at a time)",
+            "variant": "plain (FP64, one right-hand side at a time, decoupled sweeps)",
+            "setup_steps_ms": setup_steps,
             "outer_its": outer,
             "inner_its_total": inner,
             "relres_true": max(i["relres_true"] for i in infos),
@@ -684,7 +711,8 @@ def main():
             "ms_per_launch": slab_ms,
         },
         "cpu_baseline": cpu,
-        "variants": {"fp32_refine_single": fp32_single, "fp32_refine_2048_grf": c3,
+        "variants": {"plain_sequential_sweeps": seq_single, "fp32_refine_single": fp32_single,
+                     "fp32_refine_2048_grf": c3,
                      "batched_fp32_multigrid": batched,
                      "learned_fp32_multigrid": learned},
     }
