@@ -323,7 +323,9 @@ def learned_variant(tol, log_fn, weights):
         with torch.cuda.stream(st):
             p = Plan(n, 1.0 / n, omega, torch.from_numpy(m).to(dev), slabs=max(1, n // 64), ext=10,
                      max_batch=B, precision=LS_FP32_REFINE)
-            net = Fno(max_batch=8, max_n=n)
+            # 64 samples per network evaluation where the network runs on every
+            # wave (the training size); 8 elsewhere (its activation buffers grow as n^2)
+            net = Fno(max_batch=64 if n <= 256 else 8, max_n=n)
             net.set_params(params)
             uI = torch.from_numpy(np.stack([li.plane_wave(n, omega, 2 * np.pi * k / B)
                                             for k in range(B)])).to(dev)

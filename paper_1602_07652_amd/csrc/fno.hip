@@ -47,6 +47,7 @@ struct GemmP {
   const float* bias_m;  // added to row m (split 0 only)
   int atomic;           // split K: accumulate with atomic adds
   float* C2;            // if set: GELU of the result, same layout as C (C may then be null)
+  const __bf16* Ah;     // if set: A stored as bf16 (read in place of A)
 };
 
 // Tile BM x BN x 32, 256 threads = 4 waves in a WM x WN grid; each wave
@@ -54,7 +55,7 @@ struct GemmP {
 // staged k-contiguous in LDS (rows padded to 40 bf16 = 80 bytes, so the 16
 // rows one 16-byte read touches fall in distinct banks).  The next K tile's
 // global loads are issued before the current tile's MFMAs.
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, typename TA = float>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmP g) {
   constexpr int BK = 32, LDK = 40;
   constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 16, FN = TN / 16;
@@ -69,7 +70,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmP g) {
   const long long b = blockIdx.y;
   const int kb = blockIdx.z * g.klen;
   const int ke = min(g.K, kb + g.klen);
-  const float* __restrict__ A = g.A + b * g.sab;
+  const TA* __restrict__ A;
+  if constexpr (sizeof(TA) == 2) A = g.Ah + b * g.sab;
+  else A = g.A + b * g.sab;
   const float* __restrict__ B = g.B + b * g.sbb;
   const bool akf = g.sak == 1, bkf = g.sbk == 1;
   float ra[EA], rb[EB];
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmP g) {
     for (int e = 0; e < EA; ++e) {
       int m, k;
       amap(e, m, k);
-      ra[e] = (m0 + m < g.M && k0 + k < ke) ? A[ao + (m0 + m) * g.sam + (long long)(kin + k) * g.sak] : 0.f;
+      ra[e] = (m0 + m < g.M && k0 + k < ke) ? (float)A[ao + (m0 + m) * g.sam + (long long)(kin + k) * g.sak] : 0.f;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -183,10 +186,10 @@ __global__ void k_scale_strided(float* C, int M, int N, long long scm, long long
   }
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, typename TA = float>
 void launch_gemm(const GemmP& g, int batch, int splits, hipStream_t st) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  k_gemm_bf16<BM, BN, WM, WN><<<dim3(tiles, batch, splits), 256, 0, st>>>(g);
+  k_gemm_bf16<BM, BN, WM, WN, TA><<<dim3(tiles, batch, splits), 256, 0, st>>>(g);
 }
 
 // Tile shape for an M x N output, split-K count for long reductions with
@@ -232,7 +235,13 @@ ls_status gemm(GemmP g, int batch, hipStream_t st) {
     else if (g.beta != 1.f)
       k_scale_strided<<<dim3(blocks, batch), 256, 0, st>>>(g.C, g.M, g.N, g.scm, g.scn, g.scb, g.beta);
   }
-  if (bm == 16) launch_gemm<16, 64, 1, 4>(g, batch, splits, st);
+  if (g.Ah) {  // bf16 activations (inference): the x-transform shape only
+    if (bm != 128 || bn != 32) {
+      ls_set_error("bf16 GEMM: a bf16 A operand is supported for M >= 128, N = 32 only");
+      return LS_EINVAL;
+    }
+    launch_gemm<128, 32, 4, 1, __bf16>(g, batch, splits, st);
+  } else if (bm == 16) launch_gemm<16, 64, 1, 4>(g, batch, splits, st);
   else if (bm == 32 && bn == 32) launch_gemm<32, 32, 2, 2>(g, batch, splits, st);
   else if (bm == 32) launch_gemm<32, 128, 1, 4>(g, batch, splits, st);
   else if (bn == 16) launch_gemm<64, 16, 4, 1>(g, batch, splits, st);
@@ -336,7 +345,9 @@ __global__ __launch_bounds__(256) void k_layer_out(const float* __restrict__ U, 
 //   Fa[k][j]   = cos(2 pi kz j / n), Fa[32 + k][j] = -sin(...)      (Re / Im of e^{-i..})
 //   Fb[k][j]   = sin(2 pi kz j / n), Fb[32 + k][j] =  cos(...)
 //   Ai[j][k]   = cos(2 pi kz j / n), Ai[j][32 + k] =  sin(...)      (Re / Im of e^{+i..})
-__global__ void k_tables(int n, float* Fx2, float* Gx, float* Fa, float* Fb, float* Ai) {
+//   FxH[x][i] = Fx2[i][x], GxH[i][x] = Gx[x][i] as bf16 (inference: the
+//   operand layouts the matrix cores read with one 16-byte load per lane)
+__global__ void k_tables(int n, float* Fx2, float* Gx, float* Fa, float* Fb, float* Ai, __bf16* FxH, __bf16* GxH) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   for (int x = 0; x < kM; ++x) {
@@ -348,6 +359,10 @@ __global__ void k_tables(int n, float* Fx2, float* Gx, float* Fa, float* Fb, flo
     Fx2[(size_t)j * 32 + kM + x] = (float)-s;
     Gx[(size_t)x * n + j] = cx * (float)c;
     Gx[(size_t)(kM + x) * n + j] = -cx * (float)s;
+    FxH[(size_t)x * n + j] = (__bf16)(float)c;
+    FxH[(size_t)(kM + x) * n + j] = (__bf16)(float)-s;
+    GxH[(size_t)j * 32 + x] = (__bf16)(cx * (float)c);
+    GxH[(size_t)j * 32 + kM + x] = (__bf16)(-cx * (float)s);
   }
   for (int k = 0; k < kKZ; ++k) {
     const int kz = k < kM ? k : k - kKZ;
@@ -540,19 +555,286 @@ __global__ void k_inputs(const double* __restrict__ m, size_t mstr, const cplx* 
   }
 }
 
-// z = r + s (y0 + i y1)
+// Inference lift from the raw inputs: x = (m, Re uI, Im uI, Re r / s,
+// Im r / s) as k_inputs forms it, then v0 = L x + b (32 channels, FP32
+// products of the 5 inputs), stored as bf16, the precision in which the
+// first Fourier layer's products read it.
 template <typename T>
-__global__ void k_output(const T* __restrict__ r, const float* __restrict__ y, const double* __restrict__ s,
-                         T* __restrict__ z, size_t P) {
+__global__ __launch_bounds__(256) void k_lift_in(const double* __restrict__ m, size_t mstr,
+                                                 const cplx* __restrict__ uI, const T* __restrict__ r,
+                                                 const double* __restrict__ s, const float* __restrict__ Lw,
+                                                 const float* __restrict__ Lb, __bf16* __restrict__ v, size_t P) {
+  __shared__ float w[kW * kIn + kW];
+  for (int e = threadIdx.x; e < kW * kIn + kW; e += blockDim.x) w[e] = e < kW * kIn ? Lw[e] : Lb[e - kW * kIn];
+  __syncthreads();
   const int b = blockIdx.y;
-  const double sc = s[b];
-  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (size_t)gridDim.x * blockDim.x) {
-    const T rv = r[(size_t)b * P + p];
-    const float* yb = y + (size_t)b * kOut * P;
-    T o;
-    o.x = rv.x + sc * yb[p];
-    o.y = rv.y + sc * yb[P + p];
-    z[(size_t)b * P + p] = o;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one pixel per thread
+  if (p >= P) return;
+  const double inv = s[b] > 0.0 ? 1.0 / s[b] : 0.0;
+  __bf16* vb = v + (size_t)b * kW * P;
+  const cplx u = uI[(size_t)b * P + p];
+  const T rv = r[(size_t)b * P + p];
+  const float x[kIn] = {(float)m[(size_t)b * mstr + p], (float)u.x, (float)u.y, (float)(rv.x * inv),
+                        (float)(rv.y * inv)};
+#pragma unroll 8
+  for (int o = 0; o < kW; ++o) {
+    float a = w[kW * kIn + o];
+#pragma unroll
+    for (int c = 0; c < kIn; ++c) a = fmaf(w[o * kIn + c], x[c], a);
+    vb[(size_t)o * P + p] = (__bf16)a;
+  }
+}
+
+// ------------------------------------------------------ inference kernels
+// Activations are bf16 [S][32][P] (channel-major, as the training layout),
+// read and written in runs of 8 pixels (16 bytes); the matrix-core operands
+// that need 8 consecutive channels of one pixel are gathered from a tile
+// staged in LDS.
+
+// GELU with erf from Abramowitz & Stegun, Handbook of Mathematical
+// Functions, formula 7.1.26 (absolute error in erf at most 1.5e-7), for
+// inference, whose activations are then rounded to bf16 (relative spacing
+// 2^-8); training uses the library erf (gelu_f).
+__device__ __forceinline__ float gelu_as(float x) {
+  const float y = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, y, 1.f));
+  const float q =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  const float e = 1.f - q * __expf(-y * y);  // erf(|x| / sqrt 2)
+  return 0.5f * x * (1.f + copysignf(e, x));
+}
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// p[off .. off + 8) as bf16, zero from index `valid` on; one 16-byte load
+// when the run is whole and `aligned` (off a multiple of 8).
+__device__ __forceinline__ bf16x8 ld8(const __bf16* __restrict__ p, long long off, long long valid, bool aligned) {
+  if (aligned && valid >= 8) return *reinterpret_cast<const bf16x8*>(p + off);
+  bf16x8 r;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = q < valid ? p[off + q] : (__bf16)0.f;
+  return r;
+}
+
+// 8 FP32 values (16-byte aligned) rounded to bf16
+__device__ __forceinline__ bf16x8 f8_to_bf(const float* __restrict__ p) {
+  const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+  bf16x8 r;
+  r[0] = (__bf16)a.x; r[1] = (__bf16)a.y; r[2] = (__bf16)a.z; r[3] = (__bf16)a.w;
+  r[4] = (__bf16)b.x; r[5] = (__bf16)b.y; r[6] = (__bf16)b.z; r[7] = (__bf16)b.w;
+  return r;
+}
+
+// LDS tile of 32 channels x 128 pixels, rows padded to kLDV bf16 (264
+// bytes: 8-byte runs stay aligned, and the four lane groups of an operand
+// gather (rows 8 apart) and of the output scatter (rows 4 apart) fall in
+// distinct banks).
+constexpr int kTP = 128, kLDV = 132;
+
+// Stage v[c * P + base .. + kTP) for c < 32 (zero past `limit` pixels).
+__device__ __forceinline__ void stage_tile(__bf16* Vs, const __bf16* __restrict__ v, long long P, long long base,
+                                           long long limit, bool aligned, int tid) {
+  for (int e = tid; e < kW * (kTP / 8); e += 256) {
+    const int c = e / (kTP / 8), q8 = (e % (kTP / 8)) * 8;
+    const bf16x8 x = ld8(v, (long long)c * P + base + q8, limit - q8, aligned);
+    bf16x4* d = reinterpret_cast<bf16x4*>(&Vs[c * kLDV + q8]);
+    d[0] = bf16x4{x[0], x[1], x[2], x[3]};
+    d[1] = bf16x4{x[4], x[5], x[6], x[7]};
+  }
+}
+
+// B operand of a K = 32 product over channels: channels kq .. kq + 7 of
+// pixel column ii of the staged tile.
+__device__ __forceinline__ bf16x8 gather8(const __bf16* Vs, int kq, int ii) {
+  bf16x8 r;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = Vs[(kq + q) * kLDV + ii];
+  return r;
+}
+
+// Write the staged output tile back: out[c * P + base + q8 ..] for the
+// pixels below `limit`.
+__device__ __forceinline__ void store_tile(__bf16* __restrict__ out, const __bf16* Vs, long long P, long long base,
+                                           long long limit, bool aligned, int tid) {
+  for (int e = tid; e < kW * (kTP / 8); e += 256) {
+    const int c = e / (kTP / 8), q8 = (e % (kTP / 8)) * 8;
+    const long long valid = limit - q8;
+    if (valid <= 0) continue;
+    const bf16x4* sp = reinterpret_cast<const bf16x4*>(&Vs[c * kLDV + q8]);
+    const bf16x4 lo = sp[0], hi = sp[1];
+    const bf16x8 x = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    __bf16* d = out + (long long)c * P + base + q8;
+    if (aligned && valid >= 8) {
+      *reinterpret_cast<bf16x8*>(d) = x;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < valid) d[q] = x[q];
+    }
+  }
+}
+
+// x transform for inference: T[(s,c,j)][x'] = sum_i v[s][c][j n + i]
+// Fx2[i][x'] (FP32 T, as the training forward).  One wave per (s, j)
+// computes the 32 x 32 block D[x'][c] on matrix cores straight from global
+// memory: A (x', 8 consecutive i) from the bf16 table FxH, B (8 consecutive
+// i, channel c) from row j of channel c of v, one 16-byte load each (n a
+// multiple of 8: rows start on 16-byte boundaries).
+__global__ __launch_bounds__(256) void k_dftx_h(const __bf16* __restrict__ v, const __bf16* __restrict__ FxH,
+                                                float* __restrict__ T, int n, int rows) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= rows) return;  // whole waves
+  const int s = w / n, j = w % n;
+  const long long P = (long long)n * n;
+  const int r16 = lane & 15, g4 = lane >> 4, kq = g4 * 8;
+  const __bf16* vb = v + (long long)s * kW * P + (long long)j * n;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i0 = 0; i0 < n; i0 += 32) {
+    const int valid = n - (i0 + kq);
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      a[q] = ld8(FxH, (long long)(16 * q + r16) * n + i0 + kq, valid, true);
+      b[q] = ld8(vb, (long long)(16 * q + r16) * P + i0 + kq, valid, true);
+    }
+#pragma unroll
+    for (int xb = 0; xb < 2; ++xb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[xb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[xb], b[cb], acc[xb][cb], 0, 0, 0);
+  }
+  // lane holds D[x' = 16 xb + 4 g4 + t][c = 16 cb + r16]: 4 consecutive x'
+#pragma unroll
+  for (int xb = 0; xb < 2; ++xb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int c = 16 * cb + r16, x0 = 16 * xb + 4 * g4;
+      *reinterpret_cast<float4*>(&T[(((long long)s * kW + c) * n + j) * 32 + x0]) =
+          make_float4(acc[xb][cb][0], acc[xb][cb][1], acc[xb][cb][2], acc[xb][cb][3]);
+    }
+}
+
+// Fourier layer output for inference: z = U Gx + W v + b for one row j of
+// one sample and kTP pixels, as k_layer_out, then GELU(z) (or z for the
+// last layer) in bf16.  The A operands (rows of U and W, 8 consecutive K)
+// and the Gx operand (table GxH: 8 consecutive modes of one pixel) are
+// 16-byte loads from global memory; v's operand (8 consecutive channels of
+// one pixel) is gathered from the tile staged in LDS, which then holds the
+// output tile for 16-byte stores.
+__global__ __launch_bounds__(256) void k_layer_out_h(const float* __restrict__ U, const __bf16* __restrict__ GxH,
+                                                     const float* __restrict__ Wt, const float* __restrict__ bias,
+                                                     const __bf16* __restrict__ v, __bf16* __restrict__ out, int n,
+                                                     int gelu) {
+  __shared__ __attribute__((aligned(16))) __bf16 Vs[kW * kLDV];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * kTP, j = blockIdx.y, s = blockIdx.z;
+  const long long P = (long long)n * n, base = (long long)s * kW * P + (long long)j * n + i0;
+  const bool al = (n & 7) == 0;
+  stage_tile(Vs, v + base, P, 0, n - i0, al, tid);
+  const int r16 = lane & 15, g4 = lane >> 4, kq = g4 * 8;
+  bf16x8 au[2], aw[2], bg[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int o = 16 * a + r16;
+    au[a] = f8_to_bf(&U[(((long long)s * kW + o) * n + j) * 32 + kq]);
+    aw[a] = f8_to_bf(&Wt[o * kW + kq]);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int i = i0 + 32 * wave + 16 * cb + r16;
+    bg[cb] = i < n ? *reinterpret_cast<const bf16x8*>(&GxH[(long long)i * 32 + kq]) : bf16x8{};
+  }
+  __syncthreads();
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const bf16x8 bv = gather8(Vs, kq, 32 * wave + 16 * cb + r16);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      acc[a][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(au[a], bg[cb], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      acc[a][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[a], bv, acc[a][cb], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // the tile is reused for the output
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int o = 16 * a + 4 * g4 + t;
+        const float val = acc[a][cb][t] + bias[o];
+        Vs[o * kLDV + 32 * wave + 16 * cb + r16] = (__bf16)(gelu ? gelu_as(val) : val);
+      }
+  __syncthreads();
+  store_tile(out + base, Vs, P, 0, n - i0, al, tid);
+}
+
+// Inference output head and residual map in one pass over the last
+// Fourier layer's output v: hid = GELU(P1 v + b1) (128 channels, a K = 32
+// product on matrix cores per 16 x 16 block), y = P2 hid + b2 (FP32 sums of
+// the GELU values), z = r + s (y0 + i y1).  A workgroup takes kTP pixels of
+// one sample (staged in LDS as in k_layer_out_h); wave w owns pixels
+// [32 w, 32 w + 32) against all 128 hidden channels.  In a block a lane
+// holds 4 hidden channels of one pixel (rows 4 (lane / 16) + t of column
+// lane % 16), so each lane sums its share of the two 128-term projections
+// and the four lane groups of a column finish the sums with lane shuffles.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_head(const __bf16* __restrict__ v, const float* __restrict__ W1,
+                                                 const float* __restrict__ b1, const float* __restrict__ W2,
+                                                 const float* __restrict__ b2, const T* __restrict__ r,
+                                                 const double* __restrict__ s, T* __restrict__ z, long long P) {
+  __shared__ __attribute__((aligned(16))) __bf16 Vs[kW * kLDV];
+  __shared__ float sb1[kH], sw2[kOut * kH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long p0 = (long long)blockIdx.x * kTP;
+  const int b = blockIdx.y;
+  for (int e = tid; e < kH; e += 256) sb1[e] = b1[e];
+  for (int e = tid; e < kOut * kH; e += 256) sw2[e] = W2[e];
+  stage_tile(Vs, v + (long long)b * kW * P, P, p0, P - p0, (P & 7) == 0, tid);
+  __syncthreads();
+  const int r16 = lane & 15, g4 = lane >> 4, kq = g4 * 8;
+  bf16x8 bv[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) bv[j] = gather8(Vs, kq, 32 * wave + 16 * j + r16);
+  float y0[2] = {0.f, 0.f}, y1[2] = {0.f, 0.f};
+#pragma unroll 2
+  for (int a = 0; a < kH / 16; ++a) {
+    const bf16x8 av = f8_to_bf(&W1[(a * 16 + r16) * kW + kq]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int h = a * 16 + g4 * 4 + t;
+        const float g = gelu_as(acc[t] + sb1[h]);
+        y0[j] = fmaf(sw2[h], g, y0[j]);
+        y1[j] = fmaf(sw2[kH + h], g, y1[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    y0[j] += __shfl_xor(y0[j], 16);
+    y0[j] += __shfl_xor(y0[j], 32);
+    y1[j] += __shfl_xor(y1[j], 16);
+    y1[j] += __shfl_xor(y1[j], 32);
+  }
+  // lane group j < 2 writes the pixels of block column j
+  if (g4 < 2) {
+    const long long p = p0 + 32 * wave + 16 * g4 + r16;
+    if (p < P) {
+      const double sc = s[b];
+      const T rv = r[b * P + p];
+      T o;
+      o.x = rv.x + sc * (double)((g4 ? y0[1] : y0[0]) + b2[0]);
+      o.y = rv.y + sc * (double)((g4 ? y1[1] : y1[0]) + b2[1]);
+      z[b * P + p] = o;
+    }
   }
 }
 
@@ -619,6 +901,8 @@ struct FnoTables {
   float* Fa = nullptr;   // [64][n]
   float* Fb = nullptr;   // [64][n]
   float* Ai = nullptr;   // [n][64]
+  __bf16* FxH = nullptr;  // [32][n] bf16
+  __bf16* GxH = nullptr;  // [n][32] bf16
 };
 
 struct ls_fno {
@@ -695,10 +979,12 @@ ls_status tables_for(ls_fno* f, int n, FnoTables** out) {
     FnoTables t;
     LS_TRY(fno_alloc(f, (void**)&t.Fx2, sizeof(float) * n * 32));
     LS_TRY(fno_alloc(f, (void**)&t.Gx, sizeof(float) * n * 32));
-    LS_TRY(fno_alloc(f, (void**)&t.Fa, sizeof(float) * n * 64));
-    LS_TRY(fno_alloc(f, (void**)&t.Fb, sizeof(float) * n * 64));
+    LS_TRY(fno_alloc(f, (void**)&t.Fa, sizeof(float) * n * 128));  // Fa then Fb, adjacent
+    t.Fb = t.Fa + (size_t)64 * n;
     LS_TRY(fno_alloc(f, (void**)&t.Ai, sizeof(float) * n * 64));
-    k_tables<<<(n + 127) / 128, 128, 0, f->stream>>>(n, t.Fx2, t.Gx, t.Fa, t.Fb, t.Ai);
+    LS_TRY(fno_alloc(f, (void**)&t.FxH, sizeof(__bf16) * n * 64));  // FxH then GxH
+    t.GxH = t.FxH + (size_t)32 * n;
+    k_tables<<<(n + 127) / 128, 128, 0, f->stream>>>(n, t.Fx2, t.Gx, t.Fa, t.Fb, t.Ai, t.FxH, t.GxH);
     LS_HIP(hipGetLastError());
     it = f->tables.emplace(n, t).first;
   }
@@ -708,13 +994,30 @@ ls_status tables_for(ls_fno* f, int n, FnoTables** out) {
 
 inline const float* par(const ls_fno* f, int blk) { return f->params + f->off[blk]; }
 
+// Vh[s,c] = (Fa T_re + Fb T_im) / n^2: one product over K = 2n when n is a
+// multiple of the K tile (Fa and Fb adjacent; the second K segment reads
+// T's imaginary columns), else two products.
+ls_status vh_gemm(ls_fno* f, const FnoTables* tb, int n, int S, float* Vh) {
+  const float inv_n2 = 1.f / (float)((double)n * n);
+  if (n % 32 == 0) {
+    GemmP g = gp(64, kM, 2 * n, tb->Fa, n, 1, 0, f->T, 32, 1, (long long)n * 32, Vh, kM, 1, 64 * kM, inv_n2, 0.f);
+    g.kseg = n;
+    g.sag = (long long)64 * n;
+    g.sbg = kM;
+    return gemm(g, S * kW, f->stream);
+  }
+  LS_TRY(gemm(gp(64, kM, n, tb->Fa, n, 1, 0, f->T, 32, 1, (long long)n * 32, Vh, kM, 1, 64 * kM, inv_n2, 0.f),
+              S * kW, f->stream));
+  return gemm(gp(64, kM, n, tb->Fb, n, 1, 0, f->T + kM, 32, 1, (long long)n * 32, Vh, kM, 1, 64 * kM, inv_n2, 1.f),
+              S * kW, f->stream);
+}
+
 // y = network(x); keep: store every activation for backward.
 ls_status forward(ls_fno* f, int n, int S, const float* x, float* y, bool keep) {
   hipStream_t st = f->stream;
   FnoTables* tb;
   LS_TRY(tables_for(f, n, &tb));
   const long long P = (long long)n * n;
-  const float inv_n2 = 1.f / (float)((double)n * n);
   // buffers: with keep every layer has its own v / z; without, two rotate
   float* vin = f->v[0];
   LS_TRY(gemm(gp(kW, (int)P, kIn, par(f, P_LIFT_W), kIn, 1, 0, x, P, 1, kIn * P, vin, P, 1, kW * P, 1.f, 0.f,
@@ -725,11 +1028,7 @@ ls_status forward(ls_fno* f, int n, int S, const float* x, float* y, bool keep) 
     float* Vh = keep ? f->Vh[l] : f->Vh[0];
     // T[(s,c,j)][x'] = sum_i v[(s,c,j)][i] Fx2[i][x']
     LS_TRY(gemm(gp(S * kW * n, 32, n, vin, n, 1, 0, tb->Fx2, 32, 1, 0, f->T, 32, 1, 0), 1, st));
-    // Vh[s,c] = (Fa T_re + Fb T_im) / n^2
-    LS_TRY(gemm(gp(64, kM, n, tb->Fa, n, 1, 0, f->T, 32, 1, (long long)n * 32, Vh, kM, 1, 64 * kM, inv_n2, 0.f),
-                S * kW, st));
-    LS_TRY(gemm(gp(64, kM, n, tb->Fb, n, 1, 0, f->T + kM, 32, 1, (long long)n * 32, Vh, kM, 1, 64 * kM, inv_n2, 1.f),
-                S * kW, st));
+    LS_TRY(vh_gemm(f, tb, n, S, Vh));
     k_modemix<<<kKZ * kM, 256, 0, st>>>(Vh, par(f, lb(l, 0)), par(f, lb(l, 1)), f->Bst, S);
     LS_HIP(hipGetLastError());
     // U[s,o] = Ai Bst[s,o]
@@ -858,6 +1157,53 @@ ls_status check_sizes(const ls_fno* f, int n, int S) {
   return LS_OK;
 }
 
+// Inference on S <= max_batch samples straight from the raw inputs to the
+// residual map z = r + s (y0 + i y1): the scale s, the lift, the four
+// Fourier layers with bf16 activations (the two buffers v[0], v[1] hold
+// them at half their FP32 size) and the fused output head.  The same
+// network as forward(); the lift and the last projection run in FP32
+// instead of bf16 products.
+template <typename T>
+ls_status infer(ls_fno* f, int n, int S, const double* m, size_t mstr, const double* uI, const T* r, T* z) {
+  hipStream_t st = f->stream;
+  FnoTables* tb;
+  LS_TRY(tables_for(f, n, &tb));
+  const long long P = (long long)n * n;
+  const int parts = 64;
+  k_sq_partial<T><<<dim3(parts, S), 256, 0, st>>>(r, P, f->part);
+  k_rms<<<(S + 63) / 64, 64, 0, st>>>(f->part, parts, n, f->s, S);
+  __bf16* act[2] = {reinterpret_cast<__bf16*>(f->v[0]), reinterpret_cast<__bf16*>(f->v[1])};
+  k_lift_in<T><<<dim3((unsigned)((P + 255) / 256), S), 256, 0, st>>>(m, mstr, reinterpret_cast<const cplx*>(uI), r,
+                                                                 f->s, par(f, P_LIFT_W), par(f, P_LIFT_B), act[0],
+                                                                 (size_t)P);
+  LS_HIP(hipGetLastError());
+  for (int l = 0; l < kL; ++l) {
+    const __bf16* vin = act[l % 2];
+    __bf16* vout = act[(l + 1) % 2];
+    if (n % 8 == 0) {
+      k_dftx_h<<<(S * n + 3) / 4, 256, 0, st>>>(vin, tb->FxH, f->T, n, S * n);
+      LS_HIP(hipGetLastError());
+    } else {  // rows off 16-byte boundaries: the generic product
+      GemmP gt = gp(S * kW * n, 32, n, nullptr, n, 1, 0, tb->Fx2, 32, 1, 0, f->T, 32, 1, 0);
+      gt.Ah = vin;
+      LS_TRY(gemm(gt, 1, st));
+    }
+    LS_TRY(vh_gemm(f, tb, n, S, f->Vh[0]));
+    k_modemix<<<kKZ * kM, 256, 0, st>>>(f->Vh[0], par(f, lb(l, 0)), par(f, lb(l, 1)), f->Bst, S);
+    LS_HIP(hipGetLastError());
+    LS_TRY(gemm(gp(n, 32, 64, tb->Ai, 64, 1, 0, f->Bst, 32, 1, 64 * 32, f->U, 32, 1, (long long)n * 32), S * kW, st));
+    // the last layer's output is z itself (no GELU)
+    k_layer_out_h<<<dim3((n + kTP - 1) / kTP, n, S), 256, 0, st>>>(f->U, tb->GxH, par(f, lb(l, 2)), par(f, lb(l, 3)),
+                                                                  vin, vout, n, l < kL - 1);
+    LS_HIP(hipGetLastError());
+  }
+  k_head<T><<<dim3((unsigned)((P + kTP - 1) / kTP), S), 256, 0, st>>>(
+      act[kL % 2], par(f, P_PROJ1_W), par(f, P_PROJ1_B), par(f, P_PROJ2_W), par(f, P_PROJ2_B), r, f->s, z, P);
+  LS_HIP(hipGetLastError());
+  f->kept_n = f->kept_S = 0;
+  return LS_OK;
+}
+
 }  // namespace
 
 // Residual map for the solver (complex type T): z = r + s (y0 + i y1), for
@@ -870,11 +1216,7 @@ ls_status fno_residual_map(ls_fno* f, int n, int S, const double* m, size_t mstr
   const size_t P = (size_t)n * n;
   for (int b0 = 0; b0 < S; b0 += f->max_batch) {
     const int B = std::min(f->max_batch, S - b0);
-    const T* rb = r + b0 * P;
-    LS_TRY(make_inputs_t<T>(f, n, B, m + b0 * mstr, mstr, uI + 2 * b0 * P, rb, f->x, f->s));
-    LS_TRY(forward(f, n, B, f->x, f->y, false));
-    k_output<T><<<dim3(grid_for(P, 256, 1024), B), 256, 0, f->stream>>>(rb, f->y, f->s, z + b0 * P, P);
-    LS_HIP(hipGetLastError());
+    LS_TRY(infer<T>(f, n, B, m + b0 * mstr, mstr, uI + 2 * b0 * P, r + b0 * P, z + b0 * P));
   }
   return LS_OK;
 }

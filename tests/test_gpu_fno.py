@@ -169,18 +169,44 @@ def test_training_steps_reduce_the_loss(net):
     assert losses[-1] < 0.7 * losses[0]
 
 
-def test_apply_is_the_residual_map(net):
-    n = 48
+@pytest.mark.parametrize("n", [33, 40, 48, 64])
+def test_apply_is_the_residual_map(net, n):
+    """ls_fno_apply runs the inference path (bf16 activations, lift from the
+    raw inputs, fused output head): n = 33 has rows and a grid off 16-byte
+    boundaries (element-wise loads and stores, the generic x product),
+    n = 40 leaves ragged last pixel tiles (P = 1600), n = 48 takes the
+    z-transform as two products (n not a multiple of 32), n = 64 as one."""
     p, flat = _params(seed=13)
     net.set_params(flat)
-    ms, uIs, rs = _inputs(n, 2, 4000)
+    ms, uIs, rs = _inputs(n, 3, 4000 + n)
     z = host(net.apply(dev(ms[0], torch.float64), dev(uIs), dev(rs)))
-    for k in range(2):
+    for k in range(3):
         z_ref = ofno.apply(p, ms[0], uIs[k], rs[k])
         # the correction z - r carries the network's error; r passes exactly
         e = rel(z[k] - rs[k], z_ref - rs[k])
-        banner(f"apply k={k} correction rel err {e:.3e}")
+        banner(f"apply n={n} k={k} correction rel err {e:.3e}")
         assert e < TOL
+
+
+@pytest.mark.parametrize("n", [36, 64])
+def test_inference_path_is_the_training_forward(net, n):
+    """The inference path and the training forward (FP32 activations kept
+    for backward, lift and projection as bf16 products) evaluate the same
+    network: the corrections agree to the bf16 rounding of the products
+    (measured ~3e-3), and the FP64 residual r passes unchanged."""
+    p, flat = _params(seed=19)
+    net.set_params(flat)
+    ms, uIs, rs = _inputs(n, 3, 4500 + n)
+    md, uId, rd = dev(ms[0], torch.float64), dev(uIs), dev(rs)
+    z = host(net.apply(md, uId, rd))
+    x, s = net.make_inputs(md, uId, rd)
+    y = host(net.forward(x))
+    sh = host(s)
+    for k in range(3):
+        corr = sh[k] * (y[k, 0].astype(np.float64) + 1j * y[k, 1].astype(np.float64))
+        e = rel(z[k] - rs[k], corr)
+        banner(f"inference vs training forward n={n} k={k}: correction rel diff {e:.3e}")
+        assert e < 1.5e-2
 
 
 def _solve_problem(n=64, seed=5000, batch=2):

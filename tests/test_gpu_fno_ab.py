@@ -67,7 +67,8 @@ def _timed(fn):
 def test_warm_start_gain_at_training_size(trained):
     """256^2, held-out media: the network's initial guess leaves a residual
     well below ||f|| (u0 = 0 leaves exactly ||f||), and the warm-started
-    solve needs no more outer iterations than the plain one."""
+    solves need fewer outer iterations in total than the plain ones
+    (measured 24 against 26 over the four media)."""
     from paper_1602_07652_amd import Plan
     fno, _, _ = trained
     n = 256
@@ -95,7 +96,49 @@ def test_warm_start_gain_at_training_size(trained):
     banner(f"256^2 totals: plain {its_p} outer its, warm-started {its_w}; mean warm residual "
            f"{np.mean(r0s):.3f}")
     assert np.mean(r0s) < 0.6
-    assert its_w <= its_p
+    assert its_w < its_p
+
+
+def test_learned_arm_gain_on_64_waves():
+    """The learned form's job at its training size, as bench.py runs it: 64
+    plane waves (theta_k = 2 pi k / 64) on a held-out 256^2 GRF medium, FP32
+    operator and slab solves with FP64 refinement, the network (64 samples
+    per evaluation) as warm start with the probe.  Every wave of both arms
+    reaches 1e-8 (the oracle's FP64 residual checks sampled waves), and the
+    learned arm needs strictly fewer outer iterations in total (measured 6
+    against 7 per wave; wall times are printed: 35.3 against 37.8 ms)."""
+    from paper_1602_07652_amd import Plan, Fno, LS_FP32_REFINE, LS_FNO_WARM, LS_FNO_PROBE
+    from paper_1602_07652_amd.fno_train import load_weights
+    params, _ = load_weights(WEIGHTS)
+    n, B = 256, 64
+    omega = 2 * np.pi * n / 10
+    m = li.gaussian_random_field_medium(n, seed=5000)
+    plan = Plan(n, 1.0 / n, omega, dev(m, torch.float64), slabs=n // 64, ext=10, max_batch=B,
+                precision=LS_FP32_REFINE)
+    net = Fno(max_batch=B, max_n=n)
+    net.set_params(params)
+    uI = np.stack([li.plane_wave(n, omega, 2 * np.pi * k / B) for k in range(B)])
+    uId = dev(uI)
+    f = plan.rhs_from_incident(uId)
+    arms = {}
+    for arm in ("plain", "learned"):
+        run = (lambda: plan.solve(f, tol=1e-8)) if arm == "plain" else \
+              (lambda: plan.solve_fno(net, uId, f, tol=1e-8, mode=LS_FNO_WARM | LS_FNO_PROBE))
+        run()  # warm-up: graphs, Krylov spaces
+        (u, infos), t = _timed(run)
+        its = sum(i["outer_its"] for i in infos)
+        arms[arm] = (host(u), infos, its, t)
+        banner(f"64 waves at 256^2, {arm}: {its} outer its in total, {t * 1e3:.1f} ms, "
+               f"max relres {max(i['relres_true'] for i in infos):.2e}")
+        assert all(i["converged"] == 1 and i["relres_true"] <= 1e-8 for i in infos)
+    for k in (0, 37):
+        res = _oracle_residual(n, omega, m, uI[k], arms["learned"][0][k])
+        banner(f"learned arm wave {k}: oracle residual {res:.2e} (flags {arms['learned'][1][k]['fno_flags']})")
+        assert res < 2e-8
+    assert all(i["fno_flags"] & 1 for i in arms["learned"][1])  # every warm start kept
+    assert arms["learned"][2] < arms["plain"][2]
+    net.close()
+    plan.close()
 
 
 @pytest.mark.parametrize("n", [512, 1024])
