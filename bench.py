@@ -58,13 +58,24 @@ def slab_solve_bytes(n, q):
     return 16 * (n * q * (3 * q + 4) + 2 * n * q)
 
 
-def apply_bytes(n, batch):
+def apply_bytes(n, batch, cb=16, rb=8):
     """Algorithmic bytes of ls_apply: per right-hand side read v, write/read
-    the n x 2n intermediate twice each way, re-read v, write y (11 n^2 c128);
-    per batch the medium (n^2 doubles) and the stored quarter spectrum
-    ((n+1)^2 c128)."""
+    the n x 2n intermediate twice each way, re-read v, write y (11 n^2
+    complex values of cb bytes); per batch the medium (n^2 reals of rb
+    bytes) and the stored quarter spectrum ((n+1)^2 complex).  FP64: cb = 16,
+    rb = 8; the FP32 operator: cb = 8, rb = 4."""
     P = 2 * n
-    return batch * 11 * n * n * 16 + n * n * 8 + (P // 2 + 1) ** 2 * 16
+    return batch * 11 * n * n * cb + n * n * rb + (P // 2 + 1) ** 2 * cb
+
+
+def apply_io_bytes(n, batch, cb=16, rb=8):
+    """The part of apply_bytes that is the operation's own input and output
+    (v read once, y written, the medium, the spectrum): what has to cross
+    HBM whatever the cache.  The rest (the intermediate's four passes and
+    v's second read) is what the chunked apply keeps within the 256 MB
+    Infinity Cache."""
+    P = 2 * n
+    return batch * 2 * n * n * cb + n * n * rb + (P // 2 + 1) ** 2 * cb
 
 
 def cpu_baseline(cfg, L, ext, tol):
@@ -405,25 +416,49 @@ def fno_flops(n, S):
     return 2 * S * P * 5 * W + 4 * layer + 2 * S * P * (W * Hd + Hd * 2)
 
 
+def fno_infer_bytes(n, S):
+    """Algorithmic HBM bytes of one inference pass (ls_fno_apply) on S
+    samples of n x n: the lift reads uI and r (c128) and writes v0; each of
+    the 4 layers reads its input twice (x transform, pointwise map) and
+    writes its output (32 bf16 channels), and moves T and U (S 32 n 32 FP32
+    each, written once, read once); the head reads the last layer's output
+    and r and writes z (c128)."""
+    P = n * n
+    act = S * P * 32 * 2
+    tu = S * 32 * n * 32 * 4
+    return (S * P * 32 + act) + 4 * (3 * act + 4 * tu) + (act + S * P * 32)
+
+
 def fno_variant(log_fn, weights):
     """Timing of the network's kernels: one training step (forward with
-    stored activations, loss, backward, Adam) on 16 samples of 256^2, and
-    inference on 8 samples of 1024^2; flops from fno_flops (backward counted
-    as twice the forward)."""
+    stored activations, loss, backward, Adam) on 16 samples of 256^2, and the
+    inference path the solver uses (ls_fno_apply: the residual map) on 64
+    samples of 256^2, the learned form's warm start for 64 waves; flops from
+    fno_flops (backward counted as twice the forward), inference bytes from
+    fno_infer_bytes."""
     import numpy as np
     import torch
+    import ls_inputs as li
     from paper_1602_07652_amd import Fno
     from paper_1602_07652_amd.fno_train import load_weights
     dev = torch.device("cuda:0")
     params, _ = load_weights(weights)
     out = {}
-    for n, S, train in ((256, 16, True), (1024, 8, False)):
+    for n, S, train in ((256, 16, True), (256, 64, False)):
         net = Fno(max_batch=S, max_n=n)
         net.set_params(params)
         g = torch.Generator(device=dev).manual_seed(0)
-        x = torch.randn((S, 5, n, n), device=dev, generator=g)
-        t = torch.randn((S, 2, n, n), device=dev, generator=g)
         grad = torch.empty(net.nparams, dtype=torch.float32, device=dev)
+        if train:
+            x = torch.randn((S, 5, n, n), device=dev, generator=g)
+            t = torch.randn((S, 2, n, n), device=dev, generator=g)
+        else:
+            omega = 2 * np.pi * n / 10
+            m = torch.from_numpy(li.gaussian_random_field_medium(n, seed=5000)).to(dev)
+            uI = torch.from_numpy(np.stack([li.plane_wave(n, omega, 2 * np.pi * k / S)
+                                            for k in range(S)])).to(dev)
+            r = torch.randn((S, n, n), dtype=torch.complex128, device=dev, generator=g)
+            z = torch.empty_like(r)
 
         def step(k):
             if train:
@@ -432,7 +467,7 @@ def fno_variant(log_fn, weights):
                 net.backward(dy, grad)
                 net.adam(grad, 1e-6, k)
             else:
-                net.forward(x)
+                net.apply(m, uI, r, out=z)
         for k in range(1, 3):
             step(k)
         torch.cuda.synchronize()
@@ -443,10 +478,16 @@ def fno_variant(log_fn, weights):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / reps * 1e3
         fl = fno_flops(n, S) * (3 if train else 1)
-        key = f"{'train_step' if train else 'inference'}_{n}x{n}_S{S}"
+        key = f"{'train_step' if train else 'inference_residual_map'}_{n}x{n}_S{S}"
         out[key] = {"ms": ms, "gflop": fl / 1e9, "tflops": fl / (ms * 1e-3) / 1e12,
                     "mfma_frac_of_bf16_peak": fl / (ms * 1e-3) / 2.5e15}
-        log_fn(f"fno {key}: {ms:.2f} ms, {fl / 1e9:.1f} GFLOP, {fl / (ms * 1e-3) / 1e12:.1f} TFLOP/s")
+        msg = f"fno {key}: {ms:.2f} ms, {fl / 1e9:.1f} GFLOP, {fl / (ms * 1e-3) / 1e12:.1f} TFLOP/s"
+        if not train:
+            by = fno_infer_bytes(n, S)
+            out[key].update({"alg_bytes": by, "GBs": by / (ms * 1e-3) / 1e9,
+                             "hbm_frac": by / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)})
+            msg += f", {by / 1e9:.2f} GB, {by / (ms * 1e-3) / 1e9:.0f} GB/s"
+        log_fn(msg)
         net.close()
     return out
 
@@ -624,7 +665,9 @@ def main():
     ev1.synchronize()
     apply_ms = ev0.elapsed_time(ev1) / reps
     apply_gbs = apply_bytes(n, B) / (apply_ms * 1e-3) / 1e9
-    log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic")
+    apply_io_gbs = apply_io_bytes(n, B) / (apply_ms * 1e-3) / 1e9
+    log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic "
+        f"({apply_io_gbs:.0f} GB/s of input and output)")
 
     plan.close()
     # the same solve with the sequential sweeps (Alg. 1 as written)
@@ -647,7 +690,7 @@ def main():
     # the same workload with FP32 operator and slab solves and FP64 refinement
     from paper_1602_07652_amd import LS_FP32_REFINE
     t0 = time.perf_counter()
-    p32 = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, precision=LS_FP32_REFINE)
+    p32 = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, precision=LS_FP32_REFINE, max_batch=8)
     torch.cuda.synchronize()
     setup32 = time.perf_counter() - t0
     p32.solve(f, tol=args.tol, out=u)
@@ -656,6 +699,19 @@ def main():
     infos32 = [p32.solve(f, tol=args.tol, out=u)[1][0] for _ in range(args.steps)]
     torch.cuda.synchronize()
     el32 = time.perf_counter() - t0
+    # the FP32 operator (ls_apply_c64) on the same batch of 8
+    v32 = vb.to(torch.complex64)
+    y32 = torch.empty_like(v32)
+    for _ in range(2):
+        p32.apply_c64(v32, out=y32)
+    ev0.record(p32.stream)
+    for _ in range(reps):
+        p32.apply_c64(v32, out=y32)
+    ev1.record(p32.stream)
+    ev1.synchronize()
+    apply32_ms = ev0.elapsed_time(ev1) / reps
+    apply32_gbs = apply_bytes(n, B, 8, 4) / (apply32_ms * 1e-3) / 1e9
+    log(f"ls_apply_c64 batch {B}: {apply32_ms:.3f} ms, {apply32_gbs:.0f} GB/s algorithmic")
     p32.close()
     fp32_single = {"workload": "the plain workload with FP32 operator and slab solves, FP64 refinement",
                    "solves_per_s": args.steps / el32, "ms_per_solve": 1e3 * el32 / args.steps,
@@ -700,6 +756,9 @@ def main():
             "setup_s": setup_s,
             "fft_matvec_GBs": apply_gbs,
             "fft_matvec_ms_batch8": apply_ms,
+            "fft_matvec_io_GBs": apply_io_gbs,
+            "fft_matvec_fp32_GBs": apply32_gbs,
+            "fft_matvec_fp32_ms_batch8": apply32_ms,
         },
         "roofline": {
             "kernel": "slab solve (block cyclic reduction, q=%d)" % q,

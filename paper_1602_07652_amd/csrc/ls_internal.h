@@ -231,14 +231,18 @@ struct ls_plan {
   // circulant, stencils, spectrum, slab assembly, slab factorisation, top
   // operators, trace-transfer maps, FFT autotuning, whole ls_plan_create
   double stage_ms[9] = {};
-  // decoupled sweep: side streams for the independent local solves, their
-  // fork / join events and per-stream scratch (elimination, solution)
+  // decoupled sweep: the layers of each orientation grouped by slab shape
+  // (same q and level structure: one multi-slab launch per level step and
+  // group), every layer's elimination scratch [L][n][set_qmax] in the
+  // plan's precision, and side streams (with fork / join events) that run
+  // the groups after the first concurrently
+  std::vector<std::vector<int>> dec_groups[2];
+  void* set_elim = nullptr;
+  int set_qmax = 0;
   static constexpr int kSide = 4;
   hipStream_t side[kSide] = {};
   hipEvent_t side_fork = nullptr;
   hipEvent_t side_join[kSide] = {};
-  void* side_elim[kSide] = {};
-  void* side_work[kSide] = {};
 };
 
 inline ApplyView<cplx, double> view64(ls_plan* p) {

@@ -282,13 +282,34 @@ inline int row_splits(int q, int t, int ncol) {
 //   R_LAST  top level:       y_0 = Dinv t_0
 //   R_BWD   level l, k odd:  y_k = Dinv_k t_k - (Dinv L)_k y_{k-1} - (Dinv U)_k y_{k+1}
 //   R_BWD0  level 0, k odd:  y_k -= Dinv_k t_k, t_k = L_k y_{k-1} + U_k y_{k+1} (k_odd0_lu)
+// Slabs of one launch: the one-right-hand-side steps run the same level
+// step (same q and level structure: the factor blocks of a level at the
+// same offsets) for up to kSet slabs at once, blockIdx.y (k_rstep, k_top)
+// or blockIdx.z (k_even0, k_odd0_lu) picking the slab; a single solve is a
+// set of one.
+constexpr int kSet = 16;
+template <typename C>
+struct SlabSet {
+  const C* g[kSet];    // right-hand sides [n][q]
+  C* t[kSet];          // elimination scratch [n][q]
+  C* y[kSet];          // solutions [n][q]
+  const C* fac[kSet];  // factors (level offsets shared by the set)
+  const C* coef[kSet];
+  const C* top[kSet];  // dense top operators (or null)
+};
+
 template <typename C, int MODE>
-__global__ __launch_bounds__(256, 4) void k_rstep(const C* __restrict__ g, C* __restrict__ t, C* __restrict__ y,
-                                              const C* __restrict__ m0, const C* __restrict__ m1,
-                                              const C* __restrict__ m2, const C* __restrict__ coef, int n,
-                                              int q, int nl, int shift, int RS) {
+__global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_t o1, size_t o2, int n, int q,
+                                              int nl, int shift, int RS) {
   __shared__ C xs[3 * kMaxQ];
   __shared__ C part[256];
+  const int z = blockIdx.y;
+  const C* __restrict__ g = S.g[z];
+  C* __restrict__ t = S.t[z];
+  C* __restrict__ y = S.y[z];
+  const C* __restrict__ m0 = S.fac[z] + o0;
+  const C* __restrict__ m1 = S.fac[z] + o1;
+  const C* __restrict__ m2 = S.fac[z] + o2;
   // the RS row tiles of a block on one XCD: they share the 128-byte lines
   // that straddle tile boundaries through that XCD's L2
   const int lid = bstep_remap(blockIdx.x, gridDim.x);
@@ -376,10 +397,13 @@ __global__ __launch_bounds__(256, 4) void k_rstep(const C* __restrict__ g, C* __
 // level 0, odd blocks: t_k = L_k y_{k-1} + U_k y_{k+1} (L, U from coef;
 // the odd rows of t are free once the forward elimination is done)
 template <typename C>
-__global__ void k_odd0_lu(const C* __restrict__ y, C* __restrict__ t, const C* __restrict__ coef, int n, int q) {
+__global__ void k_odd0_lu(SlabSet<C> S, int n, int q) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 2 * blockIdx.y + 1;
   if (r >= q) return;
+  const C* __restrict__ y = S.y[blockIdx.z];
+  C* __restrict__ t = S.t[blockIdx.z];
+  const C* __restrict__ coef = S.coef[blockIdx.z];
   const C* cf = coef + ((size_t)k * q + r) * 9;
   C acc = tmk<C>(0, 0);
   for (int dZ = -1; dZ <= 1; ++dZ) {
@@ -402,9 +426,11 @@ constexpr int kTopMax = kTopBlocks * kMaxQ;
 constexpr int kTopBatchMin = 16;  // right-hand sides from which batched solves use the top operator
 
 template <typename C>
-__global__ __launch_bounds__(256) void k_top(const C* __restrict__ top, const C* __restrict__ t,
-                                             C* __restrict__ y, int Nt, int q, int shift) {
+__global__ __launch_bounds__(256) void k_top(SlabSet<C> S, int Nt, int q, int shift) {
   __shared__ C tv[kTopMax];
+  const C* __restrict__ top = S.top[blockIdx.y];
+  const C* __restrict__ t = S.t[blockIdx.y];
+  C* __restrict__ y = S.y[blockIdx.y];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int o = blockIdx.x * 4 + w;
   C mv[kTopK];
@@ -462,11 +488,14 @@ __global__ void k_transpose_to(const cplx* __restrict__ in, T* __restrict__ out,
 
 // level 0, even blocks: t_k = g_k - L_k z_{k-1} - U_k z_{k+1} with z_j = y_j
 template <typename C>
-__global__ void k_even0(const C* __restrict__ g, const C* __restrict__ y, C* __restrict__ t,
-                        const C* __restrict__ coef, int n, int q) {
+__global__ void k_even0(SlabSet<C> S, int n, int q) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 2 * blockIdx.y;
   if (r >= q) return;
+  const C* __restrict__ g = S.g[blockIdx.z];
+  const C* __restrict__ y = S.y[blockIdx.z];
+  C* __restrict__ t = S.t[blockIdx.z];
+  const C* __restrict__ coef = S.coef[blockIdx.z];
   const C* cf = coef + ((size_t)k * q + r) * 9;
   C acc = g[(size_t)k * q + r];
   for (int dZ = -1; dZ <= 1; ++dZ) {
@@ -1175,31 +1204,6 @@ __global__ __launch_bounds__(256) void k_trace_step(T* __restrict__ out, const T
   }
 }
 
-// rhs += A ta (+ Bi tb): the two trace-source injections of one layer
-// (either may be absent: null trace).
-template <typename T>
-__global__ void k_inject_traces(T* __restrict__ rhs, const T* __restrict__ coef, int n, int q, TraceInj A,
-                                const T* __restrict__ ta, TraceInj Bi, const T* __restrict__ tb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int s = 0; s < 2; ++s) {
-    const TraceInj& J = s ? Bi : A;
-    const T* tr = s ? tb : ta;
-    if (!tr) continue;
-    for (int p = 0; p < 2; ++p) {
-      const T* cf = coef + ((size_t)i * q + J.rt[p]) * 9 + (J.dZ[p] + 1) * 3;
-      T acc = tmk<T>(0, 0);
-      for (int dX = -1; dX <= 1; ++dX) {
-        const int ii = i + dX;
-        if (ii < 0 || ii >= n) continue;
-        acc = tfma(cf[dX + 1], tr[(size_t)p * n + ii], acc);
-      }
-      T* o = rhs + (size_t)i * q + J.rt[p];
-      *o = tadd(*o, tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]));
-    }
-  }
-}
-
 // Horizontal slabs (grid rows are the slab's short axis), many right-hand
 // sides, no trace sources: the same copies as k_gather / k_scatter through
 // a 64 (i) x 32 (r) LDS tile, so that both the grid rows (i fastest) and the
@@ -1335,6 +1339,124 @@ __global__ __launch_bounds__(128) void k_scatter_h1(const T* __restrict__ src, T
     rhs[(size_t)t * qr + A.rt] = tadd(va, ta);
     rhs[(size_t)t * qr + Bj.rt] = tadd(vb, tb);
   }
+}
+
+// Per-layer arguments of the decoupled sweep's multi-layer launches
+// (blockIdx.z picks the layer): the layer's slab vector x (right-hand side
+// or solution, [n][q]), its matrix, frame, and the two trace injections
+// with their traces (null where the layer has no neighbour).
+template <typename T>
+struct LayerSet {
+  T* x[kSet];
+  const T* coef[kSet];
+  int q[kSet], z0[kSet], a[kSet], b[kSet];
+  TraceInj dn[kSet], up[kSet];
+  const T* tau[kSet];
+  const T* sig[kSet];
+};
+
+// x^l[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere, for
+// every layer of the set; horizontal slabs through 16 (i) x 32 (r) LDS
+// tiles as k_gather_h1 (grid rows read and slab rows written in runs).
+template <typename T>
+__global__ __launch_bounds__(128) void k_gather_set_h(const T* __restrict__ g, LayerSet<T> S, int n) {
+  __shared__ T tile[kTR][16 + 1];
+  const int z = blockIdx.z, q = S.q[z], z0 = S.z0[z], a = S.a[z], b = S.b[z];
+  const int i0 = blockIdx.x * 16, r0 = blockIdx.y * kTR;
+  if (r0 >= q) return;  // whole workgroup, before any barrier
+  T* __restrict__ dst = S.x[z];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < 16 * kTR / 128; ++e) {  // grid row Z = z0 + r, i fastest
+    const int ii = tid % 16, rr = tid / 16 + e * (128 / 16);
+    const int i = i0 + ii, Z = z0 + r0 + rr;
+    tile[rr][ii] = (i < n && r0 + rr < q && Z >= a && Z <= b) ? g[(size_t)Z * n + i] : tmk<T>(0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 16 * kTR / 128; ++e) {  // slab row i, r fastest
+    const int rr = tid % kTR, ii = tid / kTR + e * (128 / kTR);
+    const int i = i0 + ii, r = r0 + rr;
+    if (i < n && r < q) dst[(size_t)i * q + r] = tile[rr][ii];
+  }
+}
+
+// The same for vertical slabs (the short axis is the grid's fast axis).
+template <typename T>
+__global__ void k_gather_set_v(const T* __restrict__ g, LayerSet<T> S, int n) {
+  const int z = blockIdx.z, q = S.q[z];
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * q) return;
+  const int i = (int)(t / q), r = (int)(t % q), Z = S.z0[z] + r;
+  S.x[z][t] = (Z >= S.a[z] && Z <= S.b[z]) ? g[(size_t)i * n + Z] : tmk<T>(0, 0);
+}
+
+// x^l += E^l tau^{l+1} + F^l sigma^{l-1} for every layer of the set: line
+// part p of a trace enters row rt[p] of the layer through the stencil
+// couplings of row dZ[p], times sgn[p] (a null trace adds nothing).
+template <typename T>
+__global__ void k_inject_set(LayerSet<T> S, int n) {
+  const int z = blockIdx.z, i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int q = S.q[z];
+  const T* __restrict__ coef = S.coef[z];
+  T* __restrict__ rhs = S.x[z];
+  for (int s = 0; s < 2; ++s) {
+    const TraceInj& J = s ? S.up[z] : S.dn[z];
+    const T* tr = s ? S.sig[z] : S.tau[z];
+    if (!tr) continue;
+    for (int p = 0; p < 2; ++p) {
+      const T* cf = coef + ((size_t)i * q + J.rt[p]) * 9 + (J.dZ[p] + 1) * 3;
+      T acc = tmk<T>(0, 0);
+      for (int dX = -1; dX <= 1; ++dX) {
+        const int ii = i + dX;
+        if (ii < 0 || ii >= n) continue;
+        acc = tfma(cf[dX + 1], tr[(size_t)p * n + ii], acc);
+      }
+      T* o = rhs + (size_t)i * q + J.rt[p];
+      *o = tadd(*o, tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]));
+    }
+  }
+}
+
+// out(i, Z) (+)= x^l[i][Z - z0] for the layer lines Z in [a, b] of every
+// layer of the set (disjoint rows of out); horizontal slabs through LDS
+// tiles as k_scatter_h1.
+template <typename T>
+__global__ __launch_bounds__(128) void k_scatter_set_h(T* __restrict__ out, LayerSet<T> S, int n, int accumulate) {
+  __shared__ T tile[kTR][16 + 1];
+  const int z = blockIdx.z, q = S.q[z], z0 = S.z0[z], a = S.a[z], b = S.b[z];
+  const int i0 = blockIdx.x * 16, Z0 = a + blockIdx.y * kTR;
+  if (Z0 > b) return;  // whole workgroup, before any barrier
+  const T* __restrict__ src = S.x[z];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < 16 * kTR / 128; ++e) {  // slab row i, Z fastest
+    const int rr = tid % kTR, ii = tid / kTR + e * (128 / kTR);
+    const int i = i0 + ii, Z = Z0 + rr;
+    if (i < n && Z <= b) tile[rr][ii] = src[(size_t)i * q + (Z - z0)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 16 * kTR / 128; ++e) {  // grid row Z, i fastest
+    const int ii = tid % 16, rr = tid / 16 + e * (128 / 16);
+    const int i = i0 + ii, Z = Z0 + rr;
+    if (i < n && Z <= b) {
+      const size_t o = (size_t)Z * n + i;
+      out[o] = accumulate ? tadd(out[o], tile[rr][ii]) : tile[rr][ii];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_scatter_set_v(T* __restrict__ out, LayerSet<T> S, int n, int accumulate) {
+  const int z = blockIdx.z, a = S.a[z], rows = S.b[z] - a + 1;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * rows) return;
+  const int i = (int)(t / rows), Z = a + (int)(t % rows);
+  const T v = S.x[z][(size_t)i * S.q[z] + (Z - S.z0[z])];
+  const size_t o = (size_t)i * n + Z;
+  out[o] = accumulate ? tadd(out[o], v) : v;
 }
 
 __global__ void k_down_copy(const cplx* __restrict__ a, fcplx* __restrict__ b, size_t cnt) {
@@ -1747,6 +1869,21 @@ static ls_status build_maps(ls_plan* p, Slab& s, const cplx* fac, cplx* work, si
 
 // Layers (Section 3.1): t = n / L lines each, the first n mod L layers one
 // more; extension ext lines each side, clipped to the grid.
+// Two slabs can share multi-slab launches: same thickness, the same levels
+// (block counts and factor offsets) and the same top operator shape.
+static bool same_shape(const Slab& x, const Slab& y) {
+  if (x.q != y.q || x.levels.size() != y.levels.size() || x.top_level != y.top_level || x.top_n != y.top_n ||
+      x.fac_elems != y.fac_elems)
+    return false;
+  for (size_t l = 0; l < x.levels.size(); ++l) {
+    const SlabLevel &a = x.levels[l], &b = y.levels[l];
+    if (a.nl != b.nl || a.off_dinv != b.off_dinv || a.off_dinvl != b.off_dinvl || a.off_dinvu != b.off_dinvu ||
+        a.off_pm != b.off_pm || a.off_pp != b.off_pp)
+      return false;
+  }
+  return true;
+}
+
 ls_status slabs_build(ls_plan* p) {
   const int n = p->n, L = p->L, ext = p->opt.ext;
   const int t = n / L, rem = n % L;
@@ -1856,14 +1993,34 @@ ls_status slabs_build(ls_plan* p) {
     const size_t tr = (size_t)2 * L * 2 * n;
     if (p->fp32) LS_TRY(plan_alloc(p, (void**)&p->traces32, tr * sizeof(fcplx)));
     else LS_TRY(plan_alloc(p, (void**)&p->traces, tr * sizeof(cplx)));
-    // side streams (default priority) for the independent local solves
+    // layers grouped by slab shape (at most kSet per group), every layer's
+    // elimination scratch, side streams (default priority) for the groups
+    for (int o = 0; o < 2; ++o) {
+      std::vector<std::vector<int>>& G = p->dec_groups[o];
+      G.clear();
+      const std::vector<Slab>& S = p->slabs[o];
+      for (int l = 0; l < (int)S.size(); ++l) {
+        bool placed = false;
+        for (auto& grp : G)
+          if ((int)grp.size() < kSet && same_shape(S[grp[0]], S[l])) {
+            grp.push_back(l);
+            placed = true;
+            break;
+          }
+        if (!placed) G.push_back({l});
+      }
+      std::stable_sort(G.begin(), G.end(), [](const std::vector<int>& x, const std::vector<int>& y) {
+        return x.size() > y.size();
+      });
+    }
     const size_t esz = p->fp32 ? sizeof(fcplx) : sizeof(cplx);
+    const size_t Lmax = std::max(p->slabs[0].size(), p->slabs[1].size());
+    p->set_qmax = qmax;
+    LS_TRY(plan_alloc(p, &p->set_elim, Lmax * n * qmax * esz));
     LS_HIP(hipEventCreateWithFlags(&p->side_fork, hipEventDisableTiming));
     for (int k = 0; k < ls_plan::kSide; ++k) {
       LS_HIP(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
       LS_HIP(hipEventCreateWithFlags(&p->side_join[k], hipEventDisableTiming));
-      LS_TRY(plan_alloc(p, &p->side_elim[k], (size_t)n * qmax * esz));
-      LS_TRY(plan_alloc(p, &p->side_work[k], (size_t)n * qmax * esz));
     }
   }
   const size_t wv = (size_t)n * qmax * p->opt.max_batch;
@@ -1934,16 +2091,16 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
   return LS_OK;
 }
 
-// One right-hand side: y = C_slab^{-1} g (g untouched, t scratch).
+// One right-hand side per slab: y = C_slab^{-1} g (g untouched, t scratch)
+// for the cnt <= kSet slabs of S, which share s's q and level structure.
 template <typename C>
-static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* top, const C* g,
-                            C* t, C* y) {
+static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, int cnt) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
-  auto step = [&](auto kern, auto mode, int nb, const C* a0, const C* a1, const C* a2, int nl, int shift) {
+  auto step = [&](auto kern, auto mode, int nb, size_t o0, size_t o1, size_t o2, int nl, int shift) {
     using RC = RCols<decltype(mode)::value>;
     const int RS = row_splits(q, RC::T, RC::N);
-    kern<<<nb * RS, 256, 0, p->stream>>>(g, t, y, a0, a1, a2, coef, n, q, nl, shift, RS);
+    kern<<<dim3(nb * RS, cnt), 256, 0, p->stream>>>(S, o0, o1, o2, n, q, nl, shift, RS);
   };
   using ModeOdd0 = std::integral_constant<int, R_ODD0>;
   using ModeFwd = std::integral_constant<int, R_FWD>;
@@ -1951,33 +2108,48 @@ static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* co
   using ModeBwd = std::integral_constant<int, R_BWD>;
   using ModeBwd0 = std::integral_constant<int, R_BWD0>;
   if (nlev == 1) {  // a single block row
-    LS_HIP(hipMemcpyAsync(t, g, sizeof(C) * q, hipMemcpyDeviceToDevice, p->stream));
-    step(k_rstep<C, R_LAST>, ModeLast{}, 1, fac + s.levels[0].off_dinv, nullptr, nullptr, 1, 0);
+    for (int z = 0; z < cnt; ++z)
+      LS_HIP(hipMemcpyAsync(S.t[z], S.g[z], sizeof(C) * q, hipMemcpyDeviceToDevice, p->stream));
+    step(k_rstep<C, R_LAST>, ModeLast{}, 1, s.levels[0].off_dinv, 0, 0, 1, 0);
     LS_HIP(hipGetLastError());
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
-  step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
-  k_even0<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2), 128, 0, p->stream>>>(g, y, t, coef, n, q);
+  step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
+  k_even0<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, cnt), 128, 0, p->stream>>>(S, n, q);
   // levels from `top` up: one dense operator when the plan built it
-  const int top_l = (s.top_level >= 1 && top) ? s.top_level : nlev - 1;
+  const int top_l = (s.top_level >= 1 && S.top[0]) ? s.top_level : nlev - 1;
   for (int l = 1; l < top_l; ++l) {
     const SlabLevel& L = s.levels[l];
-    step(k_rstep<C, R_FWD>, ModeFwd{}, (L.nl + 1) / 2, fac + L.off_pm, fac + L.off_pp, nullptr, L.nl, l);
+    step(k_rstep<C, R_FWD>, ModeFwd{}, (L.nl + 1) / 2, L.off_pm, L.off_pp, 0, L.nl, l);
   }
   if (top_l < nlev - 1) {
-    k_top<C><<<(s.top_n + 3) / 4, 256, 0, p->stream>>>(top, t, y, s.top_n, q, top_l);
+    k_top<C><<<dim3((s.top_n + 3) / 4, cnt), 256, 0, p->stream>>>(S, s.top_n, q, top_l);
   } else {
-    step(k_rstep<C, R_LAST>, ModeLast{}, 1, fac + s.levels[nlev - 1].off_dinv, nullptr, nullptr, 1, 0);
+    step(k_rstep<C, R_LAST>, ModeLast{}, 1, s.levels[nlev - 1].off_dinv, 0, 0, 1, 0);
   }
   for (int l = top_l - 1; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
-    step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, fac + L.off_dinv, fac + L.off_dinvl, fac + L.off_dinvu, L.nl, l);
+    step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
   }
-  k_odd0_lu<C><<<dim3((q + 127) / 128, L0.nl / 2), 128, 0, p->stream>>>(y, t, coef, n, q);
-  step(k_rstep<C, R_BWD0>, ModeBwd0{}, L0.nl / 2, fac + L0.off_dinv, nullptr, nullptr, L0.nl, 0);
+  k_odd0_lu<C><<<dim3((q + 127) / 128, L0.nl / 2, cnt), 128, 0, p->stream>>>(S, n, q);
+  step(k_rstep<C, R_BWD0>, ModeBwd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
+}
+
+// One right-hand side of one slab.
+template <typename C>
+static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* top, const C* g,
+                            C* t, C* y) {
+  SlabSet<C> S{};
+  S.g[0] = g;
+  S.t[0] = t;
+  S.y[0] = y;
+  S.fac[0] = fac;
+  S.coef[0] = coef;
+  S.top[0] = top;
+  return solve_rows_set<C>(p, s, S, 1);
 }
 
 // Per-precision views of the slab buffers.
@@ -2107,49 +2279,72 @@ static ls_status scatter(ls_plan* p, const Slab& s, const T* src, T* out, bool a
 // (mU^l + J) tau^{l+1} + mV^l sigma^{l-1}, by two chains of dense products;
 // then every layer's solve of g^l + E^l tau^{l+1} + F^l sigma^{l-1}, whose
 // layer lines are Alg. 1's output.
-// The independent per-layer work runs on the plan's side streams, layer l on
-// stream l mod kSide (forked from and joined back to the plan's stream by
-// events, so a captured graph records it as parallel branches); while a
-// side stream runs, the plan's stream and single-solve scratch are swapped
-// for that stream's own.
-struct SideSwap {
-  ls_plan* p;
-  hipStream_t st;
-  cplx* e64;
-  cplx* w64;
-  fcplx* e32;
-  fcplx* w32;
-  SideSwap(ls_plan* p_, int k) : p(p_), st(p_->stream), e64(p_->slab_elim), w64(p_->slab_work),
-                                 e32(p_->slab_elim32), w32(p_->slab_work32) {
-    p->stream = p->side[k];
-    if (p->fp32) {
-      p->slab_elim32 = (fcplx*)p->side_elim[k];
-      p->slab_work32 = (fcplx*)p->side_work[k];
-    } else {
-      p->slab_elim = (cplx*)p->side_elim[k];
-      p->slab_work = (cplx*)p->side_work[k];
-    }
-  }
-  ~SideSwap() {
-    p->stream = st;
-    p->slab_elim = e64;
-    p->slab_work = w64;
-    p->slab_elim32 = e32;
-    p->slab_work32 = w32;
-  }
-};
+// The per-layer work is batched over the layers: one launch gathers every
+// g^l, one adds every layer's trace sources, one scatters every solution,
+// and the independent solves run as one multi-slab chain per group of
+// like slabs (the largest group on the plan's stream, the others on side
+// streams forked from and joined back to it by events, so that a captured
+// graph records them as parallel branches).
 
-template <class F>
-static ls_status on_side_streams(ls_plan* p, int L, F per_layer) {
-  constexpr int K = ls_plan::kSide;
-  LS_HIP(hipEventRecord(p->side_fork, p->stream));
-  for (int k = 0; k < K && k < L; ++k) LS_HIP(hipStreamWaitEvent(p->side[k], p->side_fork, 0));
-  ls_status st = LS_OK;
-  for (int l = 0; l < L && st == LS_OK; ++l) {
-    SideSwap sw(p, l % K);
-    st = per_layer(l);
+// Per-layer arguments of layers [l0, l0 + cnt): x = g^l, or the solution
+// slot w^l when sol is set.
+template <typename T>
+static LayerSet<T> layer_set(ls_plan* p, std::vector<Slab>& S, int l0, int cnt, bool sol, const T* tau,
+                             const T* sig) {
+  const int L = (int)S.size(), N2 = 2 * p->n;
+  LayerSet<T> ls{};
+  for (int k = 0; k < cnt; ++k) {
+    const int l = l0 + k;
+    Slab& s = S[l];
+    ls.x[k] = sol ? SB<T>::w(s) : SB<T>::g(s);
+    ls.coef[k] = SB<T>::coef(s);
+    ls.q[k] = s.q;
+    ls.z0[k] = s.z0;
+    ls.a[k] = s.a;
+    ls.b[k] = s.b;
+    ls.dn[k] = inj_down(s);
+    ls.up[k] = inj_up(s);
+    ls.tau[k] = (tau && l <= L - 2) ? tau + (size_t)(l + 1) * N2 : nullptr;
+    ls.sig[k] = (sig && l >= 1) ? sig + (size_t)(l - 1) * N2 : nullptr;
   }
-  for (int k = 0; k < K && k < L; ++k) {
+  return ls;
+}
+
+// w^l = (C^l)^{-1} g^l for every layer of one orientation.
+template <typename T>
+static ls_status solve_groups(ls_plan* p, int orient) {
+  std::vector<Slab>& S = p->slabs[orient];
+  const std::vector<std::vector<int>>& G = p->dec_groups[orient];
+  const size_t stride = (size_t)p->n * p->set_qmax;
+  T* elim = static_cast<T*>(p->set_elim);
+  auto run = [&](const std::vector<int>& grp) {
+    SlabSet<T> ss{};
+    for (size_t k = 0; k < grp.size(); ++k) {
+      Slab& s = S[grp[k]];
+      ss.g[k] = SB<T>::g(s);
+      ss.t[k] = elim + (size_t)grp[k] * stride;
+      ss.y[k] = SB<T>::w(s);
+      ss.fac[k] = SB<T>::fac(s);
+      ss.coef[k] = SB<T>::coef(s);
+      ss.top[k] = SB<T>::top(s);
+    }
+    return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size());
+  };
+  constexpr int K = ls_plan::kSide;
+  const int side = std::min((int)G.size() - 1, K);
+  if (side > 0) {
+    LS_HIP(hipEventRecord(p->side_fork, p->stream));
+    for (int k = 0; k < side; ++k) LS_HIP(hipStreamWaitEvent(p->side[k], p->side_fork, 0));
+  }
+  ls_status st = LS_OK;
+  const hipStream_t main = p->stream;
+  for (size_t gi = 1; gi < G.size() && st == LS_OK; ++gi) {
+    p->stream = p->side[(gi - 1) % K];
+    st = run(G[gi]);
+  }
+  p->stream = main;
+  if (st == LS_OK) st = run(G[0]);
+  for (int k = 0; k < side; ++k) {
     LS_HIP(hipEventRecord(p->side_join[k], p->side[k]));
     LS_HIP(hipStreamWaitEvent(p->stream, p->side_join[k], 0));
   }
@@ -2162,11 +2357,21 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
   const int L = (int)S.size(), n = p->n, N2 = 2 * n;
   T* tau = SB<T>::traces(p);
   T* sig = tau + (size_t)L * N2;
-  LS_TRY(on_side_streams(p, L, [&](int l) -> ls_status {
-    Slab& s = S[l];
-    LS_TRY(gather<T>(p, s, g, SB<T>::g(s), 1, nullptr));
-    return solve_t<T>(p, s, SB<T>::g(s), SB<T>::w(s), 1);
-  }));
+  int qmax = 0, rmax = 0;
+  for (const Slab& s : S) {
+    qmax = std::max(qmax, s.q);
+    rmax = std::max(rmax, s.b - s.a + 1);
+  }
+  for (int l0 = 0; l0 < L; l0 += kSet) {  // every g^l
+    const int cnt = std::min(kSet, L - l0);
+    const LayerSet<T> ls = layer_set<T>(p, S, l0, cnt, false, nullptr, nullptr);
+    if (orient == 0)
+      k_gather_set_h<T><<<dim3((n + 15) / 16, (qmax + kTR - 1) / kTR, cnt), 128, 0, p->stream>>>(g, ls, n);
+    else
+      k_gather_set_v<T><<<dim3((unsigned)(((size_t)n * qmax + 255) / 256), 1, cnt), 256, 0, p->stream>>>(g, ls, n);
+  }
+  LS_HIP(hipGetLastError());
+  LS_TRY(solve_groups<T>(p, orient));
   const unsigned steps = (unsigned)((N2 + 3) / 4);
   for (int l = L - 1; l >= 1; --l) {
     Slab& s = S[l];
@@ -2182,17 +2387,25 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
                                                   l >= 1 ? SB<T>::mV(s) : nullptr,
                                                   l >= 1 ? sig + (size_t)(l - 1) * N2 : nullptr, 1);
   }
+  for (int l0 = 0; l0 < L; l0 += kSet) {  // every layer's trace sources into g^l
+    const int cnt = std::min(kSet, L - l0);
+    k_inject_set<T><<<dim3((n + 255) / 256, 1, cnt), 256, 0, p->stream>>>(
+        layer_set<T>(p, S, l0, cnt, false, tau, sig), n);
+  }
   LS_HIP(hipGetLastError());
-  return on_side_streams(p, L, [&](int l) -> ls_status {
-    Slab& s = S[l];
-    k_inject_traces<T><<<(n + 255) / 256, 256, 0, p->stream>>>(
-        SB<T>::g(s), SB<T>::coef(s), n, s.q, inj_down(s), l <= L - 2 ? tau + (size_t)(l + 1) * N2 : nullptr,
-        inj_up(s), l >= 1 ? sig + (size_t)(l - 1) * N2 : nullptr);
-    LS_HIP(hipGetLastError());
-    T* x = SB<T>::work(p, 0);
-    LS_TRY(solve_t<T>(p, s, SB<T>::g(s), x, 1));
-    return scatter<T>(p, s, x, v, accumulate, 1, nullptr);
-  });
+  LS_TRY(solve_groups<T>(p, orient));  // the chains have read w^l: it takes the final solutions
+  for (int l0 = 0; l0 < L; l0 += kSet) {  // their layer lines into v
+    const int cnt = std::min(kSet, L - l0);
+    const LayerSet<T> ls = layer_set<T>(p, S, l0, cnt, true, nullptr, nullptr);
+    if (orient == 0)
+      k_scatter_set_h<T><<<dim3((n + 15) / 16, (rmax + kTR - 1) / kTR, cnt), 128, 0, p->stream>>>(
+          v, ls, n, accumulate ? 1 : 0);
+    else
+      k_scatter_set_v<T><<<dim3((unsigned)(((size_t)n * rmax + 255) / 256), 1, cnt), 256, 0, p->stream>>>(
+          v, ls, n, accumulate ? 1 : 0);
+  }
+  LS_HIP(hipGetLastError());
+  return LS_OK;
 }
 
 // Alg. 1 (Gauss-Seidel polarized traces) on layers of one orientation, for
