@@ -1171,36 +1171,65 @@ __global__ void k_extract_map(const cplx* __restrict__ x, int n, int q, int r0, 
   map[(size_t)k * 2 * n + j0 + b] = tmk<M>(v.x, v.y);
 }
 
-// One step of a trace chain, k < 2n:
-//   out[k] = y[k mod n][row(k / n)] (+ x1[k - n] for k >= n when addJ)
-//            + sum_j M1[k][j] x1[j] + sum_j M2[k][j] x2[j]
-// (M1, M2 may be null).  One wave per output entry.
+// Trace products of the decoupled sweep for a set of layers (blockIdx.y
+// picks the layer), k < 2n:
+//   out[k] = base[k] + sum_j M[k][j] x[j]            (base set)
+//   out[k] = y[k mod n][row(k / n)] (+ x[k - n] for k >= n when addJ)
+//            + sum_j M[k][j] x[j]                     (base null)
+// with row(0) = r0, row(1) = r1, M [2n][2n] row-major or null.  One wave per
+// output entry, eight loads of M and eight of x in flight per lane.  out
+// may be base (each entry is read and written by the same lane).
 template <typename T>
-__global__ __launch_bounds__(256) void k_trace_step(T* __restrict__ out, const T* __restrict__ y, int n, int q,
-                                                    int r0, int r1, const T* __restrict__ M1,
-                                                    const T* __restrict__ x1, const T* __restrict__ M2,
-                                                    const T* __restrict__ x2, int addJ) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+struct TraceSet {
+  T* out[kSet];
+  const T* base[kSet];
+  const T* y[kSet];
+  const T* M[kSet];
+  const T* x[kSet];
+  int q[kSet], r0[kSet], r1[kSet];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trace_set(TraceSet<T> S, int n, int addJ) {
+  const int z = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k = blockIdx.x * 4 + w, N2 = 2 * n;
   if (k >= N2) return;
-  T acc = tmk<T>(0, 0);
-  if (M1) {
-    const T* row = M1 + (size_t)k * N2;
-    for (int j = lane; j < N2; j += 64) acc = tfma(row[j], x1[j], acc);
+  const T* __restrict__ M = S.M[z];
+  const T* __restrict__ x = S.x[z];
+  T a0 = tmk<T>(0, 0), a1 = tmk<T>(0, 0);
+  if (M) {
+    const T* row = M + (size_t)k * N2;
+    int j = lane;
+    for (; j + 7 * 64 < N2; j += 8 * 64) {
+      T mv[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        mv[u] = row[j + 64 * u];
+        xv[u] = x[j + 64 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        a0 = tfma(mv[u], xv[u], a0);
+        a1 = tfma(mv[u + 1], xv[u + 1], a1);
+      }
+    }
+    for (; j < N2; j += 64) a0 = tfma(row[j], x[j], a0);
   }
-  if (M2) {
-    const T* row = M2 + (size_t)k * N2;
-    for (int j = lane; j < N2; j += 64) acc = tfma(row[j], x2[j], acc);
-  }
+  T acc = tadd(a0, a1);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     acc.x += __shfl_xor(acc.x, off);
     acc.y += __shfl_xor(acc.y, off);
   }
   if (lane == 0) {
-    T v = tadd(y[(size_t)(k % n) * q + (k < n ? r0 : r1)], acc);
-    if (addJ && k >= n) v = tadd(v, x1[k - n]);
-    out[k] = v;
+    T v;
+    if (S.base[z]) {
+      v = S.base[z][k];
+    } else {
+      v = S.y[z][(size_t)(k % n) * S.q[z] + (k < n ? S.r0[z] : S.r1[z])];
+      if (addJ && k >= n) v = tadd(v, x[k - n]);
+    }
+    S.out[z][k] = tadd(v, acc);
   }
 }
 
@@ -2372,20 +2401,45 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
   }
   LS_HIP(hipGetLastError());
   LS_TRY(solve_groups<T>(p, orient));
-  const unsigned steps = (unsigned)((N2 + 3) / 4);
+  // the traces: tau^l = R_tau y^l + mT^l tau^{l+1} from the top layer down
+  // (a chain); sigma0^l = R_sigma y^l + (mU^l + J) tau^{l+1} for every
+  // layer at once; sigma^l = sigma0^l + mV^l sigma^{l-1} upwards (a chain)
+  const unsigned rows4 = (unsigned)((N2 + 3) / 4);
   for (int l = L - 1; l >= 1; --l) {
     Slab& s = S[l];
     const bool m = l <= L - 2;
-    k_trace_step<T><<<steps, 256, 0, p->stream>>>(tau + (size_t)l * N2, SB<T>::w(s), n, s.q, s.a - s.z0,
-                                                  s.a - 1 - s.z0, m ? SB<T>::mT(s) : nullptr,
-                                                  m ? tau + (size_t)(l + 1) * N2 : nullptr, nullptr, nullptr, 0);
+    TraceSet<T> ts{};
+    ts.out[0] = tau + (size_t)l * N2;
+    ts.y[0] = SB<T>::w(s);
+    ts.M[0] = m ? SB<T>::mT(s) : nullptr;
+    ts.x[0] = m ? tau + (size_t)(l + 1) * N2 : nullptr;
+    ts.q[0] = s.q;
+    ts.r0[0] = s.a - s.z0;
+    ts.r1[0] = s.a - 1 - s.z0;
+    k_trace_set<T><<<dim3(rows4, 1), 256, 0, p->stream>>>(ts, n, 0);
   }
-  for (int l = 0; l <= L - 2; ++l) {
-    Slab& s = S[l];
-    k_trace_step<T><<<steps, 256, 0, p->stream>>>(sig + (size_t)l * N2, SB<T>::w(s), n, s.q, s.b - s.z0,
-                                                  s.b + 1 - s.z0, SB<T>::mU(s), tau + (size_t)(l + 1) * N2,
-                                                  l >= 1 ? SB<T>::mV(s) : nullptr,
-                                                  l >= 1 ? sig + (size_t)(l - 1) * N2 : nullptr, 1);
+  for (int l0 = 0; l0 <= L - 2; l0 += kSet) {
+    const int cnt = std::min(kSet, L - 1 - l0);
+    TraceSet<T> ts{};
+    for (int k = 0; k < cnt; ++k) {
+      Slab& s = S[l0 + k];
+      ts.out[k] = sig + (size_t)(l0 + k) * N2;
+      ts.y[k] = SB<T>::w(s);
+      ts.M[k] = SB<T>::mU(s);
+      ts.x[k] = tau + (size_t)(l0 + k + 1) * N2;
+      ts.q[k] = s.q;
+      ts.r0[k] = s.b - s.z0;
+      ts.r1[k] = s.b + 1 - s.z0;
+    }
+    k_trace_set<T><<<dim3(rows4, cnt), 256, 0, p->stream>>>(ts, n, 1);
+  }
+  for (int l = 1; l <= L - 2; ++l) {
+    TraceSet<T> ts{};
+    ts.out[0] = sig + (size_t)l * N2;
+    ts.base[0] = ts.out[0];
+    ts.M[0] = SB<T>::mV(S[l]);
+    ts.x[0] = sig + (size_t)(l - 1) * N2;
+    k_trace_set<T><<<dim3(rows4, 1), 256, 0, p->stream>>>(ts, n, 0);
   }
   for (int l0 = 0; l0 < L; l0 += kSet) {  // every layer's trace sources into g^l
     const int cnt = std::min(kSet, L - l0);
