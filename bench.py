@@ -14,9 +14,10 @@ precomputed trace-transfer maps; the same operator as the sequential
 sweep, whose solve rate is reported as a variant).  Plan creation (with the
 maps) is timed separately (config.setup_s).  Prints one JSON line.  Also
 reports:
-  * roofline of the dominant kernel chain (the single-right-hand-side
-    block-cyclic-reduction slab solve of an interior layer, ~95 % of a
-    solve), timed live with HIP events on the plan's stream;
+  * roofline of the dominant unit, one decoupled sweep (every layer's slab
+    solved twice as multi-slab launches, the trace chains; ~95 % of a
+    solve), timed live with HIP events on the plan's stream, and the
+    single-right-hand-side slab solve of an interior layer on its own;
   * the FFT matvec (ls_apply) achieved HBM GB/s on a batch of 8;
   * cpu_baseline: one full solve of the same workload by the FP64 CPU
     oracle on the host cores (see cpu_baseline());
@@ -45,6 +46,12 @@ HBM_PEAK_GBS = 8000.0
 SLAB_TRAFFIC_BYTES = 450.09e6
 SLAB_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode slab` (5 interior slab solves), "
                        "scaled by the counters of a 1 GiB device copy; see the slab-solve profile")
+# The same for one decoupled sweep (the dominant unit of the plain solve),
+# from `bench.py --mode sweep`; see the sweep profile.
+SWEEP_TRAFFIC_BYTES = 17.41e9
+SWEEP_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sweep`, summed over the sweep "
+                        "kernels and divided by the sweeps run, scaled by the counters of a 1 GiB device copy; "
+                        "see the sweep profile")
 
 
 def log(msg):
@@ -56,6 +63,42 @@ def slab_solve_bytes(n, q):
     a block-tridiagonal LU with bandwidth q+1 read once, n*q*(3q+4) entries,
     plus reading and writing the right-hand side."""
     return 16 * (n * q * (3 * q + 4) + 2 * n * q)
+
+
+def sweep_bytes(n, qs):
+    """Algorithmic bytes of one decoupled sweep (Alg. 1, FP64, one
+    right-hand side) over layers of thicknesses qs: every layer's slab
+    solved twice (slab_solve_bytes each), the trace-transfer maps read once
+    ((L - 2) mT, (L - 1) mU and (L - 2) mV, each (2n)^2 c128), g read and v
+    written once."""
+    L = len(qs)
+    return 2 * sum(slab_solve_bytes(n, q) for q in qs) + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
+
+
+def time_sweeps(plan, n, reps):
+    """Mean time of one decoupled sweep of the plan (orientations 0 and 1
+    alternating), by HIP events on the plan's stream (the sweep's side
+    streams join back into it), and the sweep's algorithmic bytes."""
+    import torch
+    dev = torch.device("cuda:0")
+    g = torch.randn((n, n), dtype=torch.complex128, device=dev)
+    v = torch.empty_like(g)
+    for o in (0, 1, 0, 1):
+        plan.sweep(o, g, out=v)
+    stream = plan.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for k in range(reps):
+        plan.sweep(k % 2, g, out=v)
+    ev1.record(stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    qs = []
+    for l in range(plan.L):
+        lims = plan.slab_info(0, l)
+        qs.append(lims[3] - lims[2] + 1)
+    return ms, sweep_bytes(n, qs), qs
 
 
 def apply_bytes(n, batch, cb=16, rb=8):
@@ -505,7 +548,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
     ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
     ap.add_argument("--mode", default="full",
-                    choices=["full", "slab", "copy", "batched", "learned", "apply", "fno", "trend", "setup"],
+                    choices=["full", "slab", "sweep", "copy", "batched", "learned", "apply", "fno", "trend",
+                             "setup"],
                     help="profiling sub-runs: slab = only slab solves of the bench workload's "
                          "interior layer; copy = 1 GiB device copies (counter calibration); "
                          "batched = only the multi-grid variant; learned = only the learned-form "
@@ -564,7 +608,7 @@ def main():
     popts = {}
     if args.fft_variant is not None:
         popts = dict(autotune=0, fft_variant=args.fft_variant, precision=1)
-    if args.mode == "full":
+    if args.mode in ("full", "sweep"):
         popts["sweep"] = 1    # decoupled sweeps for the timed solve
     plan = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, max_batch=8, **popts)
     torch.cuda.synchronize()
@@ -599,6 +643,12 @@ def main():
         print(json.dumps(out))
         plan.close()
         return
+    if args.mode == "sweep":
+        ms, by, qs = time_sweeps(plan, n, args.slab_reps)
+        print(json.dumps({"mode": "sweep", "reps": args.slab_reps, "warmup_sweeps": 4, "ms": ms,
+                          "alg_bytes": by, "qs": qs, "GBs": by / (ms * 1e-3) / 1e9}))
+        plan.close()
+        return
     if args.mode == "slab":
         lims = plan.slab_info(0, 1)
         q = lims[3] - lims[2] + 1
@@ -631,7 +681,11 @@ def main():
     log(f"timed {args.steps} solves in {elapsed:.3f} s; last {infos[-1]}")
     value = args.steps / elapsed
 
-    # dominant kernel: slab solve of an interior layer (q = 84), HIP events on the plan stream
+    # dominant unit: one decoupled sweep (95 % of a solve), HIP events on the plan stream
+    sweep_ms, sweep_alg, sweep_qs = time_sweeps(plan, n, 2 * args.slab_reps)
+    sweep_gbs = sweep_alg / (sweep_ms * 1e-3) / 1e9
+    log(f"decoupled sweep: {sweep_ms:.3f} ms, {sweep_alg / 1e9:.2f} GB algorithmic, {sweep_gbs:.0f} GB/s")
+    # one slab solve of an interior layer (q = 84) on its own
     lims = plan.slab_info(0, 1)
     q = lims[3] - lims[2] + 1
     b = torch.randn(n * q, dtype=torch.complex128, device=dev)
@@ -754,6 +808,10 @@ def main():
             "inner_its_total": inner,
             "relres_true": max(i["relres_true"] for i in infos),
             "setup_s": setup_s,
+            "slab_solve_single_us": slab_ms * 1e3,
+            "slab_solve_single_GBs": slab_gbs,
+            "slab_solve_single_alg_bytes": slab_alg,
+            "slab_solve_single_traffic": SLAB_TRAFFIC_BYTES,
             "fft_matvec_GBs": apply_gbs,
             "fft_matvec_ms_batch8": apply_ms,
             "fft_matvec_io_GBs": apply_io_gbs,
@@ -761,15 +819,18 @@ def main():
             "fft_matvec_fp32_ms_batch8": apply32_ms,
         },
         "roofline": {
-            "kernel": "slab solve (block cyclic reduction, q=%d)" % q,
+            "kernel": ("one decoupled sweep (Alg. 1): every layer's slab solved twice as multi-slab launches "
+                       "(block cyclic reduction), the trace chains, gather / inject / scatter"),
             "bound": "hbm",
-            "achieved": slab_gbs,
+            "achieved": sweep_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": slab_gbs / HBM_PEAK_GBS,
-            "traffic": SLAB_TRAFFIC_BYTES,
-            "traffic_source": SLAB_TRAFFIC_SOURCE,
-            "ms_per_launch": slab_ms,
+            "frac": sweep_gbs / HBM_PEAK_GBS,
+            "traffic": SWEEP_TRAFFIC_BYTES,
+            "traffic_source": SWEEP_TRAFFIC_SOURCE,
+            "ms_per_launch": sweep_ms,
+            "alg_bytes_per_launch": sweep_alg,
+            "layer_q": sweep_qs,
         },
         "cpu_baseline": cpu,
         "variants": {"plain_sequential_sweeps": seq_single, "fp32_refine_single": fp32_single,
