@@ -48,7 +48,7 @@ SLAB_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sl
                        "scaled by the counters of a 1 GiB device copy; see the slab-solve profile")
 # The same for one decoupled sweep (the dominant unit of the plain solve),
 # from `bench.py --mode sweep`; see the sweep profile.
-SWEEP_TRAFFIC_BYTES = 17.41e9
+SWEEP_TRAFFIC_BYTES = None
 SWEEP_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sweep`, summed over the sweep "
                         "kernels and divided by the sweeps run, scaled by the counters of a 1 GiB device copy; "
                         "see the sweep profile")
@@ -68,11 +68,14 @@ def slab_solve_bytes(n, q):
 def sweep_bytes(n, qs):
     """Algorithmic bytes of one decoupled sweep (Alg. 1, FP64, one
     right-hand side) over layers of thicknesses qs: every layer's slab
-    solved twice (slab_solve_bytes each), the trace-transfer maps read once
-    ((L - 2) mT, (L - 1) mU and (L - 2) mV, each (2n)^2 c128), g read and v
-    written once."""
+    solved twice (slab_solve_bytes each), less, in the first solve, the
+    rows of the level-0 odd blocks' inverses that are not needed (only the
+    four grid lines the trace chains read are completed: n/2 blocks of
+    (q - 4) q entries); the trace-transfer maps read once ((L - 2) mT,
+    (L - 1) mU and (L - 2) mV, each (2n)^2 c128); g read and v written once."""
     L = len(qs)
-    return 2 * sum(slab_solve_bytes(n, q) for q in qs) + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
+    solves = sum(2 * slab_solve_bytes(n, q) - (n // 2) * (q - 4) * q * 16 for q in qs)
+    return solves + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
 
 
 def time_sweeps(plan, n, reps):

@@ -258,7 +258,7 @@ __device__ __forceinline__ int bstep_remap(int id, int total) {
 // elements (at most RCols::N) into registers before anything else, so a
 // level costs about one memory round trip however deep it is; the inputs
 // x_t are staged in LDS meanwhile and the G partial sums added in LDS.
-enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4 };
+enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4, R_BWD0S = 5 };
 // factor columns a thread preloads: one, two or three matrices per step
 template <int MODE>
 struct RCols {
@@ -282,6 +282,9 @@ inline int row_splits(int q, int t, int ncol) {
 //   R_LAST  top level:       y_0 = Dinv t_0
 //   R_BWD   level l, k odd:  y_k = Dinv_k t_k - (Dinv L)_k y_{k-1} - (Dinv U)_k y_{k+1}
 //   R_BWD0  level 0, k odd:  y_k -= Dinv_k t_k, t_k = L_k y_{k-1} + U_k y_{k+1} (k_odd0_lu)
+//   R_BWD0S as R_BWD0 for the rows S.sel[slab] only (at most 4, -1 = none; one
+//           row tile per block): the other rows of the odd blocks keep the
+//           level-0 forward values
 // Slabs of one launch: the one-right-hand-side steps run the same level
 // step (same q and level structure: the factor blocks of a level at the
 // same offsets) for up to kSet slabs at once, blockIdx.y (k_rstep, k_top)
@@ -296,6 +299,7 @@ struct SlabSet {
   const C* fac[kSet];  // factors (level offsets shared by the set)
   const C* coef[kSet];
   const C* top[kSet];  // dense top operators (or null)
+  int sel[kSet][4];    // R_BWD0S: the rows to compute, -1 = unused
 };
 
 template <typename C, int MODE>
@@ -314,17 +318,19 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   // that straddle tile boundaries through that XCD's L2
   const int lid = bstep_remap(blockIdx.x, gridDim.x);
   const int blk = lid / RS, rs = lid % RS;
-  const int R = (q + RS - 1) / RS, r0 = rs * R;
+  const int R = MODE == R_BWD0S ? 4 : (q + RS - 1) / RS, r0 = rs * R;
   const int tid = threadIdx.x;
   const int rl = tid % R, grp = tid / R, G = 256 / R;
-  const bool act = grp < G && r0 + rl < q;
+  // row of tile entry i: r0 + i, or the selected row (R_BWD0S)
+  auto row_of = [&](int i) { return MODE == R_BWD0S ? S.sel[z][i] : r0 + i; };
+  const bool act = grp < G && (MODE == R_BWD0S ? row_of(rl) >= 0 : r0 + rl < q);
   const size_t qq = (size_t)q * q;
   int k = 0, T = 1;
   bool hm = false;
   const C* M0 = nullptr;
   const C* M1 = nullptr;
   const C* M2 = nullptr;
-  if (MODE == R_ODD0 || MODE == R_BWD0) {
+  if (MODE == R_ODD0 || MODE == R_BWD0 || MODE == R_BWD0S) {
     k = 2 * blk + 1;
     M0 = m0 + blk * qq;
   } else if (MODE == R_FWD) {
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
     if (act && v < V) {
       const int tt = v >= 2 * q ? 2 : (v >= q ? 1 : 0);
       const C* Mt = tt == 0 ? M0 : (tt == 1 ? M1 : M2);
-      mv[j] = Mt[(size_t)(v - tt * q) * q + r0 + rl];
+      mv[j] = Mt[(size_t)(v - tt * q) * q + row_of(rl)];
     }
   }
   // inputs x_t (flat over the T*q virtual columns)
@@ -382,10 +388,10 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   for (int j = 0; j < NC; ++j) acc = tfma(mv[j], xs[min(grp + G * j, V - 1)], acc);
   part[tid] = acc;  // part[grp * R + rl]
   __syncthreads();
-  if (tid < R && r0 + tid < q) {
+  if (tid < R && (MODE == R_BWD0S ? row_of(tid) >= 0 : r0 + tid < q)) {
     C sum = tmk<C>(0, 0);
     for (int gg = 0; gg < G; ++gg) sum = tadd(sum, part[gg * R + tid]);
-    const int r = r0 + tid;
+    const int r = row_of(tid);
     if (MODE == R_ODD0) y[(size_t)k * q + r] = sum;
     else if (MODE == R_FWD) { C* o = t + ((size_t)k << shift) * q + r; *o = tsub(*o, sum); }
     else if (MODE == R_LAST) y[r] = sum;
@@ -2122,8 +2128,10 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
 
 // One right-hand side per slab: y = C_slab^{-1} g (g untouched, t scratch)
 // for the cnt <= kSet slabs of S, which share s's q and level structure.
+// With sel, only the rows S.sel of the level-0 odd blocks are completed (the
+// rest of those blocks keeps intermediate values).
 template <typename C>
-static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, int cnt) {
+static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, int cnt, bool sel = false) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
   auto step = [&](auto kern, auto mode, int nb, size_t o0, size_t o1, size_t o2, int nl, int shift) {
@@ -2162,7 +2170,10 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
     step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
   }
   k_odd0_lu<C><<<dim3((q + 127) / 128, L0.nl / 2, cnt), 128, 0, p->stream>>>(S, n, q);
-  step(k_rstep<C, R_BWD0>, ModeBwd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
+  if (sel)  // one tile of the selected rows per block
+    k_rstep<C, R_BWD0S><<<dim3(L0.nl / 2, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, 0, 0, n, q, L0.nl, 0, 1);
+  else
+    step(k_rstep<C, R_BWD0>, ModeBwd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -2339,9 +2350,11 @@ static LayerSet<T> layer_set(ls_plan* p, std::vector<Slab>& S, int l0, int cnt, 
   return ls;
 }
 
-// w^l = (C^l)^{-1} g^l for every layer of one orientation.
+// w^l = (C^l)^{-1} g^l for every layer of one orientation.  With `lines`,
+// only the grid lines the trace chains read from w^l are made exact: the
+// lines a-1, a (layers l >= 1) and b, b+1 (layers l <= L-2).
 template <typename T>
-static ls_status solve_groups(ls_plan* p, int orient) {
+static ls_status solve_groups(ls_plan* p, int orient, bool lines) {
   std::vector<Slab>& S = p->slabs[orient];
   const std::vector<std::vector<int>>& G = p->dec_groups[orient];
   const size_t stride = (size_t)p->n * p->set_qmax;
@@ -2356,8 +2369,12 @@ static ls_status solve_groups(ls_plan* p, int orient) {
       ss.fac[k] = SB<T>::fac(s);
       ss.coef[k] = SB<T>::coef(s);
       ss.top[k] = SB<T>::top(s);
+      const int l = grp[k], L = (int)S.size();
+      const int want[4] = {l >= 1 ? s.a - s.z0 : -1, l >= 1 ? s.a - 1 - s.z0 : -1,
+                           l <= L - 2 ? s.b - s.z0 : -1, l <= L - 2 ? s.b + 1 - s.z0 : -1};
+      for (int u = 0; u < 4; ++u) ss.sel[k][u] = (want[u] >= 0 && want[u] < s.q) ? want[u] : -1;
     }
-    return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size());
+    return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size(), lines);
   };
   constexpr int K = ls_plan::kSide;
   const int side = std::min((int)G.size() - 1, K);
@@ -2400,7 +2417,7 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
       k_gather_set_v<T><<<dim3((unsigned)(((size_t)n * qmax + 255) / 256), 1, cnt), 256, 0, p->stream>>>(g, ls, n);
   }
   LS_HIP(hipGetLastError());
-  LS_TRY(solve_groups<T>(p, orient));
+  LS_TRY(solve_groups<T>(p, orient, true));  // the chains read four lines of each w^l
   // the traces: tau^l = R_tau y^l + mT^l tau^{l+1} from the top layer down
   // (a chain); sigma0^l = R_sigma y^l + (mU^l + J) tau^{l+1} for every
   // layer at once; sigma^l = sigma0^l + mV^l sigma^{l-1} upwards (a chain)
@@ -2447,7 +2464,7 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
         layer_set<T>(p, S, l0, cnt, false, tau, sig), n);
   }
   LS_HIP(hipGetLastError());
-  LS_TRY(solve_groups<T>(p, orient));  // the chains have read w^l: it takes the final solutions
+  LS_TRY(solve_groups<T>(p, orient, false));  // the chains have read w^l: it takes the final solutions
   for (int l0 = 0; l0 < L; l0 += kSet) {  // their layer lines into v
     const int cnt = std::min(kSet, L - l0);
     const LayerSet<T> ls = layer_set<T>(p, S, l0, cnt, true, nullptr, nullptr);
