@@ -1182,7 +1182,7 @@ __global__ void k_extract_map(const cplx* __restrict__ x, int n, int q, int r0, 
 //   out[k] = base[k] + sum_j M[k][j] x[j]            (base set)
 //   out[k] = y[k mod n][row(k / n)] (+ x[k - n] for k >= n when addJ)
 //            + sum_j M[k][j] x[j]                     (base null)
-// with row(0) = r0, row(1) = r1, M [2n][2n] row-major or null.  One wave per
+// with row(0) = r0, row(1) = r1, M [2n][2n] row-major or null.  WPR waves per
 // output entry, eight loads of M and eight of x in flight per lane.  out
 // may be base (each entry is read and written by the same lane).
 template <typename T>
@@ -1195,18 +1195,23 @@ struct TraceSet {
   int q[kSet], r0[kSet], r1[kSet];
 };
 
-template <typename T>
+template <typename T, int WPR>
 __global__ __launch_bounds__(256) void k_trace_set(TraceSet<T> S, int n, int addJ) {
+  // WPR waves per output entry (4 / WPR entries per workgroup): wave part w
+  // takes columns [w N2 / WPR, (w + 1) N2 / WPR) and the partial sums meet
+  // in LDS
+  __shared__ T red[4];
   const int z = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int k = blockIdx.x * 4 + w, N2 = 2 * n;
-  if (k >= N2) return;
+  const int k = blockIdx.x * (4 / WPR) + w / WPR, part = w % WPR, N2 = 2 * n;
+  if (k >= N2) return;  // with WPR = 4 the whole workgroup (k is uniform)
   const T* __restrict__ M = S.M[z];
   const T* __restrict__ x = S.x[z];
   T a0 = tmk<T>(0, 0), a1 = tmk<T>(0, 0);
   if (M) {
+    const int j1 = part == WPR - 1 ? N2 : (part + 1) * (N2 / WPR);
     const T* row = M + (size_t)k * N2;
-    int j = lane;
-    for (; j + 7 * 64 < N2; j += 8 * 64) {
+    int j = part * (N2 / WPR) + lane;
+    for (; j + 7 * 64 < j1; j += 8 * 64) {
       T mv[8], xv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1219,13 +1224,20 @@ __global__ __launch_bounds__(256) void k_trace_set(TraceSet<T> S, int n, int add
         a1 = tfma(mv[u + 1], xv[u + 1], a1);
       }
     }
-    for (; j < N2; j += 64) a0 = tfma(row[j], x[j], a0);
+    for (; j < j1; j += 64) a0 = tfma(row[j], x[j], a0);
   }
   T acc = tadd(a0, a1);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     acc.x += __shfl_xor(acc.x, off);
     acc.y += __shfl_xor(acc.y, off);
+  }
+  if constexpr (WPR > 1) {
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int u = 1; u < WPR; ++u) acc = tadd(acc, red[u]);
   }
   if (lane == 0) {
     T v;
@@ -2433,7 +2445,7 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
     ts.q[0] = s.q;
     ts.r0[0] = s.a - s.z0;
     ts.r1[0] = s.a - 1 - s.z0;
-    k_trace_set<T><<<dim3(rows4, 1), 256, 0, p->stream>>>(ts, n, 0);
+    k_trace_set<T, 4><<<dim3(N2, 1), 256, 0, p->stream>>>(ts, n, 0);
   }
   for (int l0 = 0; l0 <= L - 2; l0 += kSet) {
     const int cnt = std::min(kSet, L - 1 - l0);
@@ -2448,7 +2460,7 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
       ts.r0[k] = s.b - s.z0;
       ts.r1[k] = s.b + 1 - s.z0;
     }
-    k_trace_set<T><<<dim3(rows4, cnt), 256, 0, p->stream>>>(ts, n, 1);
+    k_trace_set<T, 1><<<dim3(rows4, cnt), 256, 0, p->stream>>>(ts, n, 1);
   }
   for (int l = 1; l <= L - 2; ++l) {
     TraceSet<T> ts{};
@@ -2456,7 +2468,7 @@ static ls_status sweep_decoupled_t(ls_plan* p, int orient, const T* g, T* v, boo
     ts.base[0] = ts.out[0];
     ts.M[0] = SB<T>::mV(S[l]);
     ts.x[0] = sig + (size_t)(l - 1) * N2;
-    k_trace_set<T><<<dim3(rows4, 1), 256, 0, p->stream>>>(ts, n, 0);
+    k_trace_set<T, 4><<<dim3(N2, 1), 256, 0, p->stream>>>(ts, n, 0);
   }
   for (int l0 = 0; l0 < L; l0 += kSet) {  // every layer's trace sources into g^l
     const int cnt = std::min(kSet, L - l0);
