@@ -65,16 +65,17 @@ def slab_solve_bytes(n, q):
     return 16 * (n * q * (3 * q + 4) + 2 * n * q)
 
 
-def sweep_bytes(n, qs):
+def sweep_bytes(n, qs, spans):
     """Algorithmic bytes of one decoupled sweep (Alg. 1, FP64, one
-    right-hand side) over layers of thicknesses qs: every layer's slab
-    solved twice (slab_solve_bytes each), less, in the first solve, the
-    rows of the level-0 odd blocks' inverses that are not needed (only the
-    four grid lines the trace chains read are completed: n/2 blocks of
-    (q - 4) q entries); the trace-transfer maps read once ((L - 2) mT,
+    right-hand side) over layers of thicknesses qs and spans layer lines:
+    every layer's slab solved twice (slab_solve_bytes each), less the rows
+    of the level-0 odd blocks' inverses that the last step does not need
+    (n/2 blocks of (q - r) q entries: the first solve completes the r = 4
+    grid lines the trace chains read, the second the r = span layer lines
+    the scatter reads); the trace-transfer maps read once ((L - 2) mT,
     (L - 1) mU and (L - 2) mV, each (2n)^2 c128); g read and v written once."""
     L = len(qs)
-    solves = sum(2 * slab_solve_bytes(n, q) - (n // 2) * (q - 4) * q * 16 for q in qs)
+    solves = sum(2 * slab_solve_bytes(n, q) - (n // 2) * (2 * q - 4 - r) * q * 16 for q, r in zip(qs, spans))
     return solves + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
 
 
@@ -97,11 +98,12 @@ def time_sweeps(plan, n, reps):
     ev1.record(stream)
     ev1.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
-    qs = []
+    qs, spans = [], []
     for l in range(plan.L):
-        lims = plan.slab_info(0, l)
-        qs.append(lims[3] - lims[2] + 1)
-    return ms, sweep_bytes(n, qs), qs
+        a, b, z0, z1 = plan.slab_info(0, l)
+        qs.append(z1 - z0 + 1)
+        spans.append(b - a + 1)
+    return ms, sweep_bytes(n, qs, spans), qs
 
 
 def apply_bytes(n, batch, cb=16, rb=8):

@@ -258,7 +258,7 @@ __device__ __forceinline__ int bstep_remap(int id, int total) {
 // elements (at most RCols::N) into registers before anything else, so a
 // level costs about one memory round trip however deep it is; the inputs
 // x_t are staged in LDS meanwhile and the G partial sums added in LDS.
-enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4, R_BWD0S = 5 };
+enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4, R_BWD0S = 5, R_BWD0R = 6 };
 // factor columns a thread preloads: one, two or three matrices per step
 template <int MODE>
 struct RCols {
@@ -266,15 +266,17 @@ struct RCols {
   static constexpr int N = 7 * T;
 };
 
-// Row tiles per block for extended thickness q: the fewest with at most
-// ncol columns per thread for a step with t factor matrices.
-inline int row_splits(int q, int t, int ncol) {
-  for (int rs = 1; rs <= q; ++rs) {
-    const int R = (q + rs - 1) / rs, G = 256 / R;
+// Row tiles per block for `rows` rows of factor matrices with q columns:
+// the fewest with at most ncol columns per thread for a step with t
+// factor matrices (rows = q: whole blocks).
+inline int row_splits(int rows, int q, int t, int ncol) {
+  for (int rs = 1; rs <= rows; ++rs) {
+    const int R = (rows + rs - 1) / rs, G = 256 / R;
     if (G >= 1 && (t * q + G - 1) / G <= ncol) return rs;
   }
-  return q;
+  return rows;
 }
+inline int row_splits(int q, int t, int ncol) { return row_splits(q, q, t, ncol); }
 
 // Modes (k: block row at this level, rows of level l are global rows k<<l):
 //   R_ODD0  level 0, k odd:  y_k = Dinv_k g_k
@@ -285,6 +287,7 @@ inline int row_splits(int q, int t, int ncol) {
 //   R_BWD0S as R_BWD0 for the rows S.sel[slab] only (at most 4, -1 = none; one
 //           row tile per block): the other rows of the odd blocks keep the
 //           level-0 forward values
+//   R_BWD0R as R_BWD0 for the rows [S.lo[slab], S.hi[slab]) only (RS tiles)
 // Slabs of one launch: the one-right-hand-side steps run the same level
 // step (same q and level structure: the factor blocks of a level at the
 // same offsets) for up to kSet slabs at once, blockIdx.y (k_rstep, k_top)
@@ -300,6 +303,7 @@ struct SlabSet {
   const C* coef[kSet];
   const C* top[kSet];  // dense top operators (or null)
   int sel[kSet][4];    // R_BWD0S: the rows to compute, -1 = unused
+  int lo[kSet], hi[kSet];  // R_BWD0R: the rows [lo, hi) to compute
 };
 
 template <typename C, int MODE>
@@ -318,19 +322,20 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   // that straddle tile boundaries through that XCD's L2
   const int lid = bstep_remap(blockIdx.x, gridDim.x);
   const int blk = lid / RS, rs = lid % RS;
-  const int R = MODE == R_BWD0S ? 4 : (q + RS - 1) / RS, r0 = rs * R;
+  const int rlo = MODE == R_BWD0R ? S.lo[z] : 0, rhi = MODE == R_BWD0R ? S.hi[z] : q;
+  const int R = MODE == R_BWD0S ? 4 : (rhi - rlo + RS - 1) / RS, r0 = rlo + rs * R;
   const int tid = threadIdx.x;
   const int rl = tid % R, grp = tid / R, G = 256 / R;
   // row of tile entry i: r0 + i, or the selected row (R_BWD0S)
   auto row_of = [&](int i) { return MODE == R_BWD0S ? S.sel[z][i] : r0 + i; };
-  const bool act = grp < G && (MODE == R_BWD0S ? row_of(rl) >= 0 : r0 + rl < q);
+  const bool act = grp < G && (MODE == R_BWD0S ? row_of(rl) >= 0 : r0 + rl < rhi);
   const size_t qq = (size_t)q * q;
   int k = 0, T = 1;
   bool hm = false;
   const C* M0 = nullptr;
   const C* M1 = nullptr;
   const C* M2 = nullptr;
-  if (MODE == R_ODD0 || MODE == R_BWD0 || MODE == R_BWD0S) {
+  if (MODE == R_ODD0 || MODE == R_BWD0 || MODE == R_BWD0S || MODE == R_BWD0R) {
     k = 2 * blk + 1;
     M0 = m0 + blk * qq;
   } else if (MODE == R_FWD) {
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   for (int j = 0; j < NC; ++j) acc = tfma(mv[j], xs[min(grp + G * j, V - 1)], acc);
   part[tid] = acc;  // part[grp * R + rl]
   __syncthreads();
-  if (tid < R && (MODE == R_BWD0S ? row_of(tid) >= 0 : r0 + tid < q)) {
+  if (tid < R && (MODE == R_BWD0S ? row_of(tid) >= 0 : r0 + tid < rhi)) {
     C sum = tmk<C>(0, 0);
     for (int gg = 0; gg < G; ++gg) sum = tadd(sum, part[gg * R + tid]);
     const int r = row_of(tid);
@@ -2140,10 +2145,12 @@ static ls_status solve_levels_b(ls_plan* p, const Slab& s, const C* fac, const C
 
 // One right-hand side per slab: y = C_slab^{-1} g (g untouched, t scratch)
 // for the cnt <= kSet slabs of S, which share s's q and level structure.
-// With sel, only the rows S.sel of the level-0 odd blocks are completed (the
-// rest of those blocks keeps intermediate values).
+// Rows of the level-0 odd blocks to complete (the rest of those blocks
+// keeps intermediate values): all, the lists S.sel, or the ranges
+// [S.lo, S.hi).
+enum { ROWS_ALL = 0, ROWS_SEL = 1, ROWS_RANGE = 2 };
 template <typename C>
-static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, int cnt, bool sel = false) {
+static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, int cnt, int rows = ROWS_ALL) {
   const int n = p->n, q = s.q;
   const int nlev = (int)s.levels.size();
   auto step = [&](auto kern, auto mode, int nb, size_t o0, size_t o1, size_t o2, int nl, int shift) {
@@ -2182,10 +2189,16 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
     step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
   }
   k_odd0_lu<C><<<dim3((q + 127) / 128, L0.nl / 2, cnt), 128, 0, p->stream>>>(S, n, q);
-  if (sel)  // one tile of the selected rows per block
+  if (rows == ROWS_SEL) {  // one tile of the selected rows per block
     k_rstep<C, R_BWD0S><<<dim3(L0.nl / 2, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, 0, 0, n, q, L0.nl, 0, 1);
-  else
+  } else if (rows == ROWS_RANGE) {  // tiles over the longest range of the set
+    int span = 1;
+    for (int z = 0; z < cnt; ++z) span = std::max(span, S.hi[z] - S.lo[z]);
+    const int RS = row_splits(span, q, RCols<R_BWD0R>::T, RCols<R_BWD0R>::N);
+    k_rstep<C, R_BWD0R><<<dim3(L0.nl / 2 * RS, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, 0, 0, n, q, L0.nl, 0, RS);
+  } else {
     step(k_rstep<C, R_BWD0>, ModeBwd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
+  }
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -2362,11 +2375,12 @@ static LayerSet<T> layer_set(ls_plan* p, std::vector<Slab>& S, int l0, int cnt, 
   return ls;
 }
 
-// w^l = (C^l)^{-1} g^l for every layer of one orientation.  With `lines`,
-// only the grid lines the trace chains read from w^l are made exact: the
-// lines a-1, a (layers l >= 1) and b, b+1 (layers l <= L-2).
+// w^l = (C^l)^{-1} g^l for every layer of one orientation, exact on the
+// grid lines the next step reads: with `chains`, the lines a-1, a (layers
+// l >= 1) and b, b+1 (layers l <= L-2) the trace chains read; without, the
+// layer lines [a, b] the scatter reads.
 template <typename T>
-static ls_status solve_groups(ls_plan* p, int orient, bool lines) {
+static ls_status solve_groups(ls_plan* p, int orient, bool chains) {
   std::vector<Slab>& S = p->slabs[orient];
   const std::vector<std::vector<int>>& G = p->dec_groups[orient];
   const size_t stride = (size_t)p->n * p->set_qmax;
@@ -2385,8 +2399,10 @@ static ls_status solve_groups(ls_plan* p, int orient, bool lines) {
       const int want[4] = {l >= 1 ? s.a - s.z0 : -1, l >= 1 ? s.a - 1 - s.z0 : -1,
                            l <= L - 2 ? s.b - s.z0 : -1, l <= L - 2 ? s.b + 1 - s.z0 : -1};
       for (int u = 0; u < 4; ++u) ss.sel[k][u] = (want[u] >= 0 && want[u] < s.q) ? want[u] : -1;
+      ss.lo[k] = s.a - s.z0;
+      ss.hi[k] = s.b - s.z0 + 1;
     }
-    return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size(), lines);
+    return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size(), chains ? ROWS_SEL : ROWS_RANGE);
   };
   constexpr int K = ls_plan::kSide;
   const int side = std::min((int)G.size() - 1, K);
