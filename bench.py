@@ -48,7 +48,7 @@ SLAB_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sl
                        "scaled by the counters of a 1 GiB device copy; see the slab-solve profile")
 # The same for one decoupled sweep (the dominant unit of the plain solve),
 # from `bench.py --mode sweep`; see the sweep profile.
-SWEEP_TRAFFIC_BYTES = None
+SWEEP_TRAFFIC_BYTES = 16.53e9
 SWEEP_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sweep`, summed over the sweep "
                         "kernels and divided by the sweeps run, scaled by the counters of a 1 GiB device copy; "
                         "see the sweep profile")
@@ -87,8 +87,8 @@ def time_sweeps(plan, n, reps):
     dev = torch.device("cuda:0")
     g = torch.randn((n, n), dtype=torch.complex128, device=dev)
     v = torch.empty_like(g)
-    for o in (0, 1, 0, 1):
-        plan.sweep(o, g, out=v)
+    for k in range(10):  # warm-up (clocks, caches)
+        plan.sweep(k % 2, g, out=v)
     stream = plan.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -650,7 +650,7 @@ def main():
         return
     if args.mode == "sweep":
         ms, by, qs = time_sweeps(plan, n, args.slab_reps)
-        print(json.dumps({"mode": "sweep", "reps": args.slab_reps, "warmup_sweeps": 4, "ms": ms,
+        print(json.dumps({"mode": "sweep", "reps": args.slab_reps, "warmup_sweeps": 10, "ms": ms,
                           "alg_bytes": by, "qs": qs, "GBs": by / (ms * 1e-3) / 1e9}))
         plan.close()
         return
