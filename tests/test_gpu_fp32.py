@@ -113,14 +113,17 @@ def test_fp32_refined_solution_error_vs_oracle_solution():
     p.close()
 
 
+@pytest.mark.parametrize("sweep", [0, 1])
 @pytest.mark.parametrize("name", ["c3_2048_grf"])
-def test_fp32_refined_solve_full_size_residual(name):
-    """2048^2 Gaussian-random-field workload at tol 1e-10: the oracle's FP64
-    residual of the GPU solution is at most the tolerance (the library's
-    own FP64 residual and the oracle's agree to rounding)."""
+def test_fp32_refined_solve_full_size_residual(name, sweep):
+    """2048^2 Gaussian-random-field workload at tol 1e-10, with the
+    sequential and with the decoupled sweeps (FP32 trace maps, 30 interior
+    layers in multi-slab groups of 16 and 14 as bench.py runs it): the
+    oracle's FP64 residual of the GPU solution is at most the tolerance (the
+    library's own FP64 residual and the oracle's agree to rounding)."""
     cfg = li.config_inputs(name)
     n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
-    p, _ = plan32(n, omega / (2 * np.pi), m, slabs=cfg["slabs"], ext=10)
+    p, _ = plan32(n, omega / (2 * np.pi), m, slabs=cfg["slabs"], ext=10, sweep=sweep)
     uI = cfg["uI"]
     f = p.rhs_from_incident(dev(uI))
     u, info = p.solve(f, tol=1e-10)
