@@ -151,14 +151,15 @@ def test_sweeps_and_bidirectional(n, f, L, ext, shift, seed):
     p.close()
 
 
-@pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES + [(200, 20.0, 20, 4, 0.0, 5)])
+@pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES + [(80, 8.0, 2, 8, 0.0, 7), (200, 20.0, 20, 4, 0.0, 5)])
 def test_decoupled_sweep_matches_oracle(n, f, L, ext, shift, seed):
     """Alg. 1 with the layers decoupled by trace-transfer maps (independent
     local solves, two chains of dense products for the traces, independent
     solves again) is the same linear operator as the sequential sweep: both
     orientations and Alg. 2 against the oracle's sequential sweeps.  The
     independent solves run as multi-slab launches over groups of like slabs:
-    one group per layer (n = 130), two groups of two (n = 64), and at
+    one group per layer (n = 130), two groups of two (n = 64), two layers
+    only (n = 80: no chain step beyond the first, no upward chain), and at
     n = 200, L = 20 more like slabs than one launch takes (groups of 16, 2
     and 2; the per-layer launches in chunks of 16 and 4)."""
     from paper_1602_07652_amd import LS_SWEEP_DECOUPLED
