@@ -17,15 +17,19 @@ def make(n, m, **kw):
     return Plan(n, 1.0 / n, omega, dev(m, torch.float64), **kw), omega
 
 
+@pytest.mark.parametrize("sweep", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_graph_replays_match_eager(precision):
+def test_graph_replays_match_eager(precision, sweep):
     """The captured Alg. 2 graph is replayed several times with other device
     work and synchronisations in between; every replay equals the eager
-    application bit for bit (same kernels, same order)."""
+    application bit for bit (same kernels, same order).  With the decoupled
+    sweeps (sweep = 1) the three layers' slabs differ in shape, so the graph
+    holds branches on side streams forked from and joined to the plan's
+    stream: a missing dependency would show as a replay that differs."""
     n = 96
     m, _ = li.gaussian_bumps_medium(n, seed=11)
-    pg, omega = make(n, m, slabs=3, ext=8, use_graphs=1, precision=precision)
-    pe, _ = make(n, m, slabs=3, ext=8, use_graphs=0, precision=precision)
+    pg, omega = make(n, m, slabs=3, ext=8, use_graphs=1, precision=precision, sweep=sweep)
+    pe, _ = make(n, m, slabs=3, ext=8, use_graphs=0, precision=precision, sweep=sweep)
     for k in range(4):
         g = dev(li.random_complex((n, n), 40 + k))
         ve = host(pe.bidirectional(g))
