@@ -507,6 +507,9 @@ ls_status ls_plan_destroy(ls_plan* p) {
   (void)hipStreamSynchronize(p->stream);
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   for (void* a : p->allocs) (void)hipFree(a);
+  if (p->hres) (void)hipHostFree(p->hres);
+  if (p->hcoef) (void)hipHostFree(p->hcoef);
+  if (p->coef_ev) (void)hipEventDestroy(p->coef_ev);
   for (int k = 0; k < ls_plan::kSide; ++k) {
     if (p->side[k]) (void)hipStreamDestroy(p->side[k]);
     if (p->side_join[k]) (void)hipEventDestroy(p->side_join[k]);

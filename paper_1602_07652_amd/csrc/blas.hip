@@ -144,14 +144,21 @@ __global__ __launch_bounds__(kDotThreads) void k_update_dot(const T* __restrict_
   }
 }
 
+// Per-right-hand-side factors, passed by value in the kernel arguments (no
+// transfer, nothing for the host to wait on); a launch covers at most
+// kScaleChunk right-hand sides.
+constexpr int kScaleChunk = 64;
+struct Scales {
+  double s[kScaleChunk];
+};
+
 // y[b] = s[b] * x[b]
 template <typename T>
-__global__ void k_scale_b(T* __restrict__ y, const T* __restrict__ x, const double* __restrict__ s,
-                          size_t N) {
+__global__ void k_scale_b(T* __restrict__ y, const T* __restrict__ x, Scales s, size_t N) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
   const size_t off = (size_t)blockIdx.y * N + t;
-  const double f = s[blockIdx.y];
+  const double f = s.s[blockIdx.y];
   y[off] = tmk<T>(x[off].x * f, x[off].y * f);
 }
 
@@ -174,41 +181,78 @@ __global__ void k_fill_zero(T* __restrict__ y, size_t N) {
 }
 
 // y[b] (FP32) = s[b] * x[b] (FP64)
-__global__ void k_down(fcplx* __restrict__ y, const cplx* __restrict__ x,
-                       const double* __restrict__ s, size_t N) {
+__global__ void k_down(fcplx* __restrict__ y, const cplx* __restrict__ x, Scales s, size_t N) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
   const size_t o = (size_t)blockIdx.y * N + t;
-  const double f = s[blockIdx.y];
+  const double f = s.s[blockIdx.y];
   y[o] = make_float2((float)(x[o].x * f), (float)(x[o].y * f));
 }
 
 // y[b] (FP64) = y0[b] + s[b] * x[b] (FP32); y0 may be null
 __global__ void k_up_axpy(cplx* __restrict__ y, const cplx* __restrict__ y0,
-                          const fcplx* __restrict__ x, const double* __restrict__ s, size_t N) {
+                          const fcplx* __restrict__ x, Scales s, size_t N) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
   const size_t o = (size_t)blockIdx.y * N + t;
-  const double f = s[blockIdx.y];
+  const double f = s.s[blockIdx.y];
   cplx v = cmk((double)x[o].x * f, (double)x[o].y * f);
   if (y0) v = cadd(y0[o], v);
   y[o] = v;
 }
 
+// Reduction partials and the device result / coefficient buffer, with
+// pinned host twins for the transfers of the Krylov loop (a pinned copy is
+// one DMA, a pageable one is staged through the runtime's own buffer).
 ls_status ensure_red(ls_plan* p) {
   if (!p->red) {
     const int B = p->opt.max_batch;
+    const size_t small = sizeof(cplx) * 256 * B;
+    if (!p->hres) LS_HIP(hipHostMalloc((void**)&p->hres, small, hipHostMallocDefault));
+    if (!p->hcoef) LS_HIP(hipHostMalloc((void**)&p->hcoef, small, hipHostMallocDefault));
+    if (!p->coef_ev) LS_HIP(hipEventCreateWithFlags(&p->coef_ev, hipEventDisableTiming));
+    if (!p->dotbuf) LS_TRY(plan_alloc(p, (void**)&p->dotbuf, small));
     LS_TRY(plan_alloc(p, (void**)&p->red, sizeof(cplx) * kDotBlocks * kGroup * B));
-    LS_TRY(plan_alloc(p, (void**)&p->dotbuf, sizeof(cplx) * 256 * B));
   }
   return LS_OK;
 }
 
 inline int blocks_for(size_t N, int t) { return (int)((N + t - 1) / t); }
 
+// Coefficients to the device result buffer through the pinned twin.  The
+// host does not wait for the copy: the next upload waits (on the event
+// recorded after this copy) before it overwrites the pinned twin.
 ls_status upload_coef(ls_plan* p, const cplx* coef_host, size_t cnt) {
   LS_TRY(ensure_red(p));
-  LS_HIP(hipMemcpyAsync(p->dotbuf, coef_host, sizeof(cplx) * cnt, hipMemcpyHostToDevice, p->stream));
+  if (p->coef_pending) LS_HIP(hipEventSynchronize(p->coef_ev));
+  std::copy(coef_host, coef_host + cnt, p->hcoef);
+  LS_HIP(hipMemcpyAsync(p->dotbuf, p->hcoef, sizeof(cplx) * cnt, hipMemcpyHostToDevice, p->stream));
+  LS_HIP(hipEventRecord(p->coef_ev, p->stream));
+  p->coef_pending = true;
+  return LS_OK;
+}
+
+// The first cnt values of the device result buffer to out_host, through the
+// pinned twin; waits for the stream.
+ls_status download_results(ls_plan* p, cplx* out_host, size_t cnt) {
+  LS_HIP(hipMemcpyAsync(p->hres, p->dotbuf, sizeof(cplx) * cnt, hipMemcpyDeviceToHost, p->stream));
+  LS_HIP(hipStreamSynchronize(p->stream));
+  p->coef_pending = false;
+  std::copy(p->hres, p->hres + cnt, out_host);
+  return LS_OK;
+}
+
+// Launches fn(c0, cnt, factors) for the right-hand sides c0 .. c0+cnt-1 of
+// s_host, kScaleChunk at a time.
+template <class F>
+ls_status for_scale_chunks(const double* s_host, int B, F fn) {
+  for (int c0 = 0; c0 < B; c0 += kScaleChunk) {
+    Scales sc{};
+    const int cnt = std::min(kScaleChunk, B - c0);
+    for (int i = 0; i < cnt; ++i) sc.s[i] = s_host[c0 + i];
+    fn(c0, cnt, sc);
+  }
+  LS_HIP(hipGetLastError());
   return LS_OK;
 }
 
@@ -228,9 +272,7 @@ ls_status multidot_t(ls_plan* p, const T* V, int k, size_t stride, const T* w, s
     k_finish_dot<<<dim3(kk, B), 256, 0, p->stream>>>(p->red, nblk, p->dotbuf + g0, k);
   }
   LS_HIP(hipGetLastError());
-  LS_HIP(hipMemcpyAsync(out_host, p->dotbuf, sizeof(cplx) * k * B, hipMemcpyDeviceToHost, p->stream));
-  LS_HIP(hipStreamSynchronize(p->stream));
-  return LS_OK;
+  return download_results(p, out_host, (size_t)k * B);
 }
 
 template <typename T>
@@ -247,20 +289,14 @@ ls_status multiaxpy_t(ls_plan* p, T* y, const T* y0, const T* V, int k, size_t s
   k_multiaxpy<T><<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, y0, V, k, stride, p->dotbuf,
                                                                      k, N, sign);
   LS_HIP(hipGetLastError());
-  // the coefficient buffer is reused by the next call
-  LS_HIP(hipStreamSynchronize(p->stream));
   return LS_OK;
 }
 
 template <typename T>
 ls_status scale_b_t(ls_plan* p, T* y, const T* x, const double* s_host, size_t N, int B) {
-  LS_TRY(ensure_red(p));
-  double* sd = reinterpret_cast<double*>(p->dotbuf);
-  LS_HIP(hipMemcpyAsync(sd, s_host, sizeof(double) * B, hipMemcpyHostToDevice, p->stream));
-  k_scale_b<T><<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, x, sd, N);
-  LS_HIP(hipGetLastError());
-  LS_HIP(hipStreamSynchronize(p->stream));
-  return LS_OK;
+  return for_scale_chunks(s_host, B, [&](int c0, int cnt, const Scales& sc) {
+    k_scale_b<T><<<dim3(blocks_for(N, 256), cnt), 256, 0, p->stream>>>(y + c0 * N, x + c0 * N, sc, N);
+  });
 }
 
 // Classical Gram-Schmidt with one re-orthogonalisation of w against the k
@@ -289,8 +325,7 @@ ls_status cgs2_t(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, i
   k_finish_dot<<<dim3(1, B), 256, 0, p->stream>>>(p->red, nblk, nr, 1);
   LS_HIP(hipGetLastError());
   std::vector<cplx> hb((size_t)(2 * k + 1) * B);
-  LS_HIP(hipMemcpyAsync(hb.data(), h1, sizeof(cplx) * hb.size(), hipMemcpyDeviceToHost, p->stream));
-  LS_HIP(hipStreamSynchronize(p->stream));
+  LS_TRY(download_results(p, hb.data(), hb.size()));
   std::copy(hb.begin(), hb.begin() + (size_t)k * B, h1_host);
   std::copy(hb.begin() + (size_t)k * B, hb.begin() + (size_t)2 * k * B, h2_host);
   for (int b = 0; b < B; ++b) nrm2_host[b] = hb[(size_t)2 * k * B + b].x;
@@ -353,30 +388,18 @@ ls_status cgs2_t(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, i
 LS_BLAS_INSTANCES(cplx)
 LS_BLAS_INSTANCES(fcplx)
 
-static ls_status upload_scales(ls_plan* p, const double* s_host, int B, double** dev) {
-  LS_TRY(ensure_red(p));
-  *dev = reinterpret_cast<double*>(p->dotbuf);
-  LS_HIP(hipMemcpyAsync(*dev, s_host, sizeof(double) * B, hipMemcpyHostToDevice, p->stream));
-  return LS_OK;
-}
-
 ls_status vec_to_f32_b(ls_plan* p, fcplx* y, const cplx* x, const double* s_host, size_t N, int B) {
-  double* sd;
-  LS_TRY(upload_scales(p, s_host, B, &sd));
-  k_down<<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, x, sd, N);
-  LS_HIP(hipGetLastError());
-  LS_HIP(hipStreamSynchronize(p->stream));
-  return LS_OK;
+  return for_scale_chunks(s_host, B, [&](int c0, int cnt, const Scales& sc) {
+    k_down<<<dim3(blocks_for(N, 256), cnt), 256, 0, p->stream>>>(y + c0 * N, x + c0 * N, sc, N);
+  });
 }
 
 ls_status vec_from_f32_b(ls_plan* p, cplx* y, const cplx* y0, const fcplx* x, const double* s_host,
                          size_t N, int B) {
-  double* sd;
-  LS_TRY(upload_scales(p, s_host, B, &sd));
-  k_up_axpy<<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(y, y0, x, sd, N);
-  LS_HIP(hipGetLastError());
-  LS_HIP(hipStreamSynchronize(p->stream));
-  return LS_OK;
+  return for_scale_chunks(s_host, B, [&](int c0, int cnt, const Scales& sc) {
+    k_up_axpy<<<dim3(blocks_for(N, 256), cnt), 256, 0, p->stream>>>(
+        y + c0 * N, y0 ? y0 + c0 * N : nullptr, x + c0 * N, sc, N);
+  });
 }
 
 ls_status vec_to_f32(ls_plan* p, fcplx* y, const cplx* x, double s, size_t N) {

@@ -215,7 +215,11 @@ struct ls_plan {
   KrylovSpaceT<fcplx> innerV32, innerZ32, outerV32, outerZ32;
   fcplx* inner_rhs32 = nullptr;
   cplx* red = nullptr;           // reduction partials
-  cplx* dotbuf = nullptr;        // device results of multi-dots
+  cplx* dotbuf = nullptr;        // device results of multi-dots / update coefficients
+  cplx* hres = nullptr;          // pinned host twins of dotbuf: results, coefficients
+  cplx* hcoef = nullptr;
+  hipEvent_t coef_ev = nullptr;  // recorded after the last coefficient upload
+  bool coef_pending = false;
   std::vector<void*> allocs;     // every device allocation, freed at destroy
 
   bool fp32 = false;             // FP32 operator + FP64 refinement
