@@ -435,6 +435,11 @@ constexpr int kTopBlocks = 16;
 constexpr int kTopK = 24;                 // ceil(kTopBlocks * kMaxQ / 64)
 constexpr int kTopMax = kTopBlocks * kMaxQ;
 constexpr int kTopBatchMin = 16;  // right-hand sides from which batched solves use the top operator
+// Plans with the decoupled sweep and fewer right-hand sides run their slabs
+// as multi-slab launches, where the narrow levels are no longer latency
+// bound but the dense operator's bytes are streamed: there the operator
+// starts at 8 blocks (one more reduction level, a quarter of the bytes).
+constexpr int kTopBlocksDec = 8;
 
 template <typename C>
 __global__ __launch_bounds__(256) void k_top(SlabSet<C> S, int Nt, int q, int shift) {
@@ -1574,9 +1579,11 @@ static void bstep(ls_plan* p, C* x, size_t xs_b, int B, const C* a0, const C* a1
 // keeps the level-by-level chain.
 static ls_status build_top(ls_plan* p, Slab& s, const cplx* fac, cplx* work, size_t work_cap) {
   const int nlev = (int)s.levels.size();
+  const int lim = (p->opt.sweep == LS_SWEEP_DECOUPLED && p->opt.max_batch < kTopBatchMin) ? kTopBlocksDec
+                                                                                          : kTopBlocks;
   int ls = -1;
   for (int l = 1; l < nlev; ++l)
-    if (s.levels[l].nl <= kTopBlocks) {
+    if (s.levels[l].nl <= lim) {
       ls = l;
       break;
     }
