@@ -101,6 +101,11 @@ struct Slab {
   int a, b, z0, z1;  // layer lines and extended lines (short axis)
   int q;             // z1 - z0 + 1
   cplx* coef;        // [n][q][9] assembled local matrix C^l (stencil form)
+  // level-0 couplings of each block to its neighbours, [n][6][q] (row r of
+  // block k: c = 2 (dZ + 1) + side, the coefficient of row r + dZ of block
+  // k - 1 (side 0) or k + 1 (side 1)), in the plan's precision
+  cplx* cpl = nullptr;
+  fcplx* cpl32 = nullptr;
   cplx* fac;         // block-cyclic-reduction factors (offsets in levels)
   size_t fac_elems;
   std::vector<SlabLevel> levels;  // levels[0] .. levels[nlev-1]; last has nl == 1
@@ -112,7 +117,8 @@ struct Slab {
   fcplx* g32;
   fcplx* w32;
   // Top of the reduction as one dense operator: the levels from top_level
-  // up (top_level >= 1, at most 16 blocks there) solved by y = top t on the
+  // up (top_level >= 1, at most 16 blocks there, 8 on plans with the
+  // decoupled sweep and few right-hand sides) solved by y = top t on the
   // top_n = nl * q unknowns of that level; row-major [top_n][top_n].
   // top_level = -1: no such operator (the chain runs every level).
   int top_level;

@@ -301,6 +301,7 @@ struct SlabSet {
   C* y[kSet];          // solutions [n][q]
   const C* fac[kSet];  // factors (level offsets shared by the set)
   const C* coef[kSet];
+  const C* cpl[kSet];
   const C* top[kSet];  // dense top operators (or null)
   int sel[kSet][4];    // R_BWD0S: the rows to compute, -1 = unused
   int lo[kSet], hi[kSet];  // R_BWD0R: the rows [lo, hi) to compute
@@ -405,25 +406,39 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   }
 }
 
-// level 0, odd blocks: t_k = L_k y_{k-1} + U_k y_{k+1} (L, U from coef;
-// the odd rows of t are free once the forward elimination is done)
+// level 0, odd blocks: t_k = L_k y_{k-1} + U_k y_{k+1} (L, U from the
+// coupling table; the odd rows of t are free once the forward elimination
+// is done).  One thread per row of an odd block, blockIdx.y the slab.
 template <typename C>
-__global__ void k_odd0_lu(SlabSet<C> S, int n, int q) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = 2 * blockIdx.y + 1;
-  if (r >= q) return;
-  const C* __restrict__ y = S.y[blockIdx.z];
-  C* __restrict__ t = S.t[blockIdx.z];
-  const C* __restrict__ coef = S.coef[blockIdx.z];
-  const C* cf = coef + ((size_t)k * q + r) * 9;
+__global__ __launch_bounds__(256) void k_odd0_lu(SlabSet<C> S, int n, int q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (n / 2) * q) return;
+  const int j = e / q, r = e - j * q, k = 2 * j + 1;
+  const C* __restrict__ y = S.y[blockIdx.y];
+  C* __restrict__ t = S.t[blockIdx.y];
+  const C* __restrict__ cp = S.cpl[blockIdx.y] + (size_t)k * 6 * q + r;
   C acc = tmk<C>(0, 0);
   for (int dZ = -1; dZ <= 1; ++dZ) {
     const int rr = r + dZ;
     if (rr < 0 || rr >= q) continue;
-    acc = tfma(cf[(dZ + 1) * 3 + 0], y[(size_t)(k - 1) * q + rr], acc);
-    if (k + 1 < n) acc = tfma(cf[(dZ + 1) * 3 + 2], y[(size_t)(k + 1) * q + rr], acc);
+    acc = tfma(cp[(size_t)(2 * (dZ + 1)) * q], y[(size_t)(k - 1) * q + rr], acc);
+    if (k + 1 < n) acc = tfma(cp[(size_t)(2 * (dZ + 1) + 1) * q], y[(size_t)(k + 1) * q + rr], acc);
   }
   t[(size_t)k * q + r] = acc;
+}
+
+// cpl[k][c][r] (type T) from coef[k][r][9]: c = 2 (dZ + 1) + side takes the
+// stencil entry (dZ + 1) * 3 + 2 side (side 0: block k - 1, side 1: k + 1).
+template <typename T>
+__global__ void k_couplings(const cplx* __restrict__ coef, T* __restrict__ cpl, int n, int q) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * 6 * q) return;
+  const int r = (int)(e % q);
+  const size_t kc = e / q;
+  const int c = (int)(kc % 6);
+  const size_t k = kc / 6;
+  const cplx v = coef[(k * q + r) * 9 + (c / 2) * 3 + 2 * (c & 1)];
+  cpl[e] = tmk<T>(v.x, v.y);
 }
 
 // The top levels of the reduction (from level top_level, at most
@@ -504,21 +519,20 @@ __global__ void k_transpose_to(const cplx* __restrict__ in, T* __restrict__ out,
 
 // level 0, even blocks: t_k = g_k - L_k z_{k-1} - U_k z_{k+1} with z_j = y_j
 template <typename C>
-__global__ void k_even0(SlabSet<C> S, int n, int q) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = 2 * blockIdx.y;
-  if (r >= q) return;
-  const C* __restrict__ g = S.g[blockIdx.z];
-  const C* __restrict__ y = S.y[blockIdx.z];
-  C* __restrict__ t = S.t[blockIdx.z];
-  const C* __restrict__ coef = S.coef[blockIdx.z];
-  const C* cf = coef + ((size_t)k * q + r) * 9;
+__global__ __launch_bounds__(256) void k_even0(SlabSet<C> S, int n, int q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ((n + 1) / 2) * q) return;
+  const int j = e / q, r = e - j * q, k = 2 * j;
+  const C* __restrict__ g = S.g[blockIdx.y];
+  const C* __restrict__ y = S.y[blockIdx.y];
+  C* __restrict__ t = S.t[blockIdx.y];
+  const C* __restrict__ cp = S.cpl[blockIdx.y] + (size_t)k * 6 * q + r;
   C acc = g[(size_t)k * q + r];
   for (int dZ = -1; dZ <= 1; ++dZ) {
     const int rr = r + dZ;
     if (rr < 0 || rr >= q) continue;
-    if (k >= 1) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 0], y[(size_t)(k - 1) * q + rr]));
-    if (k + 1 < n) acc = tsub(acc, tmul(cf[(dZ + 1) * 3 + 2], y[(size_t)(k + 1) * q + rr]));
+    if (k >= 1) acc = tsub(acc, tmul(cp[(size_t)(2 * (dZ + 1)) * q], y[(size_t)(k - 1) * q + rr]));
+    if (k + 1 < n) acc = tsub(acc, tmul(cp[(size_t)(2 * (dZ + 1) + 1) * q], y[(size_t)(k + 1) * q + rr]));
   }
   t[(size_t)k * q + r] = acc;
 }
@@ -2010,6 +2024,18 @@ ls_status slabs_build(ls_plan* p) {
       k_assemble<<<dim3((s.q + 63) / 64, n), 64, 0, p->stream>>>(
           s.coef, tables, p->m, n, s.q, s.z0, s.a, s.b, std::max(ext, 2), o, w2, sigma);
       if (hipGetLastError() != hipSuccess) { ls_set_error("assembly launch failed"); st = LS_EDEVICE; break; }
+      {  // level-0 coupling table in the plan's precision
+        const size_t ce = (size_t)n * 6 * s.q;
+        const unsigned cb = (unsigned)((ce + 255) / 256);
+        if (p->fp32) {
+          if ((st = plan_alloc(p, (void**)&s.cpl32, ce * sizeof(fcplx))) != LS_OK) break;
+          k_couplings<fcplx><<<cb, 256, 0, p->stream>>>(s.coef, s.cpl32, n, s.q);
+        } else {
+          if ((st = plan_alloc(p, (void**)&s.cpl, ce * sizeof(cplx))) != LS_OK) break;
+          k_couplings<cplx><<<cb, 256, 0, p->stream>>>(s.coef, s.cpl, n, s.q);
+        }
+        if (hipGetLastError() != hipSuccess) { ls_set_error("coupling table launch failed"); st = LS_EDEVICE; break; }
+      }
       const double t1 = plan_clock_ms(p);
       if ((st = factor_slab(p, s, work, status)) != LS_OK) break;
       const double t2 = plan_clock_ms(p);
@@ -2179,7 +2205,7 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
   }
   const SlabLevel& L0 = s.levels[0];
   step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
-  k_even0<C><<<dim3((q + 127) / 128, (L0.nl + 1) / 2, cnt), 128, 0, p->stream>>>(S, n, q);
+  k_even0<C><<<dim3((((n + 1) / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
   // levels from `top` up: one dense operator when the plan built it
   const int top_l = (s.top_level >= 1 && S.top[0]) ? s.top_level : nlev - 1;
   for (int l = 1; l < top_l; ++l) {
@@ -2195,7 +2221,7 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
     const SlabLevel& L = s.levels[l];
     step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
   }
-  k_odd0_lu<C><<<dim3((q + 127) / 128, L0.nl / 2, cnt), 128, 0, p->stream>>>(S, n, q);
+  k_odd0_lu<C><<<dim3(((n / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
   if (rows == ROWS_SEL) {  // one tile of the selected rows per block
     k_rstep<C, R_BWD0S><<<dim3(L0.nl / 2, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, 0, 0, n, q, L0.nl, 0, 1);
   } else if (rows == ROWS_RANGE) {  // tiles over the longest range of the set
@@ -2212,14 +2238,15 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
 
 // One right-hand side of one slab.
 template <typename C>
-static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* top, const C* g,
-                            C* t, C* y) {
+static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* cpl, const C* top,
+                            const C* g, C* t, C* y) {
   SlabSet<C> S{};
   S.g[0] = g;
   S.t[0] = t;
   S.y[0] = y;
   S.fac[0] = fac;
   S.coef[0] = coef;
+  S.cpl[0] = cpl;
   S.top[0] = top;
   return solve_rows_set<C>(p, s, S, 1);
 }
@@ -2233,6 +2260,7 @@ struct SB<cplx> {
   static cplx* w(Slab& s) { return s.w; }
   static const cplx* fac(const Slab& s) { return s.fac; }
   static const cplx* coef(const Slab& s) { return s.coef; }
+  static const cplx* cpl(const Slab& s) { return s.cpl; }
   static cplx* work(ls_plan* p, int k) { return k ? p->slab_work2 : p->slab_work; }
   static cplx* elim(ls_plan* p) { return p->slab_elim; }
   static const cplx* top(const Slab& s) { return s.top; }
@@ -2248,6 +2276,7 @@ struct SB<fcplx> {
   static fcplx* w(Slab& s) { return s.w32; }
   static const fcplx* fac(const Slab& s) { return s.fac32; }
   static const fcplx* coef(const Slab& s) { return s.coef32; }
+  static const fcplx* cpl(const Slab& s) { return s.cpl32; }
   static fcplx* work(ls_plan* p, int k) { return k ? p->slab_work32b : p->slab_work32; }
   static fcplx* elim(ls_plan* p) { return p->slab_elim32; }
   static const fcplx* top(const Slab& s) { return s.top32; }
@@ -2263,7 +2292,8 @@ struct SB<fcplx> {
 // the batched in-place steps on a copy.
 template <typename T>
 static ls_status solve_t(ls_plan* p, Slab& s, const T* g, T* y, int B) {
-  if (B == 1) return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), SB<T>::top(s), g, SB<T>::elim(p), y);
+  if (B == 1)
+    return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), SB<T>::cpl(s), SB<T>::top(s), g, SB<T>::elim(p), y);
   LS_HIP(hipMemcpyAsync(y, g, (size_t)B * p->n * s.q * sizeof(T), hipMemcpyDeviceToDevice, p->stream));
   return solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), y, (size_t)p->n * s.q, B);
 }
@@ -2401,6 +2431,7 @@ static ls_status solve_groups(ls_plan* p, int orient, bool chains) {
       ss.y[k] = SB<T>::w(s);
       ss.fac[k] = SB<T>::fac(s);
       ss.coef[k] = SB<T>::coef(s);
+      ss.cpl[k] = SB<T>::cpl(s);
       ss.top[k] = SB<T>::top(s);
       const int l = grp[k], L = (int)S.size();
       const int want[4] = {l >= 1 ? s.a - s.z0 : -1, l >= 1 ? s.a - 1 - s.z0 : -1,
@@ -2643,7 +2674,7 @@ ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x) {
     fcplx* yo = gi + cnt;
     fcplx* t = yo + cnt;
     k_down_copy<<<blocks, 256, 0, p->stream>>>(b, gi, cnt);
-    LS_TRY(solve_rows<fcplx>(p, s, s.fac32, s.coef32, s.top32, gi, t, yo));
+    LS_TRY(solve_rows<fcplx>(p, s, s.fac32, s.coef32, s.cpl32, s.top32, gi, t, yo));
     k_up_copy<<<blocks, 256, 0, p->stream>>>(yo, x, cnt);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -2661,5 +2692,5 @@ ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x) {
     LS_HIP(hipMemcpyAsync(gi, b, cnt * sizeof(cplx), hipMemcpyDeviceToDevice, p->stream));
     g = gi;
   }
-  return solve_rows<cplx>(p, s, s.fac, s.coef, s.top, g, t, x);
+  return solve_rows<cplx>(p, s, s.fac, s.coef, s.cpl, s.top, g, t, x);
 }
