@@ -2448,14 +2448,16 @@ static ls_status solve_groups(ls_plan* p, int orient, bool chains) {
     LS_HIP(hipEventRecord(p->side_fork, p->stream));
     for (int k = 0; k < side; ++k) LS_HIP(hipStreamWaitEvent(p->side[k], p->side_fork, 0));
   }
-  ls_status st = LS_OK;
+  // the largest group (the critical path) first: a captured graph replays
+  // its branches' kernels in the order they were launched here, so a branch
+  // launched later starts later
+  ls_status st = run(G[0]);
   const hipStream_t main = p->stream;
   for (size_t gi = 1; gi < G.size() && st == LS_OK; ++gi) {
     p->stream = p->side[(gi - 1) % K];
     st = run(G[gi]);
   }
   p->stream = main;
-  if (st == LS_OK) st = run(G[0]);
   for (int k = 0; k < side; ++k) {
     LS_HIP(hipEventRecord(p->side_join[k], p->side[k]));
     LS_HIP(hipStreamWaitEvent(p->stream, p->side_join[k], 0));
