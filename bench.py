@@ -583,10 +583,18 @@ def main():
     if args.mode == "copy":
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         c = torch.empty_like(a)
+        c.copy_(a)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
         for _ in range(args.slab_reps):
             c.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"mode": "copy", "bytes_per_copy": 1 << 30, "reps": args.slab_reps}))
+        ev1.record()
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.slab_reps
+        # bytes moved per copy: 1 GiB read + 1 GiB written
+        print(json.dumps({"mode": "copy", "bytes_per_copy": 1 << 30, "reps": args.slab_reps, "ms": ms,
+                          "GBs_read_plus_write": 2 * (1 << 30) / (ms * 1e-3) / 1e9}))
         return
     if args.mode == "batched":
         print(json.dumps({"mode": "batched", "batched": batched_variant(args.tol, log)}))

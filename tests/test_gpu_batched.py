@@ -172,3 +172,30 @@ def test_every_fft_column_variant_matches_oracle(apply_refs, n, variant):
     banner(f"variant {variant} n={n}: FP64 rel err {e64:.3e}, FP32 {e32:.3e}")
     assert e64 < 1e-13 and e32 < 1e-6
     p.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_more_right_hand_sides_than_one_scaling_launch(precision):
+    """72 right-hand sides, more than the 64 whose per-right-hand-side factors
+    one scaling launch of the Krylov loop carries in its kernel arguments:
+    plane waves at 72 angles with a zero right-hand side in the second group.
+    Every wave converges, the zero one gives u = 0 exactly, and the oracle's
+    FP64 residual agrees on waves of both groups."""
+    n, B = 48, 72
+    m, _ = li.gaussian_bumps_medium(n, seed=21)
+    p, omega = make(n, m, slabs=2, ext=6, max_batch=B, precision=precision)
+    uI = np.stack([li.plane_wave(n, omega, 2 * np.pi * k / B) for k in range(B)])
+    uI[70] = 0
+    f = p.rhs_from_incident(dev(uI))
+    u, infos = p.solve(f, tol=1e-8)
+    uh, fh = host(u), host(f)
+    assert np.all(uh[70] == 0) and infos[70]["converged"] == 1
+    assert all(i["converged"] == 1 for i in infos)
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    Gh = kernel.circulant_spectrum(W)
+    for k in (0, 63, 64, 71):
+        res = np.linalg.norm(fh[k] - kernel.apply_H(W, m, uh[k], omega, Gh)) / np.linalg.norm(fh[k])
+        banner(f"72 waves prec={precision} wave {k}: {infos[k]}, oracle residual {res:.3e}")
+        assert res < 1e-8
+        assert abs(res - infos[k]["relres_true"]) <= 1e-3 * res + 1e-14
+    p.close()
