@@ -248,6 +248,12 @@ struct ls_plan {
   // the groups after the first concurrently
   std::vector<std::vector<int>> dec_groups[2];
   void* set_elim = nullptr;
+  // decoupled sweep, per layer: the level-0 forward values of the four chain
+  // rows of the odd blocks [L][n/2][4] kept by the first solves, and the
+  // trace sources added to those rows of every block [L][n][4]; the second
+  // solves update the level-0 step from them instead of redoing it
+  void* set_save = nullptr;
+  void* set_inj = nullptr;
   int set_qmax = 0;
   static constexpr int kSide = 4;
   hipStream_t side[kSide] = {};

@@ -305,6 +305,8 @@ struct SlabSet {
   const C* top[kSet];  // dense top operators (or null)
   int sel[kSet][4];    // R_BWD0S: the rows to compute, -1 = unused
   int lo[kSet], hi[kSet];  // R_BWD0R: the rows [lo, hi) to compute
+  C* save[kSet];       // R_BWD0S: the level-0 values of the rows sel, [n/2][4] (or null)
+  const C* inj[kSet];  // k_odd0_upd: the sources added to the rows sel, [n][4]
 };
 
 template <typename C, int MODE>
@@ -402,8 +404,38 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
     else if (MODE == R_FWD) { C* o = t + ((size_t)k << shift) * q + r; *o = tsub(*o, sum); }
     else if (MODE == R_LAST) y[r] = sum;
     else if (MODE == R_BWD) y[((size_t)k << shift) * q + r] = sum;
-    else { C* o = y + (size_t)k * q + r; *o = tsub(*o, sum); }
+    else {
+      C* o = y + (size_t)k * q + r;
+      if (MODE == R_BWD0S && S.save[z]) S.save[z][(size_t)blk * 4 + tid] = *o;
+      *o = tsub(*o, sum);
+    }
   }
+}
+
+// Level 0, odd blocks, once the right-hand side has changed only in the
+// rows sel (by the sources inj): the level-0 values y_k = Dinv_k g_k of an
+// earlier solve of the old right-hand side (still in y, those of the rows
+// sel in save) plus Dinv_k times the change, which reads only the columns
+// sel of Dinv_k.  One thread per row of an odd block, blockIdx.y the slab.
+template <typename C>
+__global__ __launch_bounds__(256) void k_odd0_upd(SlabSet<C> S, size_t o0, int n, int q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (n / 2) * q) return;
+  const int z = blockIdx.y;
+  const int j = e / q, r = e - j * q, k = 2 * j + 1;
+  const C* __restrict__ D = S.fac[z] + o0 + (size_t)j * q * q;  // column-major Dinv_k
+  const C* __restrict__ inj = S.inj[z] + (size_t)k * 4;
+  C* __restrict__ y = S.y[z];
+  C acc = y[(size_t)k * q + r];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (S.sel[z][u] == r) acc = S.save[z][(size_t)j * 4 + u];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = S.sel[z][u];
+    if (c >= 0) acc = tfma(D[(size_t)c * q + r], inj[u], acc);
+  }
+  y[(size_t)k * q + r] = acc;
 }
 
 // level 0, odd blocks: t_k = L_k y_{k-1} + U_k y_{k+1} (L, U from the
@@ -1424,6 +1456,7 @@ struct LayerSet {
   TraceInj dn[kSet], up[kSet];
   const T* tau[kSet];
   const T* sig[kSet];
+  T* inj[kSet];  // k_inject_set: each added source also to inj[i][slot] (or null)
 };
 
 // x^l[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere, for
@@ -1485,7 +1518,11 @@ __global__ void k_inject_set(LayerSet<T> S, int n) {
         acc = tfma(cf[dX + 1], tr[(size_t)p * n + ii], acc);
       }
       T* o = rhs + (size_t)i * q + J.rt[p];
-      *o = tadd(*o, tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]));
+      const T src = tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]);
+      *o = tadd(*o, src);
+      // slots as the chain rows: 0, 1 the upward pair (rows a, a - 1), 2, 3
+      // the downward pair (rows b, b + 1)
+      if (S.inj[z]) S.inj[z][(size_t)i * 4 + (s ? p : 2 + p)] = src;
     }
   }
 }
@@ -2102,6 +2139,8 @@ ls_status slabs_build(ls_plan* p) {
     const size_t Lmax = std::max(p->slabs[0].size(), p->slabs[1].size());
     p->set_qmax = qmax;
     LS_TRY(plan_alloc(p, &p->set_elim, Lmax * n * qmax * esz));
+    LS_TRY(plan_alloc(p, &p->set_save, Lmax * (size_t)(n / 2) * 4 * esz));
+    LS_TRY(plan_alloc(p, &p->set_inj, Lmax * (size_t)n * 4 * esz));
     LS_HIP(hipEventCreateWithFlags(&p->side_fork, hipEventDisableTiming));
     for (int k = 0; k < ls_plan::kSide; ++k) {
       LS_HIP(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
@@ -2204,7 +2243,10 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
-  step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
+  if (rows == ROWS_RANGE && S.save[0] && S.inj[0])
+    k_odd0_upd<C><<<dim3(((n / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, n, q);
+  else
+    step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
   k_even0<C><<<dim3((((n + 1) / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
   // levels from `top` up: one dense operator when the plan built it
   const int top_l = (s.top_level >= 1 && S.top[0]) ? s.top_level : nlev - 1;
@@ -2408,6 +2450,7 @@ static LayerSet<T> layer_set(ls_plan* p, std::vector<Slab>& S, int l0, int cnt, 
     ls.up[k] = inj_up(s);
     ls.tau[k] = (tau && l <= L - 2) ? tau + (size_t)(l + 1) * N2 : nullptr;
     ls.sig[k] = (sig && l >= 1) ? sig + (size_t)(l - 1) * N2 : nullptr;
+    ls.inj[k] = ((tau || sig) && p->set_inj) ? static_cast<T*>(p->set_inj) + (size_t)l * p->n * 4 : nullptr;
   }
   return ls;
 }
@@ -2439,6 +2482,11 @@ static ls_status solve_groups(ls_plan* p, int orient, bool chains) {
       for (int u = 0; u < 4; ++u) ss.sel[k][u] = (want[u] >= 0 && want[u] < s.q) ? want[u] : -1;
       ss.lo[k] = s.a - s.z0;
       ss.hi[k] = s.b - s.z0 + 1;
+      // the first solves keep the level-0 values of the chain rows, the
+      // second update the level-0 step from them and the trace sources
+      // (which enter exactly those rows: up pair a, a - 1; down pair b, b + 1)
+      ss.save[k] = static_cast<T*>(p->set_save) + (size_t)grp[k] * (p->n / 2) * 4;
+      ss.inj[k] = static_cast<const T*>(p->set_inj) + (size_t)grp[k] * p->n * 4;
     }
     return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size(), chains ? ROWS_SEL : ROWS_RANGE);
   };
