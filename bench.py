@@ -68,14 +68,20 @@ def slab_solve_bytes(n, q):
 def sweep_bytes(n, qs, spans):
     """Algorithmic bytes of one decoupled sweep (Alg. 1, FP64, one
     right-hand side) over layers of thicknesses qs and spans layer lines:
-    every layer's slab solved twice (slab_solve_bytes each), less the rows
-    of the level-0 odd blocks' inverses that the last step does not need
-    (n/2 blocks of (q - r) q entries: the first solve completes the r = 4
-    grid lines the trace chains read, the second the r = span layer lines
-    the scatter reads); the trace-transfer maps read once ((L - 2) mT,
-    (L - 1) mU and (L - 2) mV, each (2n)^2 c128); g read and v written once."""
+    every layer's slab solved twice (slab_solve_bytes each), less what of the
+    level-0 odd blocks' inverses (n/2 blocks of q x q) the steps do not need:
+    the first solve's last step completes only the c chain rows (4, or 2 for
+    the first and last layer) the trace chains read, the second solve's last
+    step only the r = span layer lines the scatter reads, and the second
+    solve's first step takes the first one's level-0 values plus the inverse
+    times the trace sources, which enter the c chain rows (c columns read);
+    the trace-transfer maps read once ((L - 2) mT, (L - 1) mU and (L - 2) mV,
+    each (2n)^2 c128); g read and v written once."""
     L = len(qs)
-    solves = sum(2 * slab_solve_bytes(n, q) - (n // 2) * (2 * q - 4 - r) * q * 16 for q, r in zip(qs, spans))
+    solves = 0
+    for l, (q, r) in enumerate(zip(qs, spans)):
+        c = 4 if 0 < l < L - 1 else 2
+        solves += 2 * slab_solve_bytes(n, q) - (n // 2) * ((q - c) + (q - r) + (q - c)) * q * 16
     return solves + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
 
 

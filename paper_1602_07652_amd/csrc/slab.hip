@@ -329,8 +329,14 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   const int R = MODE == R_BWD0S ? 4 : (rhi - rlo + RS - 1) / RS, r0 = rlo + rs * R;
   const int tid = threadIdx.x;
   const int rl = tid % R, grp = tid / R, G = 256 / R;
-  // row of tile entry i: r0 + i, or the selected row (R_BWD0S)
-  auto row_of = [&](int i) { return MODE == R_BWD0S ? S.sel[z][i] : r0 + i; };
+  // row of tile entry i: r0 + i, or the selected row (R_BWD0S; the four
+  // rows read as uniform values and picked per lane by selects, not by a
+  // per-lane index into the argument array, which would go through scratch)
+  const int s0 = MODE == R_BWD0S ? S.sel[z][0] : 0, s1 = MODE == R_BWD0S ? S.sel[z][1] : 0;
+  const int s2 = MODE == R_BWD0S ? S.sel[z][2] : 0, s3 = MODE == R_BWD0S ? S.sel[z][3] : 0;
+  auto row_of = [&](int i) {
+    return MODE == R_BWD0S ? (i == 0 ? s0 : (i == 1 ? s1 : (i == 2 ? s2 : s3))) : r0 + i;
+  };
   const bool act = grp < G && (MODE == R_BWD0S ? row_of(rl) >= 0 : r0 + rl < rhi);
   const size_t qq = (size_t)q * q;
   int k = 0, T = 1;
@@ -398,6 +404,7 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   __syncthreads();
   if (tid < R && (MODE == R_BWD0S ? row_of(tid) >= 0 : r0 + tid < rhi)) {
     C sum = tmk<C>(0, 0);
+#pragma unroll 8
     for (int gg = 0; gg < G; ++gg) sum = tadd(sum, part[gg * R + tid]);
     const int r = row_of(tid);
     if (MODE == R_ODD0) y[(size_t)k * q + r] = sum;
