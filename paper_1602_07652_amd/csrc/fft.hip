@@ -23,6 +23,7 @@
 #include "ls_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 namespace {
@@ -890,6 +891,206 @@ __global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_rows_inv_reg(const
   }
 }
 
+// K1 / K3 for FP64 rows with every LDS exchange made in two halves, real
+// parts then imaginary parts: a row then needs one real per element of LDS
+// (half the complex buffer), so the LDS limit on resident rows per CU (two
+// waves per SIMD for FP64 at 2048 points) moves up to what registers allow
+// (three for K1, four for K3), at twice the barriers per exchange.  Same
+// passes, twiddles and arithmetic order as k_rows_fwd_reg / k_rows_inv_reg,
+// so the results are the same bit for bit.
+#ifndef LS_ROW_SPLIT
+#define LS_ROW_SPLIT 1
+#endif
+constexpr bool kRowSplit = LS_ROW_SPLIT != 0;
+
+// a[PO][RO] to element positions po(q, r), then b[PI][RI] from positions
+// pi(q, r), through the real buffer bx (real parts, then imaginary parts).
+template <typename T, int PO, int RO, int PI, int RI, class FO, class FI>
+__device__ __forceinline__ void xchg_halves(typename CT<T>::R* bx, const T (&a)[PO][RO], T (&b)[PI][RI], FO po,
+                                            FI pi) {
+#pragma unroll
+  for (int q = 0; q < PO; ++q)
+#pragma unroll
+    for (int r = 0; r < RO; ++r) bx[po(q, r)] = a[q][r].x;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PI; ++q)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) b[q][r].x = bx[pi(q, r)];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PO; ++q)
+#pragma unroll
+    for (int r = 0; r < RO; ++r) bx[po(q, r)] = a[q][r].y;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PI; ++q)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) b[q][r].y = bx[pi(q, r)];
+  __syncthreads();
+}
+
+template <typename T, int LOGN, int H>
+struct SxCfg {
+  using C = RegCfg<T, LOGN, H>;
+  static constexpr size_t lds() { return (size_t)C::CPW * C::ROW * sizeof(typename CT<T>::R); }
+};
+
+// The middle pass of the row kernels on registers: butterflies bi = tid +
+// NT q (q < P), radix R, span NS; returns nothing, a is transformed in place.
+template <typename T, int N, int R, int NS, int P, int NT, bool INV>
+__device__ __forceinline__ void mid_pass(T (&a)[P][R], const T* __restrict__ tw, int tid) {
+  constexpr int NB = N / R;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int j = (tid + NT * q) % NB;
+    twiddle_r<T, N, R, NS, INV>(a[q], j, tw);
+    dft_r<T, R, INV>(a[q]);
+  }
+}
+
+template <typename T, typename R, int LOGN, int H>
+__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_rows_fwd_sx(const T* __restrict__ v,
+                                                                         const R* __restrict__ m,
+                                                                         T* __restrict__ X,
+                                                                         const T* __restrict__ tw, int n,
+                                                                         int total_rows) {
+  using C = RegCfg<T, LOGN, H>;
+  using PL = RegPlan<LOGN>;
+  constexpr int N = C::N, CPW = C::CPW, ROW = C::ROW, NT = C::NT;
+  constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
+  constexpr int NB0 = N / R0, NB1 = N / R1, NB2 = N / R2;
+  constexpr int P1 = CPW * NB1 / NT, P2 = CPW * NB2 / NT;
+  extern __shared__ unsigned char lds_raw[];
+  typename CT<T>::R* bx = reinterpret_cast<typename CT<T>::R*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * CPW;
+  T a0[1][R0];
+  int cc0, j0;
+  rsplit<NB0>(tid, cc0, j0);
+  {  // pass 0 (radix 16, span 1) from memory: pad(m . v), n nonzero inputs
+    const int row = row0 + cc0;
+    const bool live = row < total_rows;
+    const int jr = live ? row % n : 0;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int i = j0 + r * NB0;
+      a0[0][r] = tmk<T>(0, 0);
+      if (live && i < n) {
+        const T vv = v[(size_t)row * n + i];
+        const R mm = m[(size_t)jr * n + i];
+        a0[0][r].x = vv.x * mm;
+        a0[0][r].y = vv.y * mm;
+      }
+    }
+    dft_r<T, R0, false>(a0[0]);
+  }
+  T a1[P1][R1];
+  xchg_halves<T, 1, R0, P1, R1>(
+      bx, a0, a1, [&](int, int r) { return cc0 * ROW + lpad(j0 * R0 + r); },
+      [&](int q, int r) {
+        const int bi = tid + NT * q;
+        return (bi / NB1) * ROW + lpad(bi % NB1 + r * NB1);
+      });
+  mid_pass<T, N, R1, R0, P1, NT, false>(a1, tw, tid);
+  T a2[P2][R2];
+  xchg_halves<T, P1, R1, P2, R2>(
+      bx, a1, a2,
+      [&](int q, int r) {
+        const int bi = tid + NT * q, j = bi % NB1, k = j & (R0 - 1);
+        return (bi / NB1) * ROW + lpad((j - k) * R1 + k + r * R0);
+      },
+      [&](int q, int r) {
+        const int bi = tid + NT * q;
+        return (bi / NB2) * ROW + lpad(bi % NB2 + r * NB2);
+      });
+  // last pass: natural order straight to the tiled intermediate
+#pragma unroll
+  for (int q = 0; q < P2; ++q) {
+    int cc, j;
+    rsplit<NB2>(tid + NT * q, cc, j);
+    twiddle_r<T, N, R2, R0 * R1, false>(a2[q], j, tw);
+    dft_r<T, R2, false>(a2[q]);
+    const int row = row0 + cc;
+    if (row < total_rows) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) X[tiled<T>(row / n, n, N, row % n, j + r * NB2)] = a2[q][r];
+    }
+  }
+}
+
+template <typename T, int LOGN, int H>
+__global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_rows_inv_sx(const T* __restrict__ X,
+                                                                         const T* v, T* y,
+                                                                         const T* __restrict__ tw, int n,
+                                                                         int total_rows, double a_s,
+                                                                         double b_s) {
+  using C = RegCfg<T, LOGN, H>;
+  using PL = RegPlan<LOGN>;
+  constexpr int N = C::N, CPW = C::CPW, ROW = C::ROW, NT = C::NT;
+  constexpr int R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
+  constexpr int NB0 = N / R0, NB1 = N / R1, NB2 = N / R2;
+  constexpr int P1 = CPW * NB1 / NT, P2 = CPW * NB2 / NT;
+  extern __shared__ unsigned char lds_raw[];
+  typename CT<T>::R* bx = reinterpret_cast<typename CT<T>::R*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * CPW;
+  T a0[1][R0];
+  int cc0, j0;
+  rsplit<NB0>(tid, cc0, j0);
+  {  // pass 0 from the tiled intermediate
+    const int row = row0 + cc0;
+#pragma unroll
+    for (int r = 0; r < R0; ++r)
+      a0[0][r] = row < total_rows ? X[tiled<T>(row / n, n, N, row % n, j0 + r * NB0)] : tmk<T>(0, 0);
+    dft_r<T, R0, true>(a0[0]);
+  }
+  T a1[P1][R1];
+  xchg_halves<T, 1, R0, P1, R1>(
+      bx, a0, a1, [&](int, int r) { return cc0 * ROW + lpad(j0 * R0 + r); },
+      [&](int q, int r) {
+        const int bi = tid + NT * q;
+        return (bi / NB1) * ROW + lpad(bi % NB1 + r * NB1);
+      });
+  mid_pass<T, N, R1, R0, P1, NT, true>(a1, tw, tid);
+  T a2[P2][R2];
+  xchg_halves<T, P1, R1, P2, R2>(
+      bx, a1, a2,
+      [&](int q, int r) {
+        const int bi = tid + NT * q, j = bi % NB1, k = j & (R0 - 1);
+        return (bi / NB1) * ROW + lpad((j - k) * R1 + k + r * R0);
+      },
+      [&](int q, int r) {
+        const int bi = tid + NT * q;
+        return (bi / NB2) * ROW + lpad(bi % NB2 + r * NB2);
+      });
+  // last pass: natural order, the n kept outputs, y = a v + b conv
+#pragma unroll
+  for (int q = 0; q < P2; ++q) {
+    int cc, j;
+    rsplit<NB2>(tid + NT * q, cc, j);
+    twiddle_r<T, N, R2, R0 * R1, true>(a2[q], j, tw);
+    dft_r<T, R2, true>(a2[q]);
+    const int row = row0 + cc;
+    if (row >= total_rows) continue;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int i = j + r * NB2;
+      if (i >= n) continue;
+      const size_t idx = (size_t)row * n + i;
+      T conv = a2[q][r];
+      conv.x *= b_s;
+      conv.y *= b_s;
+      if (a_s != 0.0) {
+        const T vv = v[idx];
+        conv.x = fma((decltype(conv.x))a_s, vv.x, conv.x);
+        conv.y = fma((decltype(conv.y))a_s, vv.y, conv.y);
+      }
+      y[idx] = conv;
+    }
+  }
+}
+
 // K3: y = a v + b * (first n of IFFT_rows(X)).
 template <typename T, int LOGN>
 __global__ __launch_bounds__(RowCfg<LOGN>::NT) void k_rows_inv(const T* __restrict__ X,
@@ -1058,7 +1259,14 @@ ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, doub
   LS_SET_LDS_ONCE((k_rows_inv<T, LOGN>), lds_r);
   constexpr bool reg = LOGN >= 10 && LOGN <= 12;
   using RR = RegCfg<T, LOGN, kRowHalf>;
-  if constexpr (reg) {
+  constexpr bool sx = reg && kRowSplit && std::is_same<T, cplx>::value;
+  using SX = SxCfg<T, LOGN, kRowHalf>;
+  if constexpr (sx) {
+    LS_SET_LDS_ONCE((k_rows_fwd_sx<T, R, LOGN, kRowHalf>), SX::lds());
+    LS_SET_LDS_ONCE((k_rows_inv_sx<T, LOGN, kRowHalf>), SX::lds());
+    k_rows_fwd_sx<T, R, LOGN, kRowHalf><<<(rows + RR::CPW - 1) / RR::CPW, RR::NT, SX::lds(), av.stream>>>(
+        v, av.m, av.work, av.tw, n, rows);
+  } else if constexpr (reg) {
     LS_SET_LDS_ONCE((k_rows_fwd_reg<T, R, LOGN, kRowHalf>), RR::lds());
     LS_SET_LDS_ONCE((k_rows_inv_reg<T, LOGN, kRowHalf>), RR::lds());
     k_rows_fwd_reg<T, R, LOGN, kRowHalf><<<(rows + RR::CPW - 1) / RR::CPW, RR::NT, RR::lds(), av.stream>>>(
@@ -1093,7 +1301,10 @@ ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, doub
       else LS_TRY((run_cols<T, LOGN, 0>(av, batch)));
       break;
   }
-  if constexpr (reg)
+  if constexpr (sx)
+    k_rows_inv_sx<T, LOGN, kRowHalf><<<(rows + RR::CPW - 1) / RR::CPW, RR::NT, SX::lds(), av.stream>>>(
+        av.work, v, y, av.tw, n, rows, a, b);
+  else if constexpr (reg)
     k_rows_inv_reg<T, LOGN, kRowHalf><<<(rows + RR::CPW - 1) / RR::CPW, RR::NT, RR::lds(), av.stream>>>(
         av.work, v, y, av.tw, n, rows, a, b);
   else
