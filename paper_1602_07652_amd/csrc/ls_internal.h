@@ -235,7 +235,7 @@ struct ls_plan {
   std::vector<GraphEntry> graphs;
   cplx* solve_buf = nullptr;     // FP64 plans, learned solves: two grid-vector batches
   int col_variant64 = 0, col_variant32 = 0;  // autotuned FFT column-pass variants
-  float tune_ms64[8] = {}, tune_ms32[8] = {};
+  float tune_ms64[8] = {}, tune_ms32[8] = {};  // one per FFT column-pass variant
   int cus = 256;                 // compute units of the plan's device
   // wall time of the off-line stages (ls_plan_timings): kernel samples and
   // circulant, stencils, spectrum, slab assembly, slab factorisation, top
