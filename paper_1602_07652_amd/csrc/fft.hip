@@ -897,11 +897,8 @@ __global__ __launch_bounds__((RegCfg<T, LOGN, H>::NT)) void k_rows_inv_reg(const
 // waves per SIMD for FP64 at 2048 points) moves up to what registers allow
 // (three for K1, four for K3), at twice the barriers per exchange.  Same
 // passes, twiddles and arithmetic order as k_rows_fwd_reg / k_rows_inv_reg,
-// so the results are the same bit for bit.
-#ifndef LS_ROW_SPLIT
-#define LS_ROW_SPLIT 1
-#endif
-constexpr bool kRowSplit = LS_ROW_SPLIT != 0;
+// so the results are the same bit for bit (FP32 rows keep the complex
+// exchange: their LDS already allows what their registers do).
 
 // a[PO][RO] to element positions po(q, r), then b[PI][RI] from positions
 // pi(q, r), through the real buffer bx (real parts, then imaginary parts).
@@ -1259,7 +1256,7 @@ ls_status run_apply(const ApplyView<T, R>& av, const T* v, T* y, int batch, doub
   LS_SET_LDS_ONCE((k_rows_inv<T, LOGN>), lds_r);
   constexpr bool reg = LOGN >= 10 && LOGN <= 12;
   using RR = RegCfg<T, LOGN, kRowHalf>;
-  constexpr bool sx = reg && kRowSplit && std::is_same<T, cplx>::value;
+  constexpr bool sx = reg && std::is_same<T, cplx>::value;
   using SX = SxCfg<T, LOGN, kRowHalf>;
   if constexpr (sx) {
     LS_SET_LDS_ONCE((k_rows_fwd_sx<T, R, LOGN, kRowHalf>), SX::lds());
