@@ -156,6 +156,18 @@ ls_status ls_plan_create_like(ls_plan** out, const ls_plan* src, const double* m
  * <= 9 entries are written (more are zeroed).  HOST array. */
 ls_status ls_plan_timings(const ls_plan* plan, double* ms, int count);
 
+/* Choices the plan made at creation (Section 4.1 off-line stage): info[0]
+ * = 1 when the one-right-hand-side slab solves take the level-0 odd
+ * blocks' steps by the tridiagonal elimination (those blocks are
+ * tridiagonal: the local matrices of Section 3.2, built from Section 2's
+ * 9-point stencils, couple a point of a column only to its two vertical
+ * neighbours in that column; every block's elimination agreed with its
+ * dense inverse), 0 when they use the dense inverses;
+ * info[1] = blocks of the dense top-of-reduction operator of the first slab
+ * (0: none).  count entries are written (beyond 2: zeros).  HOST array;
+ * LS_EINVAL for a null plan or array or count < 1. */
+ls_status ls_plan_info(const ls_plan* plan, int* info, int count);
+
 /* Frees the plan (synchronises its stream first).  NULL is accepted. */
 ls_status ls_plan_destroy(ls_plan* plan);
 

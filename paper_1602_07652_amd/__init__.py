@@ -81,6 +81,7 @@ def lib():
         "ls_plan_destroy": (_i, [_vp]),
         "ls_plan_create_like": (_i, [ctypes.POINTER(_vp), _vp, _vp, ctypes.POINTER(Options), _vp]),
         "ls_plan_timings": (_i, [_vp, ctypes.POINTER(_d), _i]),
+        "ls_plan_info": (_i, [_vp, ctypes.POINTER(_i), _i]),
         "ls_apply": (_i, [_vp, _vp, _vp, _i]),
         "ls_apply_c64": (_i, [_vp, _vp, _vp, _i]),
         "ls_rhs_from_incident": (_i, [_vp, _vp, _vp, _i]),
@@ -305,6 +306,12 @@ class Plan:
         ms = (_d * 9)()
         _check("ls_plan_timings", lib().ls_plan_timings(self.handle, ms, 9))
         return dict(zip(self.STAGES, list(ms)))
+
+    def info(self):
+        """ls_plan_info: {"tridiagonal_level0": 0/1, "top_blocks": blocks}."""
+        v = (_i * 2)()
+        _check("ls_plan_info", lib().ls_plan_info(self.handle, v, 2))
+        return {"tridiagonal_level0": v[0], "top_blocks": v[1]}
 
     def slab_info(self, orient, slab):
         lims = (_i * 4)()

@@ -704,6 +704,19 @@ ls_status ls_plan_timings(const ls_plan* p, double* ms, int count) {
   return LS_OK;
 }
 
+ls_status ls_plan_info(const ls_plan* p, int* info, int count) {
+  if (!p || !info || count < 1) {
+    ls_set_error("ls_plan_info: bad arguments");
+    return LS_EINVAL;
+  }
+  int top_blocks = 0;  // blocks of the first slab's dense top operator (0: none)
+  if (!p->slabs[0].empty() && p->slabs[0][0].top_level >= 1)
+    top_blocks = p->slabs[0][0].levels[p->slabs[0][0].top_level].nl;
+  const int v[2] = {p->tri_ok ? 1 : 0, top_blocks};
+  for (int i = 0; i < count; ++i) info[i] = i < 2 ? v[i] : 0;
+  return LS_OK;
+}
+
 ls_status ls_plan_dims(const ls_plan* p, int* P, int* L, int* spec_side) {
   if (!p) return LS_EINVAL;
   if (P) *P = p->P;

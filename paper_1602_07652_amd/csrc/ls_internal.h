@@ -106,6 +106,10 @@ struct Slab {
   // k - 1 (side 0) or k + 1 (side 1)), in the plan's precision
   cplx* cpl = nullptr;
   fcplx* cpl32 = nullptr;
+  // level-0 odd blocks as tridiagonal systems [n/2][3][q]: the sub-diagonal,
+  // diagonal and super-diagonal of each block, in the plan's precision
+  cplx* tri = nullptr;
+  fcplx* tri32 = nullptr;
   cplx* fac;         // block-cyclic-reduction factors (offsets in levels)
   size_t fac_elems;
   std::vector<SlabLevel> levels;  // levels[0] .. levels[nlev-1]; last has nl == 1
@@ -248,12 +252,10 @@ struct ls_plan {
   // the groups after the first concurrently
   std::vector<std::vector<int>> dec_groups[2];
   void* set_elim = nullptr;
-  // decoupled sweep, per layer: the level-0 forward values of the four chain
-  // rows of the odd blocks [L][n/2][4] kept by the first solves, and the
-  // trace sources added to those rows of every block [L][n][4]; the second
-  // solves update the level-0 step from them instead of redoing it
-  void* set_save = nullptr;
-  void* set_inj = nullptr;
+  // the one-right-hand-side slab solves take their level-0 odd steps as
+  // tridiagonal solves (every block's agreed with its dense inverse at plan
+  // creation)
+  bool tri_ok = false;
   int set_qmax = 0;
   static constexpr int kSide = 4;
   hipStream_t side[kSide] = {};

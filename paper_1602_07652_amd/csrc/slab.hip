@@ -36,6 +36,7 @@
 #include "ls_internal.h"
 
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <mutex>
 
@@ -305,8 +306,7 @@ struct SlabSet {
   const C* top[kSet];  // dense top operators (or null)
   int sel[kSet][4];    // R_BWD0S: the rows to compute, -1 = unused
   int lo[kSet], hi[kSet];  // R_BWD0R: the rows [lo, hi) to compute
-  C* save[kSet];       // R_BWD0S: the level-0 values of the rows sel, [n/2][4] (or null)
-  const C* inj[kSet];  // k_odd0_upd: the sources added to the rows sel, [n][4]
+  const C* tri[kSet];  // level-0 odd blocks' tridiagonal factors [q][3][n/2] (or null)
 };
 
 template <typename C, int MODE>
@@ -411,38 +411,178 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
     else if (MODE == R_FWD) { C* o = t + ((size_t)k << shift) * q + r; *o = tsub(*o, sum); }
     else if (MODE == R_LAST) y[r] = sum;
     else if (MODE == R_BWD) y[((size_t)k << shift) * q + r] = sum;
-    else {
-      C* o = y + (size_t)k * q + r;
-      if (MODE == R_BWD0S && S.save[z]) S.save[z][(size_t)blk * 4 + tid] = *o;
-      *o = tsub(*o, sum);
-    }
+    else { C* o = y + (size_t)k * q + r; *o = tsub(*o, sum); }
   }
 }
 
-// Level 0, odd blocks, once the right-hand side has changed only in the
-// rows sel (by the sources inj): the level-0 values y_k = Dinv_k g_k of an
-// earlier solve of the old right-hand side (still in y, those of the rows
-// sel in save) plus Dinv_k times the change, which reads only the columns
-// sel of Dinv_k.  One thread per row of an odd block, blockIdx.y the slab.
+// Level 0, odd blocks, as tridiagonal systems.  The diagonal block D_k of a
+// level-0 odd block k couples each point of grid column k only to the
+// points above and below it (the 9-point stencil's vertical neighbours), so
+// D_k is tridiagonal and D_k x = b needs three numbers per row instead of
+// the q x q inverse.  One wave solves one block by parallel cyclic
+// reduction (no pivoting): lane L holds rows L and L + 64 (q <= 128); each
+// of the ceil(log2 q) steps eliminates, from every row, its couplings to the
+// rows s above and below (s = 1, 2, 4, ...), until every row stands alone.
+// The sub-diagonal, diagonal and super-diagonal of every block are kept as
+// [n/2][3][q] (zero sub- and super-diagonal outside the block).  The plan
+// compares every block's reduction with its dense inverse and keeps the
+// dense steps when one disagrees.  blockIdx.x the block, blockIdx.y the slab.
+constexpr int kPcrRows = 128;
+
 template <typename C>
-__global__ __launch_bounds__(256) void k_odd0_upd(SlabSet<C> S, size_t o0, int n, int q) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (n / 2) * q) return;
-  const int z = blockIdx.y;
-  const int j = e / q, r = e - j * q, k = 2 * j + 1;
-  const C* __restrict__ D = S.fac[z] + o0 + (size_t)j * q * q;  // column-major Dinv_k
-  const C* __restrict__ inj = S.inj[z] + (size_t)k * 4;
-  C* __restrict__ y = S.y[z];
-  C acc = y[(size_t)k * q + r];
+__device__ __forceinline__ void pcr_wave(const C* __restrict__ abc, C (&d)[2], int q, C* __restrict__ sh) {
+  const int lane = threadIdx.x;
+  C* sa = sh;
+  C* sb = sh + kPcrRows;
+  C* sc = sh + 2 * kPcrRows;
+  C* sd = sh + 3 * kPcrRows;
+  C a[2], b[2], c[2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-    if (S.sel[z][u] == r) acc = S.save[z][(size_t)j * 4 + u];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = S.sel[z][u];
-    if (c >= 0) acc = tfma(D[(size_t)c * q + r], inj[u], acc);
+  for (int u = 0; u < 2; ++u) {
+    const int i = lane + 64 * u;
+    const bool in = i < q;
+    a[u] = in ? abc[i] : tmk<C>(0, 0);
+    b[u] = in ? abc[q + i] : tmk<C>(1, 0);
+    c[u] = in ? abc[2 * q + i] : tmk<C>(0, 0);
+    if (!in) d[u] = tmk<C>(0, 0);
   }
-  y[(size_t)k * q + r] = acc;
+  for (int s = 1; s < q; s <<= 1) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = lane + 64 * u;
+      if (i < q) {
+        sa[i] = a[u];
+        sb[i] = b[u];
+        sc[i] = c[u];
+        sd[i] = d[u];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = lane + 64 * u;
+      if (i >= q) continue;
+      C na = tmk<C>(0, 0), nc = tmk<C>(0, 0), nb = b[u], nd = d[u];
+      if (i - s >= 0) {  // alpha = -a_i / b_{i-s}
+        const C bm = sb[i - s];
+        const auto r = 1.0 / ((double)bm.x * bm.x + (double)bm.y * bm.y);
+        const C al = tmk<C>(-(a[u].x * bm.x + a[u].y * bm.y) * r, -(a[u].y * bm.x - a[u].x * bm.y) * r);
+        na = tmul(al, sa[i - s]);
+        nb = tfma(al, sc[i - s], nb);
+        nd = tfma(al, sd[i - s], nd);
+      }
+      if (i + s < q) {  // gamma = -c_i / b_{i+s}
+        const C bp = sb[i + s];
+        const auto r = 1.0 / ((double)bp.x * bp.x + (double)bp.y * bp.y);
+        const C ga = tmk<C>(-(c[u].x * bp.x + c[u].y * bp.y) * r, -(c[u].y * bp.x - c[u].x * bp.y) * r);
+        nc = tmul(ga, sc[i + s]);
+        nb = tfma(ga, sa[i + s], nb);
+        nd = tfma(ga, sd[i + s], nd);
+      }
+      a[u] = na;
+      b[u] = nb;
+      c[u] = nc;
+      d[u] = nd;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const auto r = 1.0 / ((double)b[u].x * b[u].x + (double)b[u].y * b[u].y);
+    d[u] = tmk<C>((d[u].x * b[u].x + d[u].y * b[u].y) * r, (d[u].y * b[u].x - d[u].x * b[u].y) * r);
+  }
+}
+
+// y_k = D_k^{-1} g_k (the level-0 odd step).
+template <typename C>
+__global__ __launch_bounds__(64) void k_tri_odd0(SlabSet<C> S, int n, int q) {
+  __shared__ C sh[4 * kPcrRows];
+  const int z = blockIdx.y, j = blockIdx.x, k = 2 * j + 1, lane = threadIdx.x;
+  const C* __restrict__ g = S.g[z] + (size_t)k * q;
+  C d[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) d[u] = lane + 64 * u < q ? g[lane + 64 * u] : tmk<C>(0, 0);
+  pcr_wave<C>(S.tri[z] + (size_t)j * 3 * q, d, q, sh);
+  C* __restrict__ y = S.y[z] + (size_t)k * q;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (lane + 64 * u < q) y[lane + 64 * u] = d[u];
+}
+
+// y_k -= D_k^{-1} t_k on the rows the step completes (all of them, the rows
+// S.sel, or [S.lo, S.hi)), t_k = L_k y_{k-1} + U_k y_{k+1} as formed by
+// k_odd0_lu.
+template <typename C, int ROWS>
+__global__ __launch_bounds__(64) void k_tri_bwd0(SlabSet<C> S, int n, int q) {
+  __shared__ C sh[4 * kPcrRows];
+  const int z = blockIdx.y, j = blockIdx.x, k = 2 * j + 1, lane = threadIdx.x;
+  const C* __restrict__ t = S.t[z] + (size_t)k * q;
+  C d[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) d[u] = lane + 64 * u < q ? t[lane + 64 * u] : tmk<C>(0, 0);
+  pcr_wave<C>(S.tri[z] + (size_t)j * 3 * q, d, q, sh);
+  const int s0 = S.sel[z][0], s1 = S.sel[z][1], s2 = S.sel[z][2], s3 = S.sel[z][3];
+  const int lo = S.lo[z], hi = S.hi[z];
+  C* __restrict__ y = S.y[z] + (size_t)k * q;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int r = lane + 64 * u;
+    bool keep = r < q;
+    if (ROWS == 1) keep = keep && (r == s0 || r == s1 || r == s2 || r == s3);
+    if (ROWS == 2) keep = keep && r >= lo && r < hi;
+    if (keep) y[r] = tsub(y[r], d[u]);
+  }
+}
+
+// The three diagonals of every level-0 odd block of a slab from its
+// assembled stencil, in the type T of the solves.
+template <typename T>
+__global__ void k_tri_coef(const cplx* __restrict__ coef, T* __restrict__ tri, int n, int q) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)(n / 2) * q) return;
+  const int j = (int)(e / q), r = (int)(e % q), k = 2 * j + 1;
+  const cplx* cf = coef + ((size_t)k * q + r) * 9;
+  const cplx a = r > 0 ? cf[1] : cmk(0, 0), b = cf[4], c = r + 1 < q ? cf[7] : cmk(0, 0);
+  T* o = tri + (size_t)j * 3 * q + r;
+  o[0] = tmk<T>(a.x, a.y);
+  o[q] = tmk<T>(b.x, b.y);
+  o[2 * q] = tmk<T>(c.x, c.y);
+}
+
+// Largest relative difference, over the level-0 odd blocks of a slab,
+// between the reduction's D_k^{-1} e and the dense inverse's Dinv_k e (e =
+// all ones; FP64), as the bits of a non-negative float (atomicMax on the
+// bits orders them as the values).
+__global__ __launch_bounds__(64) void k_tri_check(const cplx* __restrict__ tri, const cplx* __restrict__ dinv,
+                                                  int n, int q, unsigned* __restrict__ worst) {
+  __shared__ cplx sh[4 * kPcrRows];
+  __shared__ double red[2][64];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  cplx d[2] = {cmk(1, 0), cmk(1, 0)};
+  pcr_wave<cplx>(tri + (size_t)j * 3 * q, d, q, sh);
+  const cplx* D = dinv + (size_t)j * q * q;
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int r = lane + 64 * u;
+    if (r >= q) continue;
+    cplx e = cmk(0, 0);
+    for (int c = 0; c < q; ++c) e = tadd(e, D[(size_t)c * q + r]);
+    const double ex = d[u].x - e.x, ey = d[u].y - e.y;
+    num = fmax(num, sqrt(ex * ex + ey * ey));
+    den = fmax(den, sqrt(e.x * e.x + e.y * e.y));
+  }
+  red[0][lane] = num;
+  red[1][lane] = den;
+  __syncthreads();
+  if (lane == 0) {
+    for (int l = 1; l < 64; ++l) {
+      num = fmax(num, red[0][l]);
+      den = fmax(den, red[1][l]);
+    }
+    const float rel = den > 0.0 ? (float)(num / den) : (num > 0.0 ? 1e30f : 0.0f);
+    atomicMax(worst, __float_as_uint(isfinite(rel) ? rel : 1e30f));
+  }
 }
 
 // level 0, odd blocks: t_k = L_k y_{k-1} + U_k y_{k+1} (L, U from the
@@ -1463,7 +1603,6 @@ struct LayerSet {
   TraceInj dn[kSet], up[kSet];
   const T* tau[kSet];
   const T* sig[kSet];
-  T* inj[kSet];  // k_inject_set: each added source also to inj[i][slot] (or null)
 };
 
 // x^l[i][r] = g(i, z0 + r) on the layer lines [a, b], 0 elsewhere, for
@@ -1525,11 +1664,7 @@ __global__ void k_inject_set(LayerSet<T> S, int n) {
         acc = tfma(cf[dX + 1], tr[(size_t)p * n + ii], acc);
       }
       T* o = rhs + (size_t)i * q + J.rt[p];
-      const T src = tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]);
-      *o = tadd(*o, src);
-      // slots as the chain rows: 0, 1 the upward pair (rows a, a - 1), 2, 3
-      // the downward pair (rows b, b + 1)
-      if (S.inj[z]) S.inj[z][(size_t)i * 4 + (s ? p : 2 + p)] = src;
+      *o = tadd(*o, tmk<T>(acc.x * J.sgn[p], acc.y * J.sgn[p]));
     }
   }
 }
@@ -2042,6 +2177,10 @@ ls_status slabs_build(ls_plan* p) {
   }
   LS_HIP(hipMalloc(&status, sizeof(int)));
   LS_HIP(hipMemsetAsync(status, 0, sizeof(int), p->stream));
+  unsigned* tri_worst = nullptr;  // largest elimination-vs-inverse difference (float bits)
+  LS_HIP(hipMalloc(&tri_worst, sizeof(unsigned)));
+  LS_HIP(hipMemsetAsync(tri_worst, 0, sizeof(unsigned), p->stream));
+  bool tri_all = true;            // every slab has level-0 odd blocks to factor
   const double w2 = p->omega * p->omega;
   const double sigma = p->opt.shift_c / p->omega;
   ls_status st = LS_OK;
@@ -2087,6 +2226,31 @@ ls_status slabs_build(ls_plan* p) {
       const double t3 = plan_clock_ms(p);
       if (p->opt.sweep == LS_SWEEP_DECOUPLED && (st = build_maps(p, s, s.fac, work, work_elems)) != LS_OK) break;
       const double t4 = plan_clock_ms(p);
+      if (s.levels.size() > 1 && n >= 2) {
+        // level-0 odd blocks' tridiagonal factors, each block's elimination
+        // checked against its dense inverse (FP64 factors for the check)
+        const int no = n / 2;
+        const size_t te = (size_t)3 * s.q * no;
+        const unsigned tb = (unsigned)(((size_t)no * s.q + 255) / 256);
+        cplx* t64 = work;
+        if (!p->fp32) {
+          if ((st = plan_alloc(p, (void**)&s.tri, te * sizeof(cplx))) != LS_OK) break;
+          t64 = s.tri;
+        }
+        k_tri_coef<cplx><<<tb, 256, 0, p->stream>>>(s.coef, t64, n, s.q);
+        if (s.q <= kPcrRows)
+          k_tri_check<<<no, 64, 0, p->stream>>>(t64, s.fac + s.levels[0].off_dinv, n, s.q, tri_worst);
+        else
+          tri_all = false;
+        if (p->fp32) {
+          if ((st = plan_alloc(p, (void**)&s.tri32, te * sizeof(fcplx))) != LS_OK) break;
+          k_tri_coef<fcplx><<<tb, 256, 0, p->stream>>>(s.coef, s.tri32, n, s.q);
+        }
+        if (hipGetLastError() != hipSuccess) { ls_set_error("tridiagonal factor launch failed"); st = LS_EDEVICE; break; }
+      } else {
+        tri_all = false;
+      }
+      p->stage_ms[4] += plan_clock_ms(p) - t4;
       p->stage_ms[3] += t1 - t0;
       p->stage_ms[4] += t2 - t1;
       p->stage_ms[5] += t3 - t2;
@@ -2107,12 +2271,21 @@ ls_status slabs_build(ls_plan* p) {
     }
   }
   int bad = 0;
+  unsigned worst_bits = 0;
   if (st == LS_OK) {
-    if (hipMemcpy(&bad, status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) st = LS_EDEVICE;
+    if (hipMemcpy(&bad, status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&worst_bits, tri_worst, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+      st = LS_EDEVICE;
   }
   (void)hipFree(work);
   if (fac64) (void)hipFree(fac64);
   (void)hipFree(status);
+  (void)hipFree(tri_worst);
+  {
+    float worst;
+    std::memcpy(&worst, &worst_bits, sizeof(worst));
+    p->tri_ok = tri_all && worst <= 1e-9f;
+  }
   if (st != LS_OK) return st;
   if (bad) {
     ls_set_error("slab factorisation: zero or non-finite pivot");
@@ -2146,8 +2319,6 @@ ls_status slabs_build(ls_plan* p) {
     const size_t Lmax = std::max(p->slabs[0].size(), p->slabs[1].size());
     p->set_qmax = qmax;
     LS_TRY(plan_alloc(p, &p->set_elim, Lmax * n * qmax * esz));
-    LS_TRY(plan_alloc(p, &p->set_save, Lmax * (size_t)(n / 2) * 4 * esz));
-    LS_TRY(plan_alloc(p, &p->set_inj, Lmax * (size_t)n * 4 * esz));
     LS_HIP(hipEventCreateWithFlags(&p->side_fork, hipEventDisableTiming));
     for (int k = 0; k < ls_plan::kSide; ++k) {
       LS_HIP(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
@@ -2250,8 +2421,12 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
     return LS_OK;
   }
   const SlabLevel& L0 = s.levels[0];
-  if (rows == ROWS_RANGE && S.save[0] && S.inj[0])
-    k_odd0_upd<C><<<dim3(((n / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, n, q);
+  // level-0 odd blocks by the tridiagonal elimination where the plan keeps
+  // its factors, else by their dense inverses
+  const bool tri = S.tri[0] != nullptr;
+  const dim3 tgrid(n / 2, cnt);
+  if (tri)
+    k_tri_odd0<C><<<tgrid, 64, 0, p->stream>>>(S, n, q);
   else
     step(k_rstep<C, R_ODD0>, ModeOdd0{}, L0.nl / 2, L0.off_dinv, 0, 0, L0.nl, 0);
   k_even0<C><<<dim3((((n + 1) / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
@@ -2271,7 +2446,11 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
     step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
   }
   k_odd0_lu<C><<<dim3(((n / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
-  if (rows == ROWS_SEL) {  // one tile of the selected rows per block
+  if (tri) {
+    if (rows == ROWS_SEL) k_tri_bwd0<C, ROWS_SEL><<<tgrid, 64, 0, p->stream>>>(S, n, q);
+    else if (rows == ROWS_RANGE) k_tri_bwd0<C, ROWS_RANGE><<<tgrid, 64, 0, p->stream>>>(S, n, q);
+    else k_tri_bwd0<C, ROWS_ALL><<<tgrid, 64, 0, p->stream>>>(S, n, q);
+  } else if (rows == ROWS_SEL) {  // one tile of the selected rows per block
     k_rstep<C, R_BWD0S><<<dim3(L0.nl / 2, cnt), 256, 0, p->stream>>>(S, L0.off_dinv, 0, 0, n, q, L0.nl, 0, 1);
   } else if (rows == ROWS_RANGE) {  // tiles over the longest range of the set
     int span = 1;
@@ -2287,9 +2466,10 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
 
 // One right-hand side of one slab.
 template <typename C>
-static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* cpl, const C* top,
-                            const C* g, C* t, C* y) {
+static ls_status solve_rows(ls_plan* p, const Slab& s, const C* fac, const C* coef, const C* cpl, const C* tri,
+                            const C* top, const C* g, C* t, C* y) {
   SlabSet<C> S{};
+  S.tri[0] = tri;
   S.g[0] = g;
   S.t[0] = t;
   S.y[0] = y;
@@ -2310,6 +2490,7 @@ struct SB<cplx> {
   static const cplx* fac(const Slab& s) { return s.fac; }
   static const cplx* coef(const Slab& s) { return s.coef; }
   static const cplx* cpl(const Slab& s) { return s.cpl; }
+  static const cplx* tri(const ls_plan* p, const Slab& s) { return p->tri_ok ? s.tri : nullptr; }
   static cplx* work(ls_plan* p, int k) { return k ? p->slab_work2 : p->slab_work; }
   static cplx* elim(ls_plan* p) { return p->slab_elim; }
   static const cplx* top(const Slab& s) { return s.top; }
@@ -2326,6 +2507,7 @@ struct SB<fcplx> {
   static const fcplx* fac(const Slab& s) { return s.fac32; }
   static const fcplx* coef(const Slab& s) { return s.coef32; }
   static const fcplx* cpl(const Slab& s) { return s.cpl32; }
+  static const fcplx* tri(const ls_plan* p, const Slab& s) { return p->tri_ok ? s.tri32 : nullptr; }
   static fcplx* work(ls_plan* p, int k) { return k ? p->slab_work32b : p->slab_work32; }
   static fcplx* elim(ls_plan* p) { return p->slab_elim32; }
   static const fcplx* top(const Slab& s) { return s.top32; }
@@ -2342,7 +2524,8 @@ struct SB<fcplx> {
 template <typename T>
 static ls_status solve_t(ls_plan* p, Slab& s, const T* g, T* y, int B) {
   if (B == 1)
-    return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), SB<T>::cpl(s), SB<T>::top(s), g, SB<T>::elim(p), y);
+    return solve_rows<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), SB<T>::cpl(s), SB<T>::tri(p, s), SB<T>::top(s), g,
+                         SB<T>::elim(p), y);
   LS_HIP(hipMemcpyAsync(y, g, (size_t)B * p->n * s.q * sizeof(T), hipMemcpyDeviceToDevice, p->stream));
   return solve_levels_b<T>(p, s, SB<T>::fac(s), SB<T>::coef(s), y, (size_t)p->n * s.q, B);
 }
@@ -2457,7 +2640,6 @@ static LayerSet<T> layer_set(ls_plan* p, std::vector<Slab>& S, int l0, int cnt, 
     ls.up[k] = inj_up(s);
     ls.tau[k] = (tau && l <= L - 2) ? tau + (size_t)(l + 1) * N2 : nullptr;
     ls.sig[k] = (sig && l >= 1) ? sig + (size_t)(l - 1) * N2 : nullptr;
-    ls.inj[k] = ((tau || sig) && p->set_inj) ? static_cast<T*>(p->set_inj) + (size_t)l * p->n * 4 : nullptr;
   }
   return ls;
 }
@@ -2489,11 +2671,7 @@ static ls_status solve_groups(ls_plan* p, int orient, bool chains) {
       for (int u = 0; u < 4; ++u) ss.sel[k][u] = (want[u] >= 0 && want[u] < s.q) ? want[u] : -1;
       ss.lo[k] = s.a - s.z0;
       ss.hi[k] = s.b - s.z0 + 1;
-      // the first solves keep the level-0 values of the chain rows, the
-      // second update the level-0 step from them and the trace sources
-      // (which enter exactly those rows: up pair a, a - 1; down pair b, b + 1)
-      ss.save[k] = static_cast<T*>(p->set_save) + (size_t)grp[k] * (p->n / 2) * 4;
-      ss.inj[k] = static_cast<const T*>(p->set_inj) + (size_t)grp[k] * p->n * 4;
+      ss.tri[k] = SB<T>::tri(p, s);
     }
     return solve_rows_set<T>(p, S[grp[0]], ss, (int)grp.size(), chains ? ROWS_SEL : ROWS_RANGE);
   };
@@ -2731,7 +2909,7 @@ ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x) {
     fcplx* yo = gi + cnt;
     fcplx* t = yo + cnt;
     k_down_copy<<<blocks, 256, 0, p->stream>>>(b, gi, cnt);
-    LS_TRY(solve_rows<fcplx>(p, s, s.fac32, s.coef32, s.cpl32, s.top32, gi, t, yo));
+    LS_TRY(solve_rows<fcplx>(p, s, s.fac32, s.coef32, s.cpl32, SB<fcplx>::tri(p, s), s.top32, gi, t, yo));
     k_up_copy<<<blocks, 256, 0, p->stream>>>(yo, x, cnt);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -2749,5 +2927,5 @@ ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x) {
     LS_HIP(hipMemcpyAsync(gi, b, cnt * sizeof(cplx), hipMemcpyDeviceToDevice, p->stream));
     g = gi;
   }
-  return solve_rows<cplx>(p, s, s.fac, s.coef, s.cpl, s.top, g, t, x);
+  return solve_rows<cplx>(p, s, s.fac, s.coef, s.cpl, SB<cplx>::tri(p, s), s.top, g, t, x);
 }
