@@ -58,30 +58,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def slab_solve_bytes(n, q):
+def slab_solve_bytes(n, q, tri=False):
     """Algorithmic bytes of one banded slab solve (c128): the band factors of
     a block-tridiagonal LU with bandwidth q+1 read once, n*q*(3q+4) entries,
-    plus reading and writing the right-hand side."""
-    return 16 * (n * q * (3 * q + 4) + 2 * n * q)
+    plus reading and writing the right-hand side.  With tri (the plan solves
+    the level-0 odd blocks as the tridiagonal systems they are), the n*q^2
+    entries of those blocks' dense inverses (n/2 blocks, read by the level-0
+    forward and backward steps) are replaced by their three diagonals read
+    by the same two steps (3nq entries)."""
+    per = 2 * q + 7 if tri else 3 * q + 4
+    return 16 * (n * q * per + 2 * n * q)
 
 
-def sweep_bytes(n, qs, spans):
+def sweep_bytes(n, qs, spans, tri=False):
     """Algorithmic bytes of one decoupled sweep (Alg. 1, FP64, one
     right-hand side) over layers of thicknesses qs and spans layer lines:
-    every layer's slab solved twice (slab_solve_bytes each), less what of the
-    level-0 odd blocks' inverses (n/2 blocks of q x q) the steps do not need:
-    the first solve's last step completes only the c chain rows (4, or 2 for
-    the first and last layer) the trace chains read, the second solve's last
-    step only the r = span layer lines the scatter reads, and the second
-    solve's first step takes the first one's level-0 values plus the inverse
-    times the trace sources, which enter the c chain rows (c columns read);
-    the trace-transfer maps read once ((L - 2) mT, (L - 1) mU and (L - 2) mV,
-    each (2n)^2 c128); g read and v written once."""
+    every layer's slab solved twice (slab_solve_bytes each); without tri,
+    less the rows of the level-0 odd blocks' inverses (n/2 blocks of q x q)
+    the last steps do not need (the first solve completes only the c chain
+    rows the trace chains read, 4, or 2 for the first and last layer, the
+    second the r = span layer lines the scatter reads); the trace-transfer
+    maps read once ((L - 2) mT, (L - 1) mU and (L - 2) mV, each (2n)^2
+    c128); g read and v written once."""
     L = len(qs)
     solves = 0
     for l, (q, r) in enumerate(zip(qs, spans)):
         c = 4 if 0 < l < L - 1 else 2
-        solves += 2 * slab_solve_bytes(n, q) - (n // 2) * ((q - c) + (q - r) + (q - c)) * q * 16
+        solves += 2 * slab_solve_bytes(n, q, tri)
+        if not tri:
+            solves -= (n // 2) * ((q - c) + (q - r)) * q * 16
     return solves + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
 
 
@@ -109,7 +114,7 @@ def time_sweeps(plan, n, reps):
         a, b, z0, z1 = plan.slab_info(0, l)
         qs.append(z1 - z0 + 1)
         spans.append(b - a + 1)
-    return ms, sweep_bytes(n, qs, spans), qs
+    return ms, sweep_bytes(n, qs, spans, plan.info()["tridiagonal_level0"] == 1), qs
 
 
 def apply_bytes(n, batch, cb=16, rb=8):
@@ -681,7 +686,7 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.slab_reps
         print(json.dumps({"mode": "slab", "q": q, "reps": args.slab_reps, "ms": dt * 1e3,
-                          "alg_bytes": slab_solve_bytes(n, q)}))
+                          "alg_bytes": slab_solve_bytes(n, q, plan.info()["tridiagonal_level0"] == 1)}))
         plan.close()
         return
     uI = torch.from_numpy(cfg["uI"]).to(dev)
@@ -753,7 +758,7 @@ def main():
     ev1.record(pseq.stream)
     ev1.synchronize()
     slab_ms = ev0.elapsed_time(ev1) / args.slab_reps
-    slab_alg = slab_solve_bytes(n, q)
+    slab_alg = slab_solve_bytes(n, q, pseq.info()["tridiagonal_level0"] == 1)
     slab_gbs = slab_alg / (slab_ms * 1e-3) / 1e9
     log(f"slab solve q={q} (sequential plan): {slab_ms*1e3:.1f} us, {slab_gbs:.0f} GB/s algorithmic")
     pseq.close()
