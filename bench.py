@@ -43,12 +43,12 @@ HBM_PEAK_GBS = 8000.0
 # profiles/ named for the slab solve holds the figures and their command.
 # It is a counter figure from a profiling run, not a measurement of this
 # run: None when the kernels have changed since the counters were taken.
-SLAB_TRAFFIC_BYTES = 445.09e6
+SLAB_TRAFFIC_BYTES = 333.78e6
 SLAB_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode slab` (5 interior slab solves), "
                        "scaled by the counters of a 1 GiB device copy; see the slab-solve profile")
 # The same for one decoupled sweep (the dominant unit of the plain solve),
 # from `bench.py --mode sweep`; see the sweep profile.
-SWEEP_TRAFFIC_BYTES = 14.56e9
+SWEEP_TRAFFIC_BYTES = 12.80e9
 SWEEP_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sweep`, summed over the sweep "
                         "kernels and divided by the sweeps run, scaled by the counters of a 1 GiB device copy; "
                         "see the sweep profile")
