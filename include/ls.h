@@ -84,6 +84,7 @@ typedef struct {
   int autotune;          /* 1: time the FFT column-pass tile variants at plan creation */
   int fft_variant;       /* autotune 0: FFT column-pass variant to use, 0..7 (0: radix-16 register passes) */
   int sweep;             /* LS_SWEEP_SEQUENTIAL or LS_SWEEP_DECOUPLED (how Alg. 1 runs, one right-hand side) */
+  int level0;            /* LS_LEVEL0_AUTO or LS_LEVEL0_DENSE (the one-right-hand-side slab solves' level-0 odd blocks) */
 } ls_options;
 
 /* How one application of Alg. 1 (Section 3.4) runs for one right-hand side
@@ -103,6 +104,17 @@ typedef struct {
  *   the sequential sweep. */
 enum { LS_SWEEP_SEQUENTIAL = 0, LS_SWEEP_DECOUPLED = 1 };
 
+/* The level-0 odd blocks of a slab's block cyclic reduction (Section 3.2's
+ * local matrices, built from Section 2's 9-point stencils) are tridiagonal:
+ * a point of a grid column couples only to its two vertical neighbours in
+ * that column.  LS_LEVEL0_AUTO: the one-right-hand-side solves take those
+ * blocks' steps as tridiagonal solves (3q numbers per block read instead of
+ * the q^2 of the dense inverse) when every block's solve agrees with its
+ * dense inverse at plan creation (relative difference <= 1e-9), else by the
+ * dense inverses; LS_LEVEL0_DENSE: always by the dense inverses.
+ * ls_plan_info reports which the plan uses. */
+enum { LS_LEVEL0_AUTO = 0, LS_LEVEL0_DENSE = 1 };
+
 typedef struct {
   int outer_its;          /* outer flexible-GMRES iterations */
   int inner_its_total;    /* inner GMRES iterations summed over all outer iterations */
@@ -116,7 +128,7 @@ typedef struct {
 /* Defaults: slabs 0 (n/64), ext 10, inner_tol 1e-3, max_outer 100,
  * max_inner 50, shift_c 0, LS_FP64, LS_PREC_BD, inner_fixed_iters 0,
  * max_batch 1, lowp_tol 1e-5, max_refine 10, use_graphs 1, autotune 1,
- * fft_variant 0, sweep LS_SWEEP_SEQUENTIAL.
+ * fft_variant 0, sweep LS_SWEEP_SEQUENTIAL, level0 LS_LEVEL0_AUTO.
  * Never fails. */
 void ls_options_default(ls_options* opt);
 

@@ -21,11 +21,13 @@ from .build import lib_path
 __all__ = [
     "Options", "SolveInfo", "LSError", "Plan", "lib", "solve_multi",
     "LS_PREC_BD", "LS_PREC_PT1", "LS_PREC_NONE", "LS_FP64", "LS_FP32_REFINE",
+    "LS_SWEEP_SEQUENTIAL", "LS_SWEEP_DECOUPLED", "LS_LEVEL0_AUTO", "LS_LEVEL0_DENSE",
 ]
 
 LS_PREC_BD, LS_PREC_PT1, LS_PREC_NONE = 0, 1, 2
 LS_FP64, LS_FP32_REFINE = 0, 1
 LS_SWEEP_SEQUENTIAL, LS_SWEEP_DECOUPLED = 0, 1
+LS_LEVEL0_AUTO, LS_LEVEL0_DENSE = 0, 1
 _STATUS = {0: "LS_OK", 1: "LS_EINVAL", 2: "LS_ENOMEM", 3: "LS_EDEVICE", 4: "LS_ENOCONV",
            5: "LS_ESINGULAR", 6: "LS_EUNSUPPORTED"}
 
@@ -44,7 +46,7 @@ class Options(ctypes.Structure):
         ("inner_fixed_iters", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("lowp_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
         ("use_graphs", ctypes.c_int), ("autotune", ctypes.c_int), ("fft_variant", ctypes.c_int),
-        ("sweep", ctypes.c_int),
+        ("sweep", ctypes.c_int), ("level0", ctypes.c_int),
     ]
 
 

@@ -298,6 +298,7 @@ bool valid_opts(const ls_options& o) {
   if (o.use_graphs < 0 || o.use_graphs > 1 || o.autotune < 0 || o.autotune > 1) return false;
   if (o.fft_variant < 0 || o.fft_variant >= kFftVariants) return false;
   if (o.sweep != LS_SWEEP_SEQUENTIAL && o.sweep != LS_SWEEP_DECOUPLED) return false;
+  if (o.level0 != LS_LEVEL0_AUTO && o.level0 != LS_LEVEL0_DENSE) return false;
   return o.ext >= 0 && o.inner_tol > 0 && o.max_outer >= 1 && o.max_inner >= 1 &&
          (o.precision == LS_FP64 || o.precision == LS_FP32_REFINE) && o.precond >= LS_PREC_BD &&
          o.precond <= LS_PREC_NONE && o.inner_fixed_iters >= 0 && o.max_batch >= 1 &&
@@ -484,6 +485,7 @@ void ls_options_default(ls_options* o) {
   o->autotune = 1;
   o->fft_variant = 0;
   o->sweep = LS_SWEEP_SEQUENTIAL;
+  o->level0 = LS_LEVEL0_AUTO;
 }
 
 const char* ls_status_str(ls_status s) {

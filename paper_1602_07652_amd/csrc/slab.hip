@@ -2284,7 +2284,7 @@ ls_status slabs_build(ls_plan* p) {
   {
     float worst;
     std::memcpy(&worst, &worst_bits, sizeof(worst));
-    p->tri_ok = tri_all && worst <= 1e-9f;
+    p->tri_ok = p->opt.level0 == LS_LEVEL0_AUTO && tri_all && worst <= 1e-9f;
   }
   if (st != LS_OK) return st;
   if (bad) {

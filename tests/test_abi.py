@@ -43,6 +43,7 @@ def test_defaults_follow_the_paper():
     assert o.inner_tol == gold["inner_tol"]["value"]
     assert o.ext == gold["extension_points"]["value"]
     assert o.precond == 0 and o.max_batch == 1 and o.inner_fixed_iters == 0
+    assert o.sweep == 0 and o.level0 == 0
 
 
 def test_status_strings_and_null_arguments():

@@ -113,9 +113,11 @@ def oracle_problem(n, f, L, ext, shift, seed):
 
 
 @pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES)
-def test_slab_solves(n, f, L, ext, shift, seed):
+@pytest.mark.parametrize("level0", [0, 1])
+def test_slab_solves(n, f, L, ext, shift, seed, level0):
     m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
-    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift)
+    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift, level0=level0)
+    assert p.info()["tridiagonal_level0"] == 1 - level0
     parts = slabs.layer_partition(n, L, ext)
     for orient in (0, 1):
         a_, b_ = (al, be) if orient == 0 else (al.transpose(1, 0, 3, 2), be.transpose(1, 0, 3, 2))
@@ -151,8 +153,9 @@ def test_sweeps_and_bidirectional(n, f, L, ext, shift, seed):
     p.close()
 
 
+@pytest.mark.parametrize("level0", [0, 1])
 @pytest.mark.parametrize("n,f,L,ext,shift,seed", SLAB_CASES + [(80, 8.0, 2, 8, 0.0, 7), (200, 20.0, 20, 4, 0.0, 5)])
-def test_decoupled_sweep_matches_oracle(n, f, L, ext, shift, seed):
+def test_decoupled_sweep_matches_oracle(n, f, L, ext, shift, seed, level0):
     """Alg. 1 with the layers decoupled by trace-transfer maps (independent
     local solves, two chains of dense products for the traces, independent
     solves again) is the same linear operator as the sequential sweep: both
@@ -161,10 +164,13 @@ def test_decoupled_sweep_matches_oracle(n, f, L, ext, shift, seed):
     one group per layer (n = 130), two groups of two (n = 64), two layers
     only (n = 80: no chain step beyond the first, no upward chain), and at
     n = 200, L = 20 more like slabs than one launch takes (groups of 16, 2
-    and 2; the per-layer launches in chunks of 16 and 4)."""
+    and 2; the per-layer launches in chunks of 16 and 4).  level0 0: the
+    level-0 odd blocks as tridiagonal systems (the plan must have kept them),
+    1: by their dense inverses."""
     from paper_1602_07652_amd import LS_SWEEP_DECOUPLED
     m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
-    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift, sweep=LS_SWEEP_DECOUPLED)
+    p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift, sweep=LS_SWEEP_DECOUPLED, level0=level0)
+    assert p.info()["tridiagonal_level0"] == 1 - level0
     bd = slabs.BiDirectional(al, be, m, omega, L, ext, shift)
     g = li.random_complex((n, n), 13)
     e0 = rel(host(p.sweep(0, dev(g))), bd.prec_h(g))
