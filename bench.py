@@ -58,36 +58,62 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def slab_solve_bytes(n, q, tri=False):
-    """Algorithmic bytes of one banded slab solve (c128): the band factors of
-    a block-tridiagonal LU with bandwidth q+1 read once, n*q*(3q+4) entries,
-    plus reading and writing the right-hand side.  With tri (the plan solves
-    the level-0 odd blocks as the tridiagonal systems they are), the n*q^2
-    entries of those blocks' dense inverses (n/2 blocks, read by the level-0
-    forward and backward steps) are replaced by their three diagonals read
-    by the same two steps (3nq entries)."""
-    per = 2 * q + 7 if tri else 3 * q + 4
-    return 16 * (n * q * per + 2 * n * q)
+def slab_solve_bytes(n, q, top_blocks=16, tri=True, l1=False):
+    """Algorithmic bytes of one slab solve (c128, one right-hand side) by
+    the block cyclic reduction as built: the factor entries its steps read,
+    level by level, plus g read and y written (2nq).  Levels: n blocks at
+    level 0, (nl + 1) / 2 at the next, up to the first level with at most
+    top_blocks blocks, whose reduced system (Nt = nl q unknowns) is one dense
+    Nt x Nt operator.  Level 0: the odd blocks' solves, forward and backward,
+    read 3q entries each (tri: the three diagonals) or q^2 (the dense
+    inverse), and the six couplings per row of every block (6nq).  Level l
+    >= 1: the forward step reads two q x q matrices per even block, the
+    backward step three per odd block; with l1 (level 1's couplings applied
+    through the tridiagonal level-0 blocks) level 1 reads one q x q inverse
+    per odd block forward and backward, and per block and side 9q entries of
+    level-0 diagonals and couplings."""
+    nls = [n]
+    while nls[-1] > 1:
+        nls.append((nls[-1] + 1) // 2)
+    T = len(nls) - 1
+    for l in range(1, len(nls)):
+        if top_blocks and nls[l] <= top_blocks:
+            T = l
+            break
+    e = 2 * (n // 2) * (3 * q if tri else q * q) + 6 * n * q
+    for l in range(1, T):
+        no, ne = nls[l] // 2, (nls[l] + 1) // 2
+        if l == 1 and l1:
+            e += 2 * no * q * q + (ne + no) * 2 * 9 * q
+        else:
+            e += ne * 2 * q * q + no * 3 * q * q
+    e += (nls[T] * q) ** 2
+    return 16 * (e + 2 * n * q)
 
 
-def sweep_bytes(n, qs, spans, tri=False):
+def sweep_bytes(n, qs, spans, top_blocks=8, tri=True, l1=True):
     """Algorithmic bytes of one decoupled sweep (Alg. 1, FP64, one
     right-hand side) over layers of thicknesses qs and spans layer lines:
-    every layer's slab solved twice (slab_solve_bytes each); without tri,
-    less the rows of the level-0 odd blocks' inverses (n/2 blocks of q x q)
-    the last steps do not need (the first solve completes only the c chain
-    rows the trace chains read, 4, or 2 for the first and last layer, the
-    second the r = span layer lines the scatter reads); the trace-transfer
-    maps read once ((L - 2) mT, (L - 1) mU and (L - 2) mV, each (2n)^2
-    c128); g read and v written once."""
+    every layer's slab solved twice (slab_solve_bytes each; with the dense
+    level-0 inverses, less the rows of them the last steps do not need: the
+    first solve completes only the c chain rows the trace chains read, 4, or
+    2 for the first and last layer, the second the r = span layer lines the
+    scatter reads); the trace-transfer maps read once ((L - 2) mT, (L - 1) mU
+    and (L - 2) mV, each (2n)^2 c128); g read and v written once."""
     L = len(qs)
     solves = 0
     for l, (q, r) in enumerate(zip(qs, spans)):
         c = 4 if 0 < l < L - 1 else 2
-        solves += 2 * slab_solve_bytes(n, q, tri)
+        solves += 2 * slab_solve_bytes(n, q, top_blocks, tri, l1)
         if not tri:
             solves -= (n // 2) * ((q - c) + (q - r)) * q * 16
     return solves + (3 * L - 5) * (2 * n) ** 2 * 16 + 2 * n * n * 16
+
+
+def plan_models(plan):
+    """(top_blocks, tri) of a plan, for the byte models."""
+    info = plan.info()
+    return info["top_blocks"], info["tridiagonal_level0"] == 1
 
 
 def time_sweeps(plan, n, reps):
@@ -114,7 +140,10 @@ def time_sweeps(plan, n, reps):
         a, b, z0, z1 = plan.slab_info(0, l)
         qs.append(z1 - z0 + 1)
         spans.append(b - a + 1)
-    return ms, sweep_bytes(n, qs, spans, plan.info()["tridiagonal_level0"] == 1), qs
+    top_blocks, tri = plan_models(plan)
+    # the sweep's groups of like slabs (14 and 2 at the bench shape) take the
+    # level-1 path where the level-0 blocks are tridiagonal systems
+    return ms, sweep_bytes(n, qs, spans, top_blocks, tri, tri), qs
 
 
 def apply_bytes(n, batch, cb=16, rb=8):
@@ -686,7 +715,7 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.slab_reps
         print(json.dumps({"mode": "slab", "q": q, "reps": args.slab_reps, "ms": dt * 1e3,
-                          "alg_bytes": slab_solve_bytes(n, q, plan.info()["tridiagonal_level0"] == 1)}))
+                          "alg_bytes": slab_solve_bytes(n, q, *plan_models(plan))}))
         plan.close()
         return
     uI = torch.from_numpy(cfg["uI"]).to(dev)
@@ -758,7 +787,7 @@ def main():
     ev1.record(pseq.stream)
     ev1.synchronize()
     slab_ms = ev0.elapsed_time(ev1) / args.slab_reps
-    slab_alg = slab_solve_bytes(n, q, pseq.info()["tridiagonal_level0"] == 1)
+    slab_alg = slab_solve_bytes(n, q, *plan_models(pseq))
     slab_gbs = slab_alg / (slab_ms * 1e-3) / 1e9
     log(f"slab solve q={q} (sequential plan): {slab_ms*1e3:.1f} us, {slab_gbs:.0f} GB/s algorithmic")
     pseq.close()

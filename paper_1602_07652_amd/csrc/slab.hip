@@ -259,7 +259,7 @@ __device__ __forceinline__ int bstep_remap(int id, int total) {
 // elements (at most RCols::N) into registers before anything else, so a
 // level costs about one memory round trip however deep it is; the inputs
 // x_t are staged in LDS meanwhile and the G partial sums added in LDS.
-enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4, R_BWD0S = 5, R_BWD0R = 6 };
+enum { R_ODD0 = 0, R_FWD = 1, R_LAST = 2, R_BWD = 3, R_BWD0 = 4, R_BWD0S = 5, R_BWD0R = 6, R_ODDL = 7 };
 // factor columns a thread preloads: one, two or three matrices per step
 template <int MODE>
 struct RCols {
@@ -289,6 +289,7 @@ inline int row_splits(int q, int t, int ncol) { return row_splits(q, q, t, ncol)
 //           row tile per block): the other rows of the odd blocks keep the
 //           level-0 forward values
 //   R_BWD0R as R_BWD0 for the rows [S.lo[slab], S.hi[slab]) only (RS tiles)
+//   R_ODDL  level l, k odd:  y_k = Dinv_k t_k
 // Slabs of one launch: the one-right-hand-side steps run the same level
 // step (same q and level structure: the factor blocks of a level at the
 // same offsets) for up to kSet slabs at once, blockIdx.y (k_rstep, k_top)
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
   const C* M0 = nullptr;
   const C* M1 = nullptr;
   const C* M2 = nullptr;
-  if (MODE == R_ODD0 || MODE == R_BWD0 || MODE == R_BWD0S || MODE == R_BWD0R) {
+  if (MODE == R_ODD0 || MODE == R_BWD0 || MODE == R_BWD0S || MODE == R_BWD0R || MODE == R_ODDL) {
     k = 2 * blk + 1;
     M0 = m0 + blk * qq;
   } else if (MODE == R_FWD) {
@@ -391,6 +392,8 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
     } else if (MODE == R_BWD) {
       if (tt == 0) v = t[((size_t)k << shift) * q + c];
       else v = tneg(y[((size_t)(tt == 1 ? k - 1 : k + 1) << shift) * q + c]);
+    } else if (MODE == R_ODDL) {
+      v = t[((size_t)k << shift) * q + c];
     } else {  // R_BWD0: L_k y_{k-1} + U_k y_{k+1}, formed by k_odd0_lu in t's odd rows
       v = t[(size_t)k * q + c];
     }
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
     if (MODE == R_ODD0) y[(size_t)k * q + r] = sum;
     else if (MODE == R_FWD) { C* o = t + ((size_t)k << shift) * q + r; *o = tsub(*o, sum); }
     else if (MODE == R_LAST) y[r] = sum;
-    else if (MODE == R_BWD) y[((size_t)k << shift) * q + r] = sum;
+    else if (MODE == R_BWD || MODE == R_ODDL) y[((size_t)k << shift) * q + r] = sum;
     else { C* o = y + (size_t)k * q + r; *o = tsub(*o, sum); }
   }
 }
@@ -531,6 +534,80 @@ __global__ __launch_bounds__(64) void k_tri_bwd0(SlabSet<C> S, int n, int q) {
     if (ROWS == 1) keep = keep && (r == s0 || r == s1 || r == s2 || r == s3);
     if (ROWS == 2) keep = keep && r >= lo && r < hi;
     if (keep) y[r] = tsub(y[r], d[u]);
+  }
+}
+
+// Level 1 through the tridiagonal level-0 blocks.  Eliminating the odd
+// level-0 blocks couples level-0 block k to k - 2 by L'_k = -L_k D_{k-1}^{-1}
+// L_{k-1} and to k + 2 by U'_k = -U_k D_{k+1}^{-1} U_{k+1}, products of
+// tridiagonal blocks and the inverse of a tridiagonal one: they are applied
+// as two tridiagonal products around a tridiagonal solve instead of being
+// stored dense.  The level-1 forward step t_k -= L'_k z_{k-2} + U'_k z_{k+2}
+// (z = D'^{-1} t at the odd level-1 blocks, left in y by R_ODDL) and the
+// backward step's right-hand side t_k - L'_k y_{k-2} - U'_k y_{k+2} are both
+// t_k += L_k D_{k-1}^{-1} L_{k-1} y_{k-2} + U_k D_{k+1}^{-1} U_{k+1} y_{k+2}
+// on the level-0 blocks k = k0, k0 + 4, ... (k0 = 0: the even level-1
+// blocks, 2: the odd ones).  One wave per block k, blockIdx.y the slab.
+template <typename C>
+__global__ __launch_bounds__(64) void k_l1_couple(SlabSet<C> S, int n, int q, int k0) {
+  __shared__ C sh[4 * kPcrRows];
+  __shared__ C sv[kPcrRows];
+  const int z = blockIdx.y, lane = threadIdx.x, k = k0 + 4 * blockIdx.x;
+  if (k >= n) return;  // the whole workgroup
+  const C* __restrict__ y = S.y[z];
+  const C* __restrict__ cpl = S.cpl[z];
+  C acc[2] = {tmk<C>(0, 0), tmk<C>(0, 0)};
+  for (int side = 0; side < 2; ++side) {
+    const int km = side ? k + 1 : k - 1, ks = side ? k + 2 : k - 2;
+    if (ks < 0 || ks >= n) continue;  // uniform
+    // w = (km's coupling towards ks) y_ks
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      if (r < q) sv[r] = y[(size_t)ks * q + r];
+    }
+    __syncthreads();
+    C d[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      C w = tmk<C>(0, 0);
+      if (r < q) {
+        const C* cp = cpl + (size_t)km * 6 * q + side * q + r;
+        for (int dZ = -1; dZ <= 1; ++dZ) {
+          const int rr = r + dZ;
+          if (rr >= 0 && rr < q) w = tfma(cp[(size_t)(2 * (dZ + 1)) * q], sv[rr], w);
+        }
+      }
+      d[u] = w;
+    }
+    // x = D_km^{-1} w (km odd)
+    pcr_wave<C>(S.tri[z] + (size_t)((km - 1) / 2) * 3 * q, d, q, sh);
+    // acc += (k's coupling towards km) x (every lane done reading sv first)
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      if (r < q) sv[r] = d[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      if (r >= q) continue;
+      const C* cp = cpl + (size_t)k * 6 * q + side * q + r;
+      for (int dZ = -1; dZ <= 1; ++dZ) {
+        const int rr = r + dZ;
+        if (rr >= 0 && rr < q) acc[u] = tfma(cp[(size_t)(2 * (dZ + 1)) * q], sv[rr], acc[u]);
+      }
+    }
+    __syncthreads();
+  }
+  C* __restrict__ t = S.t[z] + (size_t)k * q;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int r = lane + 64 * u;
+    if (r < q) t[r] = tadd(t[r], acc[u]);
   }
 }
 
@@ -2432,9 +2509,20 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
   k_even0<C><<<dim3((((n + 1) / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
   // levels from `top` up: one dense operator when the plan built it
   const int top_l = (s.top_level >= 1 && S.top[0]) ? s.top_level : nlev - 1;
+  // level 1 with its couplings through the tridiagonal level-0 blocks (only
+  // D'^{-1} of its odd blocks read) when it is a level of its own and the
+  // launch takes several slabs (for one slab its coupling waves, n/4, are
+  // too few to hide their latency: the dense steps are faster there)
+  const bool l1 = tri && top_l >= 2 && cnt >= 2;
+  using ModeOddL = std::integral_constant<int, R_ODDL>;
   for (int l = 1; l < top_l; ++l) {
     const SlabLevel& L = s.levels[l];
-    step(k_rstep<C, R_FWD>, ModeFwd{}, (L.nl + 1) / 2, L.off_pm, L.off_pp, 0, L.nl, l);
+    if (l == 1 && l1) {
+      step(k_rstep<C, R_ODDL>, ModeOddL{}, L.nl / 2, L.off_dinv, 0, 0, L.nl, 1);
+      k_l1_couple<C><<<dim3((L.nl + 1) / 2, cnt), 64, 0, p->stream>>>(S, n, q, 0);
+    } else {
+      step(k_rstep<C, R_FWD>, ModeFwd{}, (L.nl + 1) / 2, L.off_pm, L.off_pp, 0, L.nl, l);
+    }
   }
   if (top_l < nlev - 1) {
     k_top<C><<<dim3((s.top_n + 3) / 4, cnt), 256, 0, p->stream>>>(S, s.top_n, q, top_l);
@@ -2443,7 +2531,12 @@ static ls_status solve_rows_set(ls_plan* p, const Slab& s, const SlabSet<C>& S, 
   }
   for (int l = top_l - 1; l >= 1; --l) {
     const SlabLevel& L = s.levels[l];
-    step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
+    if (l == 1 && l1) {
+      k_l1_couple<C><<<dim3(L.nl / 2, cnt), 64, 0, p->stream>>>(S, n, q, 2);
+      step(k_rstep<C, R_ODDL>, ModeOddL{}, L.nl / 2, L.off_dinv, 0, 0, L.nl, 1);
+    } else {
+      step(k_rstep<C, R_BWD>, ModeBwd{}, L.nl / 2, L.off_dinv, L.off_dinvl, L.off_dinvu, L.nl, l);
+    }
   }
   k_odd0_lu<C><<<dim3(((n / 2) * q + 255) / 256, cnt), 256, 0, p->stream>>>(S, n, q);
   if (tri) {
