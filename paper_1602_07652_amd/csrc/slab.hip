@@ -432,11 +432,34 @@ __global__ __launch_bounds__(256, 4) void k_rstep(SlabSet<C> S, size_t o0, size_
 // dense steps when one disagrees.  blockIdx.x the block, blockIdx.y the slab.
 constexpr int kPcrRows = 128;
 
+// 1 / x from the hardware reciprocal estimate refined by Newton-Raphson
+// steps r <- r + r (1 - x r) (two in FP64, one in FP32: each doubles the
+// correct bits), about one ulp, in place of a full IEEE division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.f), r);
+}
+template <typename C>
+__device__ __forceinline__ C trcp(C b) {  // 1 / b = conj(b) / |b|^2
+  const auto r = rcp_nr(fma(b.x, b.x, b.y * b.y));
+  C o;
+  o.x = b.x * r;
+  o.y = -b.y * r;
+  return o;
+}
+
+// Every row publishes the reciprocal of its own diagonal entry once per
+// step, so the rows s above and below it multiply instead of dividing.
 template <typename C>
 __device__ __forceinline__ void pcr_wave(const C* __restrict__ abc, C (&d)[2], int q, C* __restrict__ sh) {
   const int lane = threadIdx.x;
   C* sa = sh;
-  C* sb = sh + kPcrRows;
+  C* sr = sh + kPcrRows;
   C* sc = sh + 2 * kPcrRows;
   C* sd = sh + 3 * kPcrRows;
   C a[2], b[2], c[2];
@@ -455,7 +478,7 @@ __device__ __forceinline__ void pcr_wave(const C* __restrict__ abc, C (&d)[2], i
       const int i = lane + 64 * u;
       if (i < q) {
         sa[i] = a[u];
-        sb[i] = b[u];
+        sr[i] = trcp(b[u]);
         sc[i] = c[u];
         sd[i] = d[u];
       }
@@ -467,17 +490,13 @@ __device__ __forceinline__ void pcr_wave(const C* __restrict__ abc, C (&d)[2], i
       if (i >= q) continue;
       C na = tmk<C>(0, 0), nc = tmk<C>(0, 0), nb = b[u], nd = d[u];
       if (i - s >= 0) {  // alpha = -a_i / b_{i-s}
-        const C bm = sb[i - s];
-        const auto r = 1.0 / ((double)bm.x * bm.x + (double)bm.y * bm.y);
-        const C al = tmk<C>(-(a[u].x * bm.x + a[u].y * bm.y) * r, -(a[u].y * bm.x - a[u].x * bm.y) * r);
+        const C al = tneg(tmul(a[u], sr[i - s]));
         na = tmul(al, sa[i - s]);
         nb = tfma(al, sc[i - s], nb);
         nd = tfma(al, sd[i - s], nd);
       }
       if (i + s < q) {  // gamma = -c_i / b_{i+s}
-        const C bp = sb[i + s];
-        const auto r = 1.0 / ((double)bp.x * bp.x + (double)bp.y * bp.y);
-        const C ga = tmk<C>(-(c[u].x * bp.x + c[u].y * bp.y) * r, -(c[u].y * bp.x - c[u].x * bp.y) * r);
+        const C ga = tneg(tmul(c[u], sr[i + s]));
         nc = tmul(ga, sc[i + s]);
         nb = tfma(ga, sa[i + s], nb);
         nd = tfma(ga, sd[i + s], nd);
@@ -490,10 +509,7 @@ __device__ __forceinline__ void pcr_wave(const C* __restrict__ abc, C (&d)[2], i
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const auto r = 1.0 / ((double)b[u].x * b[u].x + (double)b[u].y * b[u].y);
-    d[u] = tmk<C>((d[u].x * b[u].x + d[u].y * b[u].y) * r, (d[u].y * b[u].x - d[u].x * b[u].y) * r);
-  }
+  for (int u = 0; u < 2; ++u) d[u] = tmul(d[u], trcp(b[u]));
 }
 
 // y_k = D_k^{-1} g_k (the level-0 odd step).
