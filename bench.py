@@ -48,7 +48,7 @@ SLAB_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sl
                        "scaled by the counters of a 1 GiB device copy; see the slab-solve profile")
 # The same for one decoupled sweep (the dominant unit of the plain solve),
 # from `bench.py --mode sweep`; see the sweep profile.
-SWEEP_TRAFFIC_BYTES = 12.80e9
+SWEEP_TRAFFIC_BYTES = 10.58e9
 SWEEP_TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of `bench.py --mode sweep`, summed over the sweep "
                         "kernels and divided by the sweeps run, scaled by the counters of a 1 GiB device copy; "
                         "see the sweep profile")
