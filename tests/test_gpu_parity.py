@@ -181,16 +181,23 @@ def test_decoupled_sweep_matches_oracle(n, f, L, ext, shift, seed, level0):
     p.close()
 
 
-def test_decoupled_sweep_fp32_plan():
+@pytest.mark.parametrize("level0", [0, 1])
+@pytest.mark.parametrize("n,f,L,ext,shift,seed", [SLAB_CASES[1], (200, 20.0, 20, 4, 0.0, 5)])
+def test_decoupled_sweep_fp32_plan(n, f, L, ext, shift, seed, level0):
+    """The decoupled Alg. 2 of an FP32 plan against the FP64 oracle: at n =
+    100, L = 3 the two boundary layers share a launch, at n = 200, L = 20
+    the interior groups take 16 and 2 slabs, so level 1 runs through the
+    tridiagonal level-0 blocks in FP32 (level0 0) or as dense products
+    (level0 1)."""
     from paper_1602_07652_amd import LS_SWEEP_DECOUPLED, LS_FP32_REFINE
-    n, f, L, ext, shift, seed = SLAB_CASES[1]
     m, omega, al, be = oracle_problem(n, f, L, ext, shift, seed)
     p, _ = make_plan(n, f, m, slabs=L, ext=ext, shift_c=shift, sweep=LS_SWEEP_DECOUPLED,
-                     precision=LS_FP32_REFINE)
+                     precision=LS_FP32_REFINE, level0=level0)
+    assert p.info()["tridiagonal_level0"] == 1 - level0
     bd = slabs.BiDirectional(al, be, m, omega, L, ext, shift)
     g = li.random_complex((n, n), 14)
     e = rel(host(p.bidirectional(dev(g))), bd.apply(g))
-    banner(f"decoupled sweeps FP32 n={n}: BD {e:.3e}")
+    banner(f"decoupled sweeps FP32 n={n} L={L} level0={level0}: BD {e:.3e}")
     assert e < 5e-5
     p.close()
 
