@@ -47,7 +47,7 @@ typedef enum {
   LS_EDEVICE = 3,     /* a HIP call failed */
   LS_ENOCONV = 4,     /* GMRES hit its iteration limit; outputs hold the last iterate */
   LS_ESINGULAR = 5,   /* a zero or non-finite pivot in a slab factorisation */
-  LS_EUNSUPPORTED = 6 /* valid request outside what this build implements */
+  LS_EUNSUPPORTED = 6 /* valid request outside what the library implements */
 } ls_status;
 
 /* Arithmetic of the on-line stage.
