@@ -438,3 +438,33 @@ def test_apply_properties_at_bench_shape(bench_shape):
     banner(f"bench-shape H: linearity {e_lin:.2e}, D H symmetry {e_sym:.2e}, rhs identity {e_rhs:.2e}, "
            f"direct-sum samples {worst:.2e}")
     assert e_lin < 1e-14 and e_sym < 1e-12 and e_rhs < 1e-14 and worst < 1e-13
+
+
+def test_batch8_apply_at_bench_shape(bench_shape):
+    """ls_apply on 8 right-hand sides at 1024^2, the batch the benchmark
+    times (run in chunks whose intermediates stay cache-resident): every
+    right-hand side equals its own one-right-hand-side apply bit for bit,
+    twice in a row (the chunks' work areas and streams are reused), and
+    sampled outputs of two of them match the O(N) direct sum of the oracle's
+    kernel samples."""
+    n, omega, m, al, be, p = bench_shape
+    B = 8
+    v = li.random_complex((B, n, n), 71)
+    vd = dev(v)
+    y1 = host(p.apply(vd))
+    y2 = host(p.apply(vd))
+    assert np.array_equal(y1, y2)
+    for k in range(B):
+        yk = host(p.apply(dev(v[k:k + 1])))[0]
+        assert np.array_equal(yk, y1[k]), f"right-hand side {k} differs from its single apply"
+    W = kernel.kernel_samples(n, 1.0 / n, omega)
+    rng = np.random.default_rng(72)
+    worst = 0.0
+    for k in (0, B - 1):
+        mv = m * v[k]
+        for j, i in rng.integers(0, n, size=(8, 2)):
+            Wk = W[n - 1 + j - np.arange(n)[:, None], n - 1 + i - np.arange(n)[None, :]]
+            direct = v[k, j, i] + omega**2 * np.sum(Wk * mv)
+            worst = max(worst, abs(y1[k, j, i] - direct) / np.max(np.abs(y1[k])))
+    banner(f"batch-8 apply at 1024^2: equal to single applies, direct-sum samples {worst:.2e}")
+    assert worst < 1e-13
