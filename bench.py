@@ -755,6 +755,7 @@ def main():
     ev1.record(stream)
     ev1.synchronize()
     apply_ms = ev0.elapsed_time(ev1) / reps
+    apply_variant = plan.info()["fft_variant64"]
     apply_gbs = apply_bytes(n, B) / (apply_ms * 1e-3) / 1e9
     apply_io_gbs = apply_io_bytes(n, B) / (apply_ms * 1e-3) / 1e9
     log(f"ls_apply batch {B}: {apply_ms:.3f} ms, {apply_gbs:.0f} GB/s algorithmic "
@@ -819,6 +820,7 @@ def main():
     ev1.record(p32.stream)
     ev1.synchronize()
     apply32_ms = ev0.elapsed_time(ev1) / reps
+    apply32_variant = p32.info()["fft_variant32"]
     apply32_gbs = apply_bytes(n, B, 8, 4) / (apply32_ms * 1e-3) / 1e9
     log(f"ls_apply_c64 batch {B}: {apply32_ms:.3f} ms, {apply32_gbs:.0f} GB/s algorithmic")
     p32.close()
@@ -874,6 +876,7 @@ def main():
             "fft_matvec_io_GBs": apply_io_gbs,
             "fft_matvec_fp32_GBs": apply32_gbs,
             "fft_matvec_fp32_ms_batch8": apply32_ms,
+            "fft_column_variants": {"fp64": apply_variant, "fp32": apply32_variant},
         },
         "roofline": {
             "kernel": ("one decoupled sweep (Alg. 1): every layer's slab solved twice as multi-slab launches "

@@ -176,8 +176,11 @@ ls_status ls_plan_timings(const ls_plan* plan, double* ms, int count);
  * neighbours in that column; every block's elimination agreed with its
  * dense inverse), 0 when they use the dense inverses;
  * info[1] = blocks of the dense top-of-reduction operator of the first slab
- * (0: none).  count entries are written (beyond 2: zeros).  HOST array;
- * LS_EINVAL for a null plan or array or count < 1. */
+ * (0: none); info[2] = the FFT column-pass variant the FP64 operator uses
+ * (the autotuner's choice, or opt.fft_variant without autotuning; Section
+ * 4.2: the FFT dominates the cost of H); info[3] = the FP32 operator's
+ * (-1 on an FP64 plan).  count entries are written (beyond 4: zeros).
+ * HOST array; LS_EINVAL for a null plan or array or count < 1. */
 ls_status ls_plan_info(const ls_plan* plan, int* info, int count);
 
 /* Frees the plan (synchronises its stream first).  NULL is accepted. */

@@ -310,10 +310,11 @@ class Plan:
         return dict(zip(self.STAGES, list(ms)))
 
     def info(self):
-        """ls_plan_info: {"tridiagonal_level0": 0/1, "top_blocks": blocks}."""
-        v = (_i * 2)()
-        _check("ls_plan_info", lib().ls_plan_info(self.handle, v, 2))
-        return {"tridiagonal_level0": v[0], "top_blocks": v[1]}
+        """ls_plan_info: {"tridiagonal_level0": 0/1, "top_blocks": blocks,
+        "fft_variant64": v, "fft_variant32": v or -1}."""
+        v = (_i * 4)()
+        _check("ls_plan_info", lib().ls_plan_info(self.handle, v, 4))
+        return {"tridiagonal_level0": v[0], "top_blocks": v[1], "fft_variant64": v[2], "fft_variant32": v[3]}
 
     def slab_info(self, orient, slab):
         lims = (_i * 4)()

@@ -714,8 +714,8 @@ ls_status ls_plan_info(const ls_plan* p, int* info, int count) {
   int top_blocks = 0;  // blocks of the first slab's dense top operator (0: none)
   if (!p->slabs[0].empty() && p->slabs[0][0].top_level >= 1)
     top_blocks = p->slabs[0][0].levels[p->slabs[0][0].top_level].nl;
-  const int v[2] = {p->tri_ok ? 1 : 0, top_blocks};
-  for (int i = 0; i < count; ++i) info[i] = i < 2 ? v[i] : 0;
+  const int v[4] = {p->tri_ok ? 1 : 0, top_blocks, p->col_variant64, p->fp32 ? p->col_variant32 : -1};
+  for (int i = 0; i < count; ++i) info[i] = i < 4 ? v[i] : 0;
   return LS_OK;
 }
 

@@ -58,6 +58,8 @@ def test_autotuned_fft_variants_agree(n):
     ea, eb = rel(ya, ref), rel(yb, ref)
     banner(f"n={n} autotuned apply rel err {ea:.3e}, default variant {eb:.3e}, between {rel(ya, yb):.3e}")
     assert ea < 1e-13 and eb < 1e-13 and rel(ya, yb) < 1e-14
+    assert 0 <= pa.info()["fft_variant64"] < 8 and pa.info()["fft_variant32"] == -1
+    assert pb.info()["fft_variant64"] == 0
     pa.close()
     pb.close()
 
@@ -167,6 +169,8 @@ def test_every_fft_column_variant_matches_oracle(apply_refs, n, variant):
     m, v, ref, ref32 = apply_refs[n]
     B = v.shape[0]
     p, _ = make(n, m, slabs=n // 50, max_batch=B, precision=1, autotune=0, fft_variant=variant)
+    info = p.info()
+    assert info["fft_variant64"] == variant and info["fft_variant32"] == variant
     e64 = rel(host(p.apply(dev(v))), ref)
     e32 = rel(host(p.apply_c64(dev(v, torch.complex64))), ref32)
     banner(f"variant {variant} n={n}: FP64 rel err {e64:.3e}, FP32 {e32:.3e}")
