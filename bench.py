@@ -604,9 +604,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form variant")
     ap.add_argument("--weights", default=None, help="network weights (default: the shipped ones)")
     ap.add_argument("--mode", default="full",
-                    choices=["full", "slab", "sweep", "copy", "batched", "learned", "apply", "fno", "trend",
-                             "setup"],
-                    help="profiling sub-runs: slab = only slab solves of the bench workload's "
+                    choices=["full", "solve", "slab", "sweep", "copy", "batched", "learned", "apply", "fno",
+                             "trend", "setup"],
+                    help="profiling sub-runs: solve = only the timed plain solves (--steps after "
+                         "--warmup); slab = only slab solves of the bench workload's "
                          "interior layer; copy = 1 GiB device copies (counter calibration); "
                          "batched = only the multi-grid variant; learned = only the learned-form "
                          "variant; apply = only ls_apply of the bench workload at batch 8; "
@@ -678,9 +679,9 @@ def main():
     popts = {}
     if args.fft_variant is not None:
         popts = dict(autotune=0, fft_variant=args.fft_variant, precision=1)
-    if args.mode in ("full", "sweep"):
+    if args.mode in ("full", "sweep", "solve"):
         popts["sweep"] = 1    # decoupled sweeps for the timed solve
-    if args.mode == "full":
+    if args.mode in ("full", "solve"):
         popts.update(inner_opts)
     plan = Plan(n, 1.0 / n, omega, m_d, slabs=L, ext=ext, max_batch=8, **popts)
     torch.cuda.synchronize()
@@ -752,6 +753,11 @@ def main():
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} solves in {elapsed:.3f} s; last {infos[-1]}")
     value = args.steps / elapsed
+    if args.mode == "solve":
+        print(json.dumps({"mode": "solve", "inner": args.inner, "steps": args.steps, "solves_per_s": value,
+                          "ms_per_solve": 1e3 * elapsed / args.steps, "last": infos[-1]}))
+        plan.close()
+        return
 
     # dominant unit: one decoupled sweep (95 % of a solve), HIP events on the plan stream
     sweep_ms, sweep_alg, sweep_qs = time_sweeps(plan, n, 2 * args.slab_reps)
