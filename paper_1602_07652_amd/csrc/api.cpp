@@ -268,6 +268,24 @@ ls_status precond_batch(ls_plan* p, const T* r, T* z, int B, std::vector<GmresRe
   T*& g = PK<T>::rhs(p);
   if (!g) LS_TRY(plan_alloc(p, (void**)&g, sizeof(T) * N * p->opt.max_batch));
   LS_TRY(stencil_apply_A(p, r, g, B));
+  if (p->opt.inner_fixed_iters == 1) {
+    // one inner iteration (Section 6: the inner solve relaxed under the
+    // flexible outer loop) in closed form, with no host transfer: zt = M g,
+    // w = C zt, z = ((w^H g) / (w^H w)) zt -- the value one step of the
+    // right-preconditioned GMRES below gives, up to rounding (M is linear)
+    KrylovSpaceT<T>& KV = PK<T>::iV(p);
+    KrylovSpaceT<T>& KZ = PK<T>::iZ(p);
+    const size_t stride = (size_t)p->opt.max_batch * N;
+    LS_TRY(ensure_krylov(p, KV, 1, stride));
+    LS_TRY(ensure_krylov(p, KZ, 1, stride));
+    LS_TRY(inner_prec<T>(p, g, KZ.base, B));
+    LS_TRY(stencil_apply_C(p, KZ.base, KV.base, B));
+    LS_TRY(vec_minres_scale(p, KV.base, g, KZ.base, z, N, B));
+    GmresResult one;
+    one.iters = 1;
+    res.assign(B, one);
+    return LS_OK;
+  }
   auto op = [&](const T* in, T* out, int nb) { return stencil_apply_C(p, in, out, nb); };
   auto pr = [&](const T* in, T* out, int nb) { return inner_prec<T>(p, in, out, nb); };
   return fgmres<T>(p, op, pr, g, z, B, p->opt.inner_tol, p->opt.max_inner,

@@ -332,6 +332,69 @@ ls_status cgs2_t(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, i
   return LS_OK;
 }
 
+// partial[b][blk][0] = this block's sum of conj(w[b]) g[b], partial[b][blk][1]
+// = of |w[b]|^2 (FP64 accumulation, the layout k_finish_dot reads).
+template <typename T>
+__global__ __launch_bounds__(kDotThreads) void k_dot_wg(const T* __restrict__ w, const T* __restrict__ g,
+                                                        size_t N, cplx* __restrict__ partial) {
+  w += (size_t)blockIdx.y * N;
+  g += (size_t)blockIdx.y * N;
+  partial += (size_t)blockIdx.y * gridDim.x * kGroup;
+  cplx acc[2] = {cmk(0, 0), cmk(0, 0)};
+  for (size_t t = (size_t)blockIdx.x * kDotThreads + threadIdx.x; t < N;
+       t += (size_t)gridDim.x * kDotThreads) {
+    const cplx wv = up(w[t]);
+    acc[0] = cfmaconj(wv, up(g[t]), acc[0]);
+    acc[1] = cfmaconj(wv, wv, acc[1]);
+  }
+  __shared__ cplx red[kDotThreads];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    red[threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kGroup + i] = red[0];
+    __syncthreads();
+  }
+}
+
+// z[b] = alpha_b zt[b], alpha_b = h[b][0] / h[b][1] (0 when h[b][1] = 0; a
+// non-finite h[b][1] gives a non-finite z[b]).
+template <typename T>
+__global__ void k_scale_alpha(T* __restrict__ z, const T* __restrict__ zt, const cplx* __restrict__ h, int ldh,
+                              size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const cplx* hb = h + (size_t)blockIdx.y * ldh;
+  const double d = hb[1].x;
+  const double ax = d == 0.0 ? 0.0 : hb[0].x / d, ay = d == 0.0 ? 0.0 : hb[0].y / d;
+  const size_t off = (size_t)blockIdx.y * N + t;
+  z[off] = tmul(tmk<T>(ax, ay), zt[off]);
+}
+
+// One step of right-preconditioned GMRES from x0 = 0 in closed form: with zt
+// = M g and w = C zt, the one-dimensional minimal-residual solution of
+// C x = g over span{zt} is x = alpha zt, alpha = (w^H g) / (w^H w).  Both
+// inner products and alpha stay on the device.
+template <typename T>
+ls_status minres_scale_t(ls_plan* p, const T* w, const T* g, const T* zt, T* z, size_t N, int B) {
+  LS_TRY(ensure_red(p));
+  if (B > p->opt.max_batch) {
+    ls_set_error("one-step inner solve: batch above max_batch");
+    return LS_EUNSUPPORTED;
+  }
+  const int nblk = (int)std::min<size_t>(kDotBlocks, (N + kDotThreads - 1) / kDotThreads);
+  cplx* h = p->dotbuf;  // [B][2]
+  k_dot_wg<T><<<dim3(nblk, B), kDotThreads, 0, p->stream>>>(w, g, N, p->red);
+  k_finish_dot<<<dim3(2, B), 256, 0, p->stream>>>(p->red, nblk, h, 2);
+  k_scale_alpha<T><<<dim3(blocks_for(N, 256), B), 256, 0, p->stream>>>(z, zt, h, 2, N);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
 }  // namespace
 
 #define LS_BLAS_INSTANCES(T)                                                                     \
@@ -357,6 +420,10 @@ ls_status cgs2_t(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, i
   ls_status vec_cgs2(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, int B,         \
                      cplx* h1_host, cplx* h2_host, double* nrm2_host) {                            \
     return cgs2_t<T>(p, V, k, stride, w, N, B, h1_host, h2_host, nrm2_host);                       \
+  }                                                                                                \
+  ls_status vec_minres_scale(ls_plan* p, const T* w, const T* g, const T* zt, T* z, size_t N,      \
+                             int B) {                                                              \
+    return minres_scale_t<T>(p, w, g, zt, z, N, B);                                                \
   }                                                                                                \
   ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host) {                        \
     return vec_norms(p, w, N, 1, out_host);                                                        \

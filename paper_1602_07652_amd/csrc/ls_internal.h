@@ -338,6 +338,10 @@ ls_status slab_solve_noalloc(ls_plan* p, Slab& s, const cplx* b, cplx* x);
   /* classical Gram-Schmidt with one re-orthogonalisation, 1 <= k <= 8 */                         \
   ls_status vec_cgs2(ls_plan* p, const T* V, int k, size_t stride, T* w, size_t N, int B,         \
                      cplx* h1_host, cplx* h2_host, double* nrm2_host);                             \
+  /* z = alpha zt with alpha = (w^H g) / (w^H w) per right-hand side, on the */                    \
+  /* device (no host transfer): one step of right-preconditioned GMRES */                        \
+  ls_status vec_minres_scale(ls_plan* p, const T* w, const T* g, const T* zt, T* z, size_t N,      \
+                             int B);                                                               \
   ls_status vec_norm(ls_plan* p, const T* w, size_t N, double* out_host);                         \
   ls_status vec_scale_b(ls_plan* p, T* y, const T* x, const double* s_host, size_t N, int B);     \
   ls_status vec_scale_copy(ls_plan* p, T* y, const T* x, double s, size_t N);                     \
