@@ -202,16 +202,27 @@ def test_decoupled_sweep_fp32_plan(n, f, L, ext, shift, seed, level0):
     p.close()
 
 
-def test_precond_fixed_iterations():
+@pytest.mark.parametrize("fixed,B", [(2, 1), (1, 1), (1, 3)])
+def test_precond_fixed_iterations(fixed, B):
+    """Alg. 3 with a fixed number of inner iterations against the oracle's:
+    two (the flexible GMRES loop) and one (its closed form on the device,
+    z = (w^H g / w^H w) M g with w = C M g), one and three right-hand sides,
+    the third a zero vector (z = 0)."""
     n, f, L = 64, 6.0, 4
     m = li.gaussian_disk_medium(n)
-    p, omega = make_plan(n, f, m, slabs=L, ext=10, inner_fixed_iters=2)
-    P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=L, ext=10, inner_fixed_iters=2)
-    r = li.random_complex((n, n), 11)
+    p, omega = make_plan(n, f, m, slabs=L, ext=10, inner_fixed_iters=fixed, max_batch=B)
+    P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=L, ext=10, inner_fixed_iters=fixed)
+    r = li.random_complex((B, n, n), 11)
+    if B > 2:
+        r[2] = 0.0
     z = host(p.precond_apply(dev(r)))
-    e = rel(z, P.precond_apply(r))
-    banner(f"precond fixed=2 rel err {e:.3e}")
-    assert e < 1e-12
+    for b in range(B):
+        if not np.any(r[b]):
+            assert not np.any(z[b])
+            continue
+        e = rel(z[b], P.precond_apply(r[b]))
+        banner(f"precond fixed={fixed} rhs {b} rel err {e:.3e}")
+        assert e < 1e-12
     p.close()
 
 
