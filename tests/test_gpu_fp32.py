@@ -86,7 +86,8 @@ def test_fp32_refined_solve_reaches_fp64_accuracy():
     p.close()
 
 
-def test_fp32_refined_solution_error_vs_oracle_solution():
+@pytest.mark.parametrize("inner", [0, 1])
+def test_fp32_refined_solution_error_vs_oracle_solution(inner):
     """The precision workload's target on a grid the oracle solves in
     seconds: a Gaussian-random-field medium (correlation length 0.05, std
     0.15, smooth compact support) at 256^2, omega = 2 pi 25.6 (10 points per
@@ -94,12 +95,13 @@ def test_fp32_refined_solution_error_vs_oracle_solution():
     against the oracle's own FP64 flexible-GMRES solution at tol 1e-12:
     relative L2 error <= 1e-8.  Both solve H u = f; the error bound is
     kappa(H) times the residuals (1e-10 and 1e-12), so the margin to 1e-8
-    covers kappa up to ~100."""
+    covers kappa up to ~100.  inner 1: one inner iteration per outer
+    iteration (the relaxed inner solve bench.py times), 0: Alg. 3 as printed."""
     n = 256
     omega = 2 * np.pi * 25.6
     m = li.gaussian_random_field_medium(n, seed=0)
     uI = li.plane_wave(n, omega, 0.0)
-    p, _ = plan32(n, 25.6, m, slabs=4, ext=10)
+    p, _ = plan32(n, 25.6, m, slabs=4, ext=10, inner_fixed_iters=inner)
     f = p.rhs_from_incident(dev(uI))
     u, info = p.solve(f, tol=1e-10)
     P = solver.Problem(n, 1.0 / n, omega, m, slabs_L=4, ext=10)
@@ -113,17 +115,19 @@ def test_fp32_refined_solution_error_vs_oracle_solution():
     p.close()
 
 
-@pytest.mark.parametrize("sweep", [0, 1])
+@pytest.mark.parametrize("sweep,inner", [(0, 0), (1, 0), (1, 1)])
 @pytest.mark.parametrize("name", ["c3_2048_grf"])
-def test_fp32_refined_solve_full_size_residual(name, sweep):
+def test_fp32_refined_solve_full_size_residual(name, sweep, inner):
     """2048^2 Gaussian-random-field workload at tol 1e-10, with the
     sequential and with the decoupled sweeps (FP32 trace maps, 30 interior
-    layers in multi-slab groups of 16 and 14 as bench.py runs it): the
+    layers in multi-slab groups of 16 and 14 as bench.py runs it), with
+    Alg. 3 as printed and (inner 1) with one inner iteration per outer
+    iteration, the form bench.py times: the
     oracle's FP64 residual of the GPU solution is at most the tolerance (the
     library's own FP64 residual and the oracle's agree to rounding)."""
     cfg = li.config_inputs(name)
     n, omega, m = cfg["n"], cfg["omega"], cfg["m"]
-    p, _ = plan32(n, omega / (2 * np.pi), m, slabs=cfg["slabs"], ext=10, sweep=sweep)
+    p, _ = plan32(n, omega / (2 * np.pi), m, slabs=cfg["slabs"], ext=10, sweep=sweep, inner_fixed_iters=inner)
     uI = cfg["uI"]
     f = p.rhs_from_incident(dev(uI))
     u, info = p.solve(f, tol=1e-10)

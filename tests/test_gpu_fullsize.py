@@ -44,17 +44,20 @@ def test_plain_solve_at_bench_size(sweep, inner):
     p.close()
 
 
-def test_batched_64_waves_at_1024():
+@pytest.mark.parametrize("inner", [0, 1])
+def test_batched_64_waves_at_1024(inner):
     """64 plane waves theta_k = 2 pi k / 64 on the 1024^2 8-bump medium (seed
     3, omega = 2 pi n / 10), FP32 operator and slab solves with FP64
-    refinement, matrix-core level steps and top operator: every wave reaches
-    1e-8 by the library's FP64 residual, and the oracle agrees on samples."""
+    refinement, matrix-core level steps and top operator, with Alg. 3 as
+    printed and (inner 1) one inner iteration per outer iteration, the form
+    bench.py times: every wave reaches 1e-8 by the library's FP64 residual,
+    and the oracle agrees on samples."""
     from paper_1602_07652_amd import Plan, LS_FP32_REFINE
     n, B = 1024, 64
     omega = 2 * np.pi * n / 10
     m, _ = li.gaussian_bumps_medium(n, seed=3)
     p = Plan(n, 1.0 / n, omega, dev(m, torch.float64), slabs=n // 64, ext=10, max_batch=B,
-             precision=LS_FP32_REFINE)
+             precision=LS_FP32_REFINE, inner_fixed_iters=inner)
     uI = np.stack([li.plane_wave(n, omega, 2 * np.pi * k / B) for k in range(B)])
     f = p.rhs_from_incident(dev(uI))
     u, infos = p.solve(f, tol=1e-8)
