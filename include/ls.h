@@ -76,7 +76,10 @@ typedef struct {
   double shift_c;        /* complex shift in the cut-off region, omega^2 sigma = shift_c*omega (Section 3.3) */
   int precision;         /* LS_FP64 or LS_FP32_REFINE */
   int precond;           /* LS_PREC_* */
-  int inner_fixed_iters; /* > 0: inner GMRES runs exactly this many iterations */
+  int inner_fixed_iters; /* > 0: inner GMRES runs exactly this many iterations;
+                          * 1 (Section 6: the inner solve relaxed under the
+                          * flexible outer loop) is computed in closed form on
+                          * the device, z = (w^H g / w^H w) M g, w = C M g */
   int max_batch;         /* largest `batch` passed to ls_apply / ls_rhs_from_incident */
   double lowp_tol;       /* LS_FP32_REFINE: relative tolerance of each FP32 correction solve */
   int max_refine;        /* refinement sweeps limit (LS_FP32_REFINE) / FP64 restarts limit (LS_FP64) */
